@@ -1,0 +1,193 @@
+"""Pins for the oracle's BRAS operator against what the paper proves or prints."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import fe, mesh, assembly, spectral, pcg
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def problem(family, dim, deg, N, jitter=0.0, seed=3, rho=None):
+    ref = fe.reference_element(family, dim, deg)
+    coords, cells = mesh.structured_mesh(dim, N, jitter=jitter, seed=seed)
+    return assembly.Problem(ref, coords, cells, rho=rho)
+
+
+SMALL = [("P", 2, 1, 4, 0.0), ("P", 2, 3, 3, 0.2), ("P", 3, 2, 2, 0.2), ("P", 3, 4, 1, 0.0),
+         ("N1curl", 3, 2, 2, 0.2), ("RT", 3, 2, 2, 0.2), ("RT", 2, 2, 3, 0.2), ("N1curl", 2, 3, 2, 0.2)]
+
+
+@pytest.mark.parametrize("family,dim,deg,N,jit", SMALL)
+def test_bras_symmetric_positive_definite(family, dim, deg, N, jit):
+    pr = problem(family, dim, deg, N, jit)
+    B = pr.B.toarray()
+    assert np.max(np.abs(B - B.T)) <= 1e-13 * np.max(np.abs(B))
+    np.linalg.cholesky(B)                         # SPD (eq. mhatinvbras_def, full-rank P)
+    # nonzeros only between DOFs that share an element: the element-adjacency
+    # graph of M (eq. mass_and_bras_element_sums)
+    inc = sp.csr_matrix((np.ones(pr.pi.size), (pr.pi.ravel(), np.repeat(np.arange(len(pr.pi)), pr.pi.shape[1]))),
+                        shape=(pr.n, len(pr.pi)))
+    adj = (inc @ inc.T).tocsr()
+    adj_set = set(zip(*adj.nonzero()))
+    assert set(zip(*pr.B.nonzero())) <= adj_set
+    assert set(zip(*pr.M.nonzero())) <= adj_set
+
+
+@pytest.mark.parametrize("family,dim,deg,N,jit", SMALL)
+def test_lambda_min_at_least_one(family, dim, deg, N, jit):
+    # Cor. bras_lambda_min
+    pr = problem(family, dim, deg, N, jit)
+    ev = spectral.preconditioned_eigs(pr.M, pr.B)
+    assert ev[0] >= 1.0 - 1e-10
+
+
+@pytest.mark.parametrize("family,dim,deg,N", [("RT", 3, 1, 2), ("RT", 3, 2, 2), ("RT", 2, 2, 3)])
+def test_lambda_min_equals_one_when_nbr_below_2n(family, dim, deg, N):
+    pr = problem(family, dim, deg, N, 0.2)
+    assert pr.n_br < 2 * pr.n                     # sum_i (d_i - 2) < 0
+    assert np.sum(pr.d - 2) == pr.n_br - 2 * pr.n
+    ev = spectral.preconditioned_eigs(pr.M, pr.B)
+    assert abs(ev[0] - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("dim,deg,N", [(2, 1, 8), (3, 1, 3), (2, 2, 4), (2, 3, 3), (3, 3, 2), (3, 4, 1)])
+def test_constant_is_fixed_on_uniform_meshes(dim, deg, N):
+    # M_br P 1 in range(P) on equal-volume meshes => Mbras^-1 M 1 = 1
+    pr = problem("P", dim, deg, N)
+    one = np.ones(pr.n)
+    y = pr.B @ (pr.M @ one)
+    assert np.max(np.abs(y - 1.0)) < 1e-13
+
+
+def test_constant_not_fixed_on_jittered_mesh():
+    pr = problem("P", 2, 1, 6, 0.2)
+    y = pr.B @ (pr.M @ np.ones(pr.n))
+    assert np.max(np.abs(y - 1.0)) > 1e-3
+
+
+@pytest.mark.parametrize("family,dim,deg,N,jit", SMALL[:6])
+def test_lambda_max_projector_identity(family, dim, deg, N, jit):
+    # Thm. bras_lambda_max_projector
+    pr = problem(family, dim, deg, N, jit)
+    lmax = spectral.preconditioned_eigs(pr.M, pr.B)[-1]
+    lq = spectral.projector_lambda_max(pr.pi, pr.mats, pr.n)
+    assert abs(lmax - lq) < 1e-10 * lmax
+
+
+@pytest.mark.parametrize("family,dim,deg,N,jit", [("P", 2, 2, 2, 0.2), ("N1curl", 3, 1, 1, 0.0), ("RT", 2, 2, 2, 0.2), ("P", 3, 1, 2, 0.2)])
+def test_exact_inverse_correction(family, dim, deg, N, jit):
+    # Lemma bras_exact_inverse_correction: Mbras^-1 = M^-1 - Z S^-1 Z^T, correction SPSD
+    pr = problem(family, dim, deg, N, jit)
+    rhs, corr = spectral.exact_inverse_correction(pr.pi, pr.mats, pr.n)
+    B = pr.B.toarray()
+    assert np.max(np.abs(B - rhs)) < 1e-10 * np.max(np.abs(B))
+    assert np.linalg.eigvalsh(0.5 * (corr + corr.T))[0] > -1e-10 * np.max(np.abs(corr))
+
+
+@pytest.mark.parametrize("family,deg", [("P", 2), ("N1curl", 2), ("RT", 2)])
+def test_metric_contrast_bound(family, deg):
+    # Cor. bras_piola_metric_contrast: lambda_max(B^G M^G) <= beta/alpha lambda_max(B^I M^I)
+    ref = fe.reference_element(family, 3, deg)
+    coords, cells = mesh.structured_mesh(3, 2, jitter=0.2, seed=21)
+    prG = assembly.Problem(ref, coords, cells)
+    G = assembly.metric(family, coords, cells)
+    ratio = spectral.metric_contrast(family, G)
+    mI = ref.mass if family == "P" else sum(ref.mass[a, a] for a in range(3))
+    matsI = np.broadcast_to(mI, (len(cells),) + mI.shape).copy()
+    MI = assembly.mass_matrix(prG.pi, matsI, prG.n)
+    BI = assembly.bras_matrix(prG.pi, matsI, prG.n, prG.d)
+    lG = spectral.preconditioned_eigs(prG.M, prG.B)[-1]
+    lI = spectral.preconditioned_eigs(MI, BI)[-1]
+    assert lG <= ratio * lI * (1 + 1e-10)
+    assert ratio > 1.0
+
+
+@pytest.mark.parametrize("family,dim,deg", [("P", 3, 3), ("RT", 3, 2), ("N1curl", 3, 2), ("P", 2, 4)])
+def test_single_element_is_exact(family, dim, deg):
+    ref = fe.reference_element(family, dim, deg)
+    coords, cells = mesh.structured_mesh(dim, 1, jitter=0.0)
+    coords = coords[cells[0]]
+    cells = np.arange(dim + 1, dtype=np.int32)[None, :]
+    pr = assembly.Problem(ref, coords, cells)
+    assert np.all(pr.d == 1)
+    B = pr.B.toarray()
+    M = pr.M.toarray()
+    assert np.max(np.abs(B @ M - np.eye(pr.n))) < 1e-11
+
+
+def test_broken_map_gives_one_iteration():
+    # P = I (every d_i = 1): Mbras^-1 = M^-1 and PCG stops after one product
+    ref = fe.reference_element("P", 2, 2)
+    coords, cells = mesh.structured_mesh(2, 3, jitter=0.2, seed=1)
+    mats = assembly.element_matrices(ref, coords, cells)
+    pi = np.arange(len(cells) * ref.n_loc).reshape(len(cells), ref.n_loc)
+    n = pi.size
+    M = assembly.mass_matrix(pi, mats, n)
+    B = assembly.bras_matrix(pi, mats, n)
+    b = workloads.vector(n, 5)
+    x, its, ok, _ = pcg.pcg(M, b, B.dot, tol=1e-12)
+    assert ok and its == 1
+
+
+@pytest.mark.parametrize("family,dim,deg,N,jit,R", [("P", 3, 3, 2, 0.2, 1), ("RT", 3, 2, 2, 0.2, 3), ("N1curl", 3, 2, 2, 0.2, 1)])
+def test_matrix_free_routes_agree(family, dim, deg, N, jit, R):
+    pr = problem(family, dim, deg, N, jit)
+    x = workloads.rhs(pr.n, R, 9)
+    inv = assembly.element_inverses(pr.mats)
+    y1 = assembly.bras_apply_matrix_free(pr.pi, inv, pr.d, x)
+    y2 = pr.B @ x
+    assert np.max(np.abs(y1 - y2)) <= 1e-13 * np.max(np.abs(y2))
+    if R == 1:
+        m1 = assembly.mass_apply_matrix_free(pr.pi, pr.mats, x)
+        m2 = pr.M @ x
+        assert np.max(np.abs(m1 - m2)) <= 1e-13 * np.max(np.abs(m2))
+    # assembly identity M = P^T Mbr P as a sparse triple product
+    P = spectral.injection(pr.pi, pr.n)
+    Mt = (P.T @ spectral.broken_mass(pr.mats) @ P).toarray()
+    assert np.max(np.abs(Mt - pr.M.toarray())) <= 1e-14 * np.max(np.abs(Mt))
+
+
+def test_diagonal_scaling_invariance():
+    # A diagonal change of basis S leaves kappa-hat of both preconditioners unchanged
+    pr = problem("RT", 3, 2, 1, 0.2)
+    s = np.linspace(0.5, 2.0, pr.n)
+    S = sp.diags(s)
+    mats_s = pr.mats * s[pr.pi][:, :, None] * s[pr.pi][:, None, :]
+    Ms = assembly.mass_matrix(pr.pi, mats_s, pr.n)
+    Bs = assembly.bras_matrix(pr.pi, mats_s, pr.n, pr.d)
+    assert np.max(np.abs((S @ pr.M @ S - Ms).toarray())) < 1e-13 * abs(Ms).max()
+    k1 = spectral.kappa_hat(pr.M, pr.B)[0]
+    k2 = spectral.kappa_hat(Ms, Bs)[0]
+    assert abs(k1 - k2) < 1e-9 * k1
+
+
+def _sig2(x):
+    return float("%.2g" % x)
+
+
+@pytest.mark.parametrize("case", json.load(open(os.path.join(GOLDEN, "paper_kappa.json")))["cases"],
+                         ids=lambda c: c["cite"])
+def test_kappa_matches_paper_tables(case):
+    pr = problem(case["family"], case["dim"], case["degree"], case["N"])
+    assert 3500 <= pr.n <= 7500                  # "approximately 5e3 DOFs"
+    kd = spectral.kappa_hat(pr.M, sp.diags(1.0 / pr.diag))[0]
+    kb = spectral.kappa_hat(pr.M, pr.B)[0]
+    assert _sig2(kd) == case["kappa_diag"], (kd, case)
+    assert _sig2(kb) == case["kappa_bras"], (kb, case)
+
+
+def test_two_dimensional_curl_and_div_are_rotations():
+    # 2D N1curl_k and RT_k differ by a rotation: identical spectra (Tables hcurl/hdiv, 2D rows)
+    for k in (1, 2):
+        a = problem("N1curl", 2, k, 3, 0.2)
+        b = problem("RT", 2, k, 3, 0.2)
+        ka = spectral.kappa_hat(a.M, a.B)[0]
+        kb = spectral.kappa_hat(b.M, b.B)[0]
+        kda = spectral.kappa_hat(a.M, sp.diags(1.0 / a.diag))[0]
+        kdb = spectral.kappa_hat(b.M, sp.diags(1.0 / b.diag))[0]
+        assert abs(ka - kb) < 1e-9 * ka and abs(kda - kdb) < 1e-9 * kda
