@@ -1,0 +1,180 @@
+"""Benchmark: BRAS-preconditioned CG time-to-solution vs Jacobi-PCG on one GPU.
+
+One step = one complete BRAS-PCG solve (mass apply, BRAS apply and the CG
+vector updates, every iteration, until the relative residual reaches the
+workload's tolerance) on inputs already resident in device memory.  The
+Jacobi-PCG solve of the same system, the BRAS apply bandwidth against the
+HBM roofline and the CPU oracle (same workload, bounded sample) are reported
+beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+METRIC = "BRAS-PCG time to 1e-8 rel. residual vs Jacobi-PCG; BRAS apply HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+DEFAULT = "h1p3_3d_24_jit"
+
+
+def algorithmic_bytes(w, n, E, n_loc, R, prec):
+    """Bytes one BRAS apply must move: x in, y out (float64), the map
+    (int32 per broken DOF), element data, and D^-1 when it is not folded."""
+    nbr = E * n_loc
+    vec = 8.0 * n * R
+    if w.family == "P":
+        elem = 8.0 * E          # one coefficient per element (shared reference inverse)
+        dinv = 8.0 * n
+    else:
+        esz = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+        elem = esz * E * n_loc * (n_loc + 1) / 2.0
+        dinv = 0.0              # folded into the stored inverses
+    return 2 * vec + 4.0 * nbr + elem + dinv
+
+
+def time_solves(prob, b, pc, tol, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = rel = st = None
+    for _ in range(steps):
+        x, st, its, rel = prob.solve(b, pc, rtol=tol)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3, st, its, rel, x
+
+
+def time_apply(fn, x, y, reps):
+    import torch
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        fn(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn(x, y)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e3   # microseconds
+
+
+def cpu_baseline(w, b_host, budget_s=25.0):
+    """The oracle's BRAS-PCG on the same workload (assembly excluded, as the
+    paper excludes preconditioner construction)."""
+    from oracle import fe, mesh, assembly, pcg
+    ref = fe.reference_element(w.family, w.dim, w.degree)
+    coords, cells = mesh.structured_mesh(w.dim, w.N, jitter=w.jitter, seed=w.mesh_seed)
+    rho = workloads.density(len(cells), w.seed(2)) if w.density else None
+    pr = assembly.Problem(ref, coords, cells, rho=rho)
+    b = b_host if b_host.ndim == 1 else b_host[:, 0]
+    times, its = [], None
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        _, its, ok, _ = pcg.pcg(pr.M, b, pr.B.dot, tol=w.tol)
+        times.append(time.perf_counter() - t0)
+        if len(times) >= 3 or time.perf_counter() - t_start + times[-1] > budget_s:
+            break
+    cols = 1 if b_host.ndim == 1 else b_host.shape[1]
+    return {
+        "value": float(np.mean(times) * 1e3 * cols),
+        "unit": "ms per solve",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "full workload, %d BRAS-PCG solve(s) of column 0 (scaled x%d columns), scipy CSR, "
+                  "1 thread; %d iterations" % (len(times), cols, its),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(workloads.BY_NAME))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-reps", type=int, default=50)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on exactly one GPU: the method has no multi-GPU path in this library "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    from paper_2607_12138_amd.problem import MassProblem
+
+    w = workloads.BY_NAME[a.workload]
+    rho = workloads.density(w.n_cells, w.seed(2)) if w.density else None
+    t0 = time.perf_counter()
+    prob = MassProblem(w.family, w.dim, w.degree, w.N, jitter=w.jitter, seed=w.mesh_seed, rho=rho, prec=w.prec,
+                       max_rhs=w.nrhs)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print("setup done: n=%d E=%d n_loc=%d (%.1f s)" % (prob.n, prob.E, prob.n_loc, setup_s), file=sys.stderr,
+          flush=True)
+    b_host = workloads.rhs(prob.n, w.nrhs, w.seed(1))
+    b = torch.from_numpy(b_host).cuda()
+    for _ in range(a.warmup):
+        prob.solve(b, "bras", rtol=w.tol)
+        prob.solve(b, "jacobi", rtol=w.tol)
+    print("warmup done", file=sys.stderr, flush=True)
+    bras_ms, st_b, its_b, rel_b, xb = time_solves(prob, b, "bras", w.tol, a.steps)
+    jac_ms, st_j, its_j, rel_j, xj = time_solves(prob, b, "jacobi", w.tol, a.steps)
+    print("solves done: bras %.3f ms (%s its), jacobi %.3f ms (%s its)" % (bras_ms, its_b, jac_ms, its_j),
+          file=sys.stderr, flush=True)
+    x = prob.vec(w.nrhs)
+    x.copy_(b)
+    y = prob.vec(w.nrhs)
+    bras_us = time_apply(lambda u, v: L.bras_apply(prob.h, u, v), x, y, a.apply_reps)
+    mass_us = time_apply(lambda u, v: L.mass_apply(prob.h, u, v), x, y, a.apply_reps)
+    nbytes = algorithmic_bytes(w, prob.n, prob.E, prob.n_loc, w.nrhs, w.prec)
+    achieved = nbytes / (bras_us * 1e-6) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(bras_ms, 4),
+        "unit": "ms (BRAS-PCG time to solution)",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(bras_ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32 apply / f64 CG", "bf16": "bf16 apply / f64 CG"}[w.prec],
+        "data": "synthetic: seeded Kuhn mesh and U[-1,1] right-hand side",
+        "config": {
+            "workload": w.name, "family": {"P": "H1 Lagrange", "N1curl": "N1curl", "RT": "RT"}[w.family],
+            "degree": w.degree, "dim": w.dim, "mesh": "%d^%d Kuhn simplices, jitter %.1fh" % (w.N, w.dim, w.jitter),
+            "n": prob.n, "E": prob.E, "n_loc": prob.n_loc, "nrhs": w.nrhs, "rtol": w.tol, "apply_precision": w.prec,
+        },
+        "jacobi_ms": round(jac_ms, 4),
+        "speedup_vs_jacobi": round(jac_ms / bras_ms, 3),
+        "iterations": {"bras": [int(v) for v in its_b], "jacobi": [int(v) for v in its_j]},
+        "true_relres": {"bras": float(np.max(rel_b)), "jacobi": float(np.max(rel_j))},
+        "bras_apply_us": round(bras_us, 3),
+        "mass_apply_us": round(mass_us, 3),
+        "bras_apply_gbs": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "bras_apply (element pass + transpose-map reduce)",
+                     "bytes_per_launch": int(nbytes)},
+        "setup_s": round(setup_s, 3),
+    }
+    if not a.no_cpu_baseline:
+        print("cpu baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, b_host)
+    prob.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * bras.h - C ABI of the MI355X (gfx950) BRAS mass-inverse library.
+ *
+ * The library solves finite-element mass systems M u = f with preconditioned
+ * conjugate gradients, where M = P^T M_br P is assembled from element mass
+ * matrices M_K and the broken-to-conforming map pi (eq. M_PMbrP), and the
+ * preconditioner is either diag(M)^-1 (Section 2.1) or the broken-space
+ * additive Schwarz inverse
+ *
+ *     M_bras^-1 = D^-1 P^T M_br^-1 P D^-1,   D = P^T P = diag(d_i)
+ *
+ * (eq. mhatinvbras_def; element-sum form eq. mass_and_bras_element_sums).
+ *
+ * Conventions shared by every call
+ *   - Functions return BRAS_OK (0) or a negative status; they never abort and
+ *     no C++ exception crosses this boundary.  bras_last_error() returns a
+ *     thread-local message for the last failure on the calling thread.
+ *   - "_d" arguments are device pointers (memory of the current HIP device),
+ *     "_h" arguments are host pointers.  Buffers passed in are owned by the
+ *     caller; the library never frees them.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Conforming vectors are float64 [n] for one right-hand side, or
+ *     [n][nrhs] row-major (right-hand-side index fastest) for several.
+ *   - Element-local order, entity numbering and the reference simplex
+ *     conv{0, e_1, .., e_d} follow the canonical convention documented with
+ *     bras_dofmap().
+ */
+#ifndef BRAS_H
+#define BRAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define BRAS_OK          0
+#define BRAS_EINVAL     -1   /* bad argument: null pointer, size, map entry  */
+#define BRAS_ENOTSPD    -2   /* an element mass matrix failed Cholesky        */
+#define BRAS_EHIP       -3   /* a HIP runtime call failed                     */
+#define BRAS_ENOCONV    -4   /* PCG reached maxit before the tolerance        */
+#define BRAS_EBREAKDOWN -5   /* PCG breakdown: p.q <= 0, r.z <= 0, NaN / Inf  */
+#define BRAS_ENOMEM     -6   /* device allocation failed                      */
+
+/* ---- element families (Section 3: Lagrange, N1curl, RT) ----------------- */
+#define BRAS_H1    0         /* H1 Lagrange P_p, GLL-based nodes             */
+#define BRAS_HCURL 1         /* first-kind Nedelec N1curl_k, covariant Piola */
+#define BRAS_HDIV  2         /* Raviart-Thomas RT_k, contravariant Piola     */
+
+/* ---- element-data forms accepted by bras_setup -------------------------- */
+#define BRAS_ELEM_EXPLICIT   0  /* elem_d: E x n_loc x n_loc float64 M_K, row-major */
+#define BRAS_ELEM_SCALED_REF 1  /* ref_d: n_loc^2 Mhat; elem_d: E scalars c_K,
+                                   M_K = c_K Mhat (affine H1, eq. h1_mass_pullback) */
+#define BRAS_ELEM_METRIC_REF 2  /* ref_d: nsym x n_loc^2 symmetric tables S_p;
+                                   elem_d: E x nsym metric entries G_p;
+                                   M_K = sum_p G_p S_p (eqs. hcurl/hdiv_mass_pullback) */
+
+/* ---- precision of the stored BRAS element inverses ---------------------- */
+#define BRAS_FP64 0
+#define BRAS_FP32 1
+#define BRAS_BF16 2          /* Gram-factor form on MFMA, FP32 accumulation  */
+
+/* ---- preconditioners for pcg_solve -------------------------------------- */
+#define BRAS_PC_NONE   0
+#define BRAS_PC_JACOBI 1     /* diag(M)^-1                                    */
+#define BRAS_PC_BRAS   2     /* D^-1 P^T M_br^-1 P D^-1                       */
+
+typedef struct bras_ctx* bras_handle;
+
+/* ======================================================================== *
+ * Host helpers: workload construction.  Every output is written to host
+ * memory and is bit-exact reproducible from the documented definitions.
+ * ======================================================================== */
+
+/* Sizes of the structured Kuhn mesh of the unit square (dim 2: N*N squares
+ * split into 2 triangles) or cube (dim 3: N^3 cubes split into the 6
+ * tetrahedra containing the main diagonal).  Returns EINVAL for dim not in
+ * {2,3} or N < 1. */
+int bras_mesh_size(int dim, int N, int64_t* nvert_h, int64_t* ncell_h);
+
+/* Structured mesh (the simplicial unit square / cube meshes of Section 3).
+ * Vertex (i,j[,k]) has id i + (N+1)(j + (N+1)k) and coordinates (i h, ...),
+ * h = 1.0/N.  Cells list ascending vertex ids: 2D square c = i + N j gives
+ * triangles [v(i,j), v(i+1,j), v(i+1,j+1)] and [v(i,j), v(i,j+1), v(i+1,j+1)];
+ * 3D cube c gives 6 tetrahedra, s-th = monotone lattice path through the
+ * cube along the s-th permutation of the axes in lexicographic order.
+ * Interior vertices move each coordinate by (jitter h)(2u - 1),
+ * u = (mix64(seed + (dim vid + axis + 1) * 0x9E3779B97F4A7C15) >> 11) 2^-53,
+ * mix64 = the SplitMix64 output function.
+ * coords_h: [nvert][dim] float64, cells_h: [ncell][dim+1] int32 (caller
+ * allocated, sizes from bras_mesh_size). */
+int bras_mesh_structured(int dim, int N, double jitter, uint64_t seed,
+                         double* coords_h, int32_t* cells_h);
+
+/* Element description: n_loc and the DOFs per vertex, edge, face and cell
+ * (dofs_per_entity_h[4]; 2D uses entries 0..2, entry 2 = cell).
+ * Supported: H1 degree 1..6 (2D/3D), HCURL and HDIV degree 1..4 (2D/3D). */
+int bras_element_info(int family, int dim, int degree, int* n_loc_h, int* dofs_per_entity_h);
+
+/* Reference mass tables on conv{0, e_1, .., e_d} (eq. piola_mass_pullbacks).
+ * H1: ref_h[n_loc*n_loc] = Mhat_ij = int phi_i phi_j.
+ * HCURL/HDIV: nsym = dim(dim+1)/2 symmetric tables, pair order
+ * (0,0),(0,1),(0,2),(1,1),(1,2),(2,2) in 3D and (0,0),(0,1),(1,1) in 2D:
+ * S_(a,a) = Mhat^{aa}, S_(a,b) = Mhat^{ab} + Mhat^{ba} for a < b, with
+ * Mhat^{ab}_ij = int phi_i^a phi_j^b, so M_K = sum_p G_p S_p.
+ * Degrees of freedom: point values at recursive GLL nodes (H1); integral
+ * moments against orthonormal polynomials of each sorted-vertex entity
+ * (HCURL / HDIV).  Computed by quadrature in extended precision. */
+int bras_reference_mass(int family, int dim, int degree, double* ref_h);
+
+/* Canonical local-to-global map.  Edges / faces are the sorted vertex pairs /
+ * triples of the cells numbered in lexicographic order; conforming DOFs come
+ * in blocks [vertex | edge | face | cell] (2D: [vertex | edge | cell]), entity
+ * e of a block owning offset + e*k + (0..k-1).  l2g_h[K][l] follows the
+ * element's local order: vertices, local edges (lex pairs of local vertices),
+ * local faces, interior.  cells_h must list ascending vertex ids.
+ * Outputs n (number of conforming DOFs) and l2g_h [E][n_loc] int32. */
+int bras_dofmap(int family, int dim, int degree, int64_t nvert, int64_t ncell,
+                const int32_t* cells_h, int64_t* n_h, int32_t* l2g_h);
+
+/* Per-element pullback coefficients on the device (eq. piola_mass_pullbacks):
+ * H1    elem_d[K]         = rho_K |det J_K|
+ * HCURL elem_d[K][nsym]   = rho_K |det J_K| J_K^-1 J_K^-T   (symmetric pairs)
+ * HDIV  elem_d[K][nsym]   = rho_K J_K^T J_K / |det J_K|
+ * J_K has columns v_i - v_0.  rho_d may be NULL (rho = 1).  Asynchronous. */
+int bras_geometry(int family, int dim, int64_t nvert, const double* coords_d,
+                  int64_t ncell, const int32_t* cells_d, const double* rho_d,
+                  double* elem_d, void* stream);
+
+/* ======================================================================== *
+ * Core: setup and the operators of the hot path.
+ * ======================================================================== */
+
+/* Build a handle for the conforming space with n DOFs, E elements of n_loc
+ * local DOFs, map l2g_d [E][n_loc] (device, int32), and element data in one
+ * of the BRAS_ELEM_* forms (nsym is used by METRIC_REF only).
+ * Validates the map: entries in [0, n), distinct within an element, and every
+ * DOF has d_i >= 1 (P has full column rank, Section 2.2) - else EINVAL.
+ * Computes d, the transpose map, diag(M), and every element's exact inverse
+ * M_K^-1 in float64 (Cholesky; ENOTSPD names the first failing element),
+ * folds D^-1 on both sides and stores it in apply_prec.  BRAS_BF16 requires
+ * METRIC_REF or EXPLICIT and stores the Gram factor G_K = L_K^-1 D_K^-1
+ * (M_K = L_K L_K^T) so that D_K^-1 M_K^-1 D_K^-1 = G_K^T G_K.
+ * max_rhs bounds nrhs in later calls and sizes the workspace.  Every input
+ * is copied; the caller may free its buffers when the call returns.
+ * Synchronous. */
+int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const int32_t* l2g_d,
+               int form, const double* ref_d, const double* elem_d, int nsym,
+               int apply_prec, int max_rhs, void* stream);
+
+/* Replace the element coefficients (same form and sizes as at setup) and
+ * recompute the element inverses and diag(M); maps are kept.  Synchronous. */
+int bras_update(bras_handle h, const double* elem_d, void* stream);
+
+/* Release every resource of the handle.  NULL is accepted. */
+int bras_destroy(bras_handle h);
+
+/* y = M_bras^-1 x = D^-1 P^T M_br^-1 P D^-1 x (eq. mhatinvbras_def).
+ * x_d, y_d: [n] or [n][nrhs] float64, distinct buffers, 1 <= nrhs <= max_rhs.
+ * Deterministic (no floating-point atomics); asynchronous on stream; no
+ * allocation. */
+int bras_apply(bras_handle h, const double* x_d, double* y_d, int nrhs, void* stream);
+
+/* y = M x = sum_K P_K^T M_K P_K x (eq. M_PMbrP), float64 throughout.
+ * Same argument rules as bras_apply. */
+int mass_apply(bras_handle h, const double* x_d, double* y_d, int nrhs, void* stream);
+
+/* y = diag(M)^-1 x (Section 2.1).  Same argument rules as bras_apply. */
+int jacobi_apply(bras_handle h, const double* x_d, double* y_d, int nrhs, void* stream);
+
+/* Preconditioned CG on M x = b (Section 3), independently per column.
+ * pc: BRAS_PC_NONE / JACOBI / BRAS.  x_d holds the initial guess on entry and
+ * the solution on exit.  Column c stops when ||r_k||_2 / ||r_0||_2 <= rtol
+ * (r_k the recursive residual, r_0 = b - M x_0) or after maxit products M p.
+ * When the stored inverses are FP32 / BF16, the iteration uses the flexible
+ * beta and, at exit, restarts from x while the true residual exceeds rtol.
+ * iters_h[nrhs]: products M p per column; relres_h[nrhs]: final true
+ * ||b - M x|| / ||r_0|| (host, may be NULL).  Blocking.  Returns ENOCONV if a
+ * column did not converge and EBREAKDOWN on breakdown; x_d, iters_h and
+ * relres_h are written in every case. */
+int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, int nrhs,
+              double rtol, int maxit, int* iters_h, double* relres_h, void* stream);
+
+/* Density gradient for M(rho) = sum_K rho_K c_K P_K^T Mhat P_K (H1,
+ * SCALED_REF): g_d[K] = -dcoef_d[K] * sum_c lam_K,c^T Mhat x_K,c, i.e.
+ * dL/drho_K = -lambda_K^T (dM_K/drho_K) x_K with dcoef_d[K] = c_K = |det J_K|
+ * (the adjoint identity of a linear solve).  x_d, lam_d: [n] or [n][nrhs];
+ * g_d: [E].  Asynchronous. */
+int bras_rho_grad(bras_handle h, const double* x_d, const double* lam_d,
+                  const double* dcoef_d, double* g_d, int nrhs, void* stream);
+
+/* ======================================================================== *
+ * Introspection and options.
+ * ======================================================================== */
+
+#define BRAS_INFO_N        0   /* conforming DOFs                              */
+#define BRAS_INFO_E        1   /* elements                                     */
+#define BRAS_INFO_NLOC     2
+#define BRAS_INFO_NBR      3   /* broken DOFs = E * n_loc                       */
+#define BRAS_INFO_PREC     4
+#define BRAS_INFO_FORM     5
+#define BRAS_INFO_MAXRHS   6
+#define BRAS_INFO_RESTARTS 7   /* refinement restarts in the last pcg_solve     */
+#define BRAS_INFO_VARIANT  8   /* apply-kernel variant chosen by the autotuner  */
+int bras_info(bras_handle h, int what, int64_t* value_h);
+
+/* Copy derived setup data to device buffers for inspection:
+ * BRAS_EXPORT_MULT   int32 [n]   multiplicities d_i
+ * BRAS_EXPORT_ROWPTR int32 [n+1] transpose-map row pointers
+ * BRAS_EXPORT_SLOT   int64 [n_br] broken slots K*n_loc + l per row, ascending
+ * BRAS_EXPORT_DIAG   float64 [n] diag(M) */
+#define BRAS_EXPORT_MULT   0
+#define BRAS_EXPORT_ROWPTR 1
+#define BRAS_EXPORT_SLOT   2
+#define BRAS_EXPORT_DIAG   3
+int bras_export(bras_handle h, int what, void* dst_d, void* stream);
+
+#define BRAS_OPT_GRAPH_ITERS 0  /* CG iterations per captured graph (>= 1)     */
+#define BRAS_OPT_MAX_RESTART 1  /* refinement restarts allowed (>= 0)         */
+#define BRAS_OPT_VARIANT     2  /* force an apply-kernel variant (-1 = auto)   */
+int bras_set_option(bras_handle h, int opt, double value);
+
+/* Time the apply-kernel variants for this handle at nrhs columns on stream
+ * and keep the fastest (per element family, order and precision).  The
+ * result can be read back with BRAS_INFO_VARIANT.  Synchronous. */
+int bras_autotune(bras_handle h, int nrhs, void* stream);
+
+const char* bras_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BRAS_H */

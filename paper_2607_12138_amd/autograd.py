@@ -1,0 +1,39 @@
+"""Differentiable mass solve x = M(rho)^-1 b for H1 elements with a
+piecewise-constant density (M_K = rho_K |det J_K| Mhat).
+
+backward: with g = dL/dx, the adjoint lambda = M^-1 g (M symmetric, the
+same BRAS-preconditioned CG), dL/db = lambda and
+dL/drho_K = -lambda_K^T (dM_K/drho_K) x_K computed by the library's
+per-element contraction.
+"""
+import torch
+
+from . import _lib as L
+
+
+class BrasMassSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, b, rho, problem, rtol=1e-10, maxit=5000):
+        problem.set_density(rho.detach().contiguous())
+        x, st, its, rel = problem.solve(b.detach().contiguous(), pc="bras", rtol=rtol, maxit=maxit)
+        if st != L.BRAS_OK:
+            raise L.BrasError(st, "forward solve: " + L.bras_last_error())
+        ctx.problem = problem
+        ctx.rtol, ctx.maxit = rtol, maxit
+        ctx.save_for_backward(x)
+        ctx.forward_iters = its
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        problem = ctx.problem
+        lam, st, its, rel = problem.solve(gx.detach().contiguous(), pc="bras", rtol=ctx.rtol, maxit=ctx.maxit)
+        if st != L.BRAS_OK:
+            raise L.BrasError(st, "adjoint solve: " + L.bras_last_error())
+        grho = problem.rho_grad(x, lam)
+        return lam, grho, None, None, None
+
+
+def mass_solve(b, rho, problem, rtol=1e-10, maxit=5000):
+    return BrasMassSolve.apply(b, rho, problem, rtol, maxit)

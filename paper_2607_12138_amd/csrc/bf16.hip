@@ -1,0 +1,13 @@
+// Multi-right-hand-side BRAS apply with the element inverses in BF16 Gram-
+// factor form on MFMA (gfx950).  Not built yet: bras_setup rejects BF16.
+#include "internal.h"
+
+namespace bras {
+
+int launch_bras_bf16(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
+                     const int* active) {
+  (void)c; (void)x; (void)y; (void)R; (void)s; (void)dotv; (void)dotpart; (void)active;
+  return fail(BRAS_EINVAL, "BF16 apply is not available in this build");
+}
+
+}  // namespace bras

@@ -1,0 +1,142 @@
+// Error reporting, introspection, options and the kernel-variant autotuner.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace bras {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+}  // namespace bras
+
+using namespace bras;
+
+extern "C" const char* bras_last_error(void) { return g_err; }
+
+extern "C" int bras_info(bras_handle h, int what, int64_t* value_h) {
+  clear_error();
+  BRAS_CHECK(h && value_h, "null argument");
+  Ctx* c = (Ctx*)h;
+  switch (what) {
+    case BRAS_INFO_N: *value_h = c->n; break;
+    case BRAS_INFO_E: *value_h = c->E; break;
+    case BRAS_INFO_NLOC: *value_h = c->nl; break;
+    case BRAS_INFO_NBR: *value_h = c->nbr; break;
+    case BRAS_INFO_PREC: *value_h = c->prec; break;
+    case BRAS_INFO_FORM: *value_h = c->form; break;
+    case BRAS_INFO_MAXRHS: *value_h = c->max_rhs; break;
+    case BRAS_INFO_RESTARTS: *value_h = c->last_restarts; break;
+    case BRAS_INFO_VARIANT: *value_h = c->variant; break;
+    default: return fail(BRAS_EINVAL, "unknown info key %d", what);
+  }
+  return BRAS_OK;
+}
+
+extern "C" int bras_set_option(bras_handle h, int opt, double value) {
+  clear_error();
+  BRAS_CHECK(h, "null handle");
+  Ctx* c = (Ctx*)h;
+  switch (opt) {
+    case BRAS_OPT_GRAPH_ITERS:
+      BRAS_CHECK(value >= 1 && value <= 32, "graph iterations must be in 1..32");
+      c->graph_iters = (int)value;
+      break;
+    case BRAS_OPT_MAX_RESTART:
+      BRAS_CHECK(value >= 0 && value <= 100, "restarts must be in 0..100");
+      c->max_restart = (int)value;
+      break;
+    case BRAS_OPT_VARIANT:
+      BRAS_CHECK(value >= -1 && value <= 1, "variant must be -1, 0 or 1");
+      c->variant = (int)value;
+      break;
+    default: return fail(BRAS_EINVAL, "unknown option %d", opt);
+  }
+  return BRAS_OK;
+}
+
+extern "C" int bras_export(bras_handle h, int what, void* dst_d, void* stream) {
+  clear_error();
+  BRAS_CHECK(h && dst_d, "null argument");
+  Ctx* c = (Ctx*)h;
+  hipStream_t s = (hipStream_t)stream;
+  switch (what) {
+    case BRAS_EXPORT_MULT:
+      BRAS_HIP(hipMemcpyAsync(dst_d, c->mult, sizeof(int32_t) * c->n, hipMemcpyDeviceToDevice, s));
+      break;
+    case BRAS_EXPORT_ROWPTR:
+      BRAS_HIP(hipMemcpyAsync(dst_d, c->rowptr, sizeof(int32_t) * (c->n + 1), hipMemcpyDeviceToDevice, s));
+      break;
+    case BRAS_EXPORT_DIAG:
+      BRAS_HIP(hipMemcpyAsync(dst_d, c->diag, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
+      break;
+    case BRAS_EXPORT_SLOT: {
+      // internal l*E + K -> canonical K*n_loc + l, on the host
+      std::vector<int32_t> in(c->nbr);
+      std::vector<int64_t> out(c->nbr);
+      BRAS_HIP(hipMemcpyAsync(in.data(), c->slot, sizeof(int32_t) * c->nbr, hipMemcpyDeviceToHost, s));
+      BRAS_HIP(hipStreamSynchronize(s));
+      for (int64_t p = 0; p < c->nbr; ++p) {
+        int64_t l = in[p] / c->E, K = in[p] % c->E;
+        out[p] = K * c->nl + l;
+      }
+      BRAS_HIP(hipMemcpyAsync(dst_d, out.data(), sizeof(int64_t) * c->nbr, hipMemcpyHostToDevice, s));
+      BRAS_HIP(hipStreamSynchronize(s));
+      break;
+    }
+    default: return fail(BRAS_EINVAL, "unknown export key %d", what);
+  }
+  return BRAS_OK;
+}
+
+extern "C" int bras_autotune(bras_handle h, int nrhs, void* stream) {
+  clear_error();
+  BRAS_CHECK(h, "null handle");
+  Ctx* c = (Ctx*)h;
+  BRAS_CHECK(nrhs >= 1 && nrhs <= c->max_rhs, "nrhs outside 1..max_rhs");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t vec = sizeof(double) * (size_t)c->n * nrhs;
+  double *x = nullptr, *y = nullptr;
+  BRAS_HIP(hipMalloc((void**)&x, vec));
+  BRAS_HIP(hipMalloc((void**)&y, vec));
+  BRAS_HIP(hipMemsetAsync(x, 0, vec, s));
+  hipEvent_t e0, e1;
+  BRAS_HIP(hipEventCreate(&e0));
+  BRAS_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_v = 0;
+  int st = BRAS_OK;
+  for (int v = 0; v <= 1 && st == BRAS_OK; ++v) {
+    c->variant = v;
+    for (int w = 0; w < 3 && st == BRAS_OK; ++w) st = launch_bras(c, x, y, nrhs, s, nullptr, nullptr, nullptr);
+    if (st) break;
+    (void)hipEventRecord(e0, s);
+    for (int rep = 0; rep < 10 && st == BRAS_OK; ++rep) st = launch_bras(c, x, y, nrhs, s, nullptr, nullptr, nullptr);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  c->variant = best_v;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(x);
+  (void)hipFree(y);
+  return st;
+}

@@ -1,0 +1,503 @@
+// Preconditioned conjugate gradients (Section 3), one independent CG per
+// column, entirely on the device:
+//
+//   x = x0; r = b - M x; z = C r; p = z; rho = r.z
+//   repeat: q = M p; alpha = rho / p.q; x += alpha p; r -= alpha q;
+//           stop when ||r|| <= rtol ||r_0|| (or maxit products M p);
+//           z = C r; rho' = r.z; beta = rho'/rho; p = z + beta p; rho = rho'
+//
+// alpha, beta, rho and the convergence flags live in device memory; every
+// dot product is a fixed-order two-stage reduction (per-block partials from
+// the producing kernel, then one block that sums them), so results are
+// bitwise reproducible.  Iterations are captured into hipGraphs of 1, 2, 4,
+// 8, 16 and 32 iterations; columns that have stopped are skipped by every
+// kernel, and the host reads the flags only between graph launches.
+// When the stored BRAS inverses are FP32/BF16 the flexible
+// beta = r_new.(z_new - z_old)/rho_old is used and, at exit, CG restarts
+// from x while the true residual is above the tolerance.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "internal.h"
+#include "block_reduce.h"
+
+namespace bras {
+
+constexpr int kBS = 256;
+constexpr int kNumGraphs = 6;   // 1, 2, 4, 8, 16, 32 iterations
+
+enum { S_RZ = 0, S_R0, S_TARGET, S_ALPHA, S_BETA, S_RZOLD, S_RELRES, S_RR, S_NSC };
+enum { I_ACTIVE = 0, I_ITERS, I_STATUS, I_NIC };
+enum { ST_RUN = 0, ST_OK = 1, ST_NOCONV = 2, ST_BREAK = 3 };
+
+struct CgState {
+  int R = 0;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double* sc = nullptr;      // [S_NSC][R]
+  int* ic = nullptr;         // [I_NIC][R]
+  double* part[3] = {nullptr, nullptr, nullptr};   // partials [blocks][R]
+  int* ic_host = nullptr;    // pinned copy of ic
+  double* sc_host = nullptr;
+  struct Key {
+    int pc, flexible, maxit;
+    bool operator<(const Key& o) const {
+      if (pc != o.pc) return pc < o.pc;
+      if (flexible != o.flexible) return flexible < o.flexible;
+      return maxit < o.maxit;
+    }
+  };
+  std::map<Key, std::vector<hipGraphExec_t>> graphs;
+};
+
+// Fixed-order sum of partial[b*R + col] over b < nb by one block.
+__device__ double block_sum(const double* __restrict__ partial, int nb, int R, int col, double* sh) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[(int64_t)b * R + col];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  double v = sh[0];
+  __syncthreads();
+  return v;
+}
+
+// r = b - q (q = M x), partial r.r
+__global__ void __launch_bounds__(kBS) k_residual(int64_t n, int R, const double* __restrict__ b,
+                                                  const double* __restrict__ q, double* __restrict__ r,
+                                                  double* __restrict__ partial) {
+  __shared__ double sh[kBS];
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double dot = 0.0;
+  for (int64_t t = t0; t < n * R; t += stride) {
+    const double v = b[t] - q[t];
+    r[t] = v;
+    dot = fma(v, v, dot);
+  }
+  sh[threadIdx.x] = dot;
+  block_partials(sh, R, partial);
+}
+
+// Start (or restart) of CG.  restart == 0: r_0 norm and target are set from
+// this residual.  Columns already within target are stopped.
+__global__ void k_fin_init(int nb, int R, const double* __restrict__ part, double* __restrict__ sc,
+                           int* __restrict__ ic, double rtol, int restart) {
+  __shared__ double sh[kBS];
+  for (int col = 0; col < R; ++col) {
+    const double rr = block_sum(part, nb, R, col, sh);
+    if (threadIdx.x == 0) {
+      const double nrm = sqrt(rr);
+      if (!restart) {
+        sc[S_R0 * R + col] = nrm;
+        sc[S_TARGET * R + col] = rtol * nrm;
+        ic[I_ITERS * R + col] = 0;
+      }
+      sc[S_RR * R + col] = rr;
+      const double r0 = sc[S_R0 * R + col];
+      sc[S_RELRES * R + col] = r0 > 0.0 ? nrm / r0 : 0.0;
+      if (!isfinite(nrm)) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
+      } else if (nrm <= sc[S_TARGET * R + col] || nrm == 0.0) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_OK;
+      } else {
+        ic[I_ACTIVE * R + col] = 1;
+        ic[I_STATUS * R + col] = ST_RUN;
+      }
+    }
+  }
+}
+
+// rho = r.z after the first preconditioner application; p = z happens in k_copy_active.
+__global__ void k_fin_rz(int nb, int R, const double* __restrict__ part, double* __restrict__ sc, int* __restrict__ ic) {
+  __shared__ double sh[kBS];
+  for (int col = 0; col < R; ++col) {
+    const double rz = block_sum(part, nb, R, col, sh);
+    if (threadIdx.x == 0 && ic[I_ACTIVE * R + col]) {
+      sc[S_RZ * R + col] = rz;
+      if (!(rz > 0.0) || !isfinite(rz)) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBS) k_copy_active(int64_t n, int R, const double* __restrict__ src,
+                                                     double* __restrict__ dst, const int* __restrict__ active) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int r = (int)(t0 % R);
+  if (!active[r]) return;
+  for (int64_t t = t0; t < n * R; t += stride) dst[t] = src[t];
+}
+
+// alpha = rho / p.q
+__global__ void k_fin_alpha(int nb, int R, const double* __restrict__ part, double* __restrict__ sc,
+                            int* __restrict__ ic) {
+  __shared__ double sh[kBS];
+  for (int col = 0; col < R; ++col) {
+    if (!ic[I_ACTIVE * R + col]) continue;   // uniform across the block
+    const double pq = block_sum(part, nb, R, col, sh);
+    if (threadIdx.x == 0) {
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
+      } else {
+        sc[S_ALPHA * R + col] = sc[S_RZ * R + col] / pq;
+      }
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; partials r.r (and r.z_old when flexible)
+__global__ void __launch_bounds__(kBS) k_update_xr(int64_t n, int R, double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   const double* __restrict__ z, const double* __restrict__ sc,
+                                                   const int* __restrict__ ic, double* __restrict__ part_rr,
+                                                   double* __restrict__ part_rz) {
+  __shared__ double sh[kBS];
+  __shared__ double sh2[kBS];
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int col = (int)(t0 % R);
+  double d1 = 0.0, d2 = 0.0;
+  if (ic[I_ACTIVE * R + col]) {
+    const double a = sc[S_ALPHA * R + col];
+    for (int64_t t = t0; t < n * R; t += stride) {
+      x[t] = fma(a, p[t], x[t]);
+      const double rv = fma(-a, q[t], r[t]);
+      r[t] = rv;
+      d1 = fma(rv, rv, d1);
+      if (part_rz) d2 = fma(rv, z[t], d2);
+    }
+  }
+  sh[threadIdx.x] = d1;
+  sh2[threadIdx.x] = d2;
+  block_partials(sh, R, part_rr);
+  if (part_rz) block_partials(sh2, R, part_rz);
+}
+
+// convergence test on the recursive residual
+__global__ void k_fin_conv(int nb, int R, const double* __restrict__ part_rr, const double* __restrict__ part_rz,
+                           double* __restrict__ sc, int* __restrict__ ic, int maxit) {
+  __shared__ double sh[kBS];
+  for (int col = 0; col < R; ++col) {
+    if (!ic[I_ACTIVE * R + col]) continue;
+    const double rr = block_sum(part_rr, nb, R, col, sh);
+    const double rzo = part_rz ? block_sum(part_rz, nb, R, col, sh) : 0.0;
+    if (threadIdx.x == 0) {
+      const int it = ic[I_ITERS * R + col] + 1;
+      ic[I_ITERS * R + col] = it;
+      const double nrm = sqrt(rr);
+      sc[S_RR * R + col] = rr;
+      sc[S_RZOLD * R + col] = rzo;
+      sc[S_RELRES * R + col] = nrm / sc[S_R0 * R + col];
+      if (!isfinite(nrm)) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
+      } else if (nrm <= sc[S_TARGET * R + col]) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_OK;
+      } else if (it >= maxit) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_NOCONV;
+      }
+    }
+  }
+}
+
+// beta = rho'/rho (or flexible), rho = rho'
+__global__ void k_fin_beta(int nb, int R, const double* __restrict__ part, double* __restrict__ sc,
+                           int* __restrict__ ic, int flexible) {
+  __shared__ double sh[kBS];
+  for (int col = 0; col < R; ++col) {
+    if (!ic[I_ACTIVE * R + col]) continue;
+    const double rz = block_sum(part, nb, R, col, sh);
+    if (threadIdx.x == 0) {
+      const double old = sc[S_RZ * R + col];
+      if (!(rz > 0.0) || !isfinite(rz)) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
+      } else {
+        sc[S_BETA * R + col] = flexible ? (rz - sc[S_RZOLD * R + col]) / old : rz / old;
+        sc[S_RZ * R + col] = rz;
+      }
+    }
+  }
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(kBS) k_update_p(int64_t n, int R, double* __restrict__ p,
+                                                  const double* __restrict__ z, const double* __restrict__ sc,
+                                                  const int* __restrict__ ic) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int col = (int)(t0 % R);
+  if (!ic[I_ACTIVE * R + col]) return;
+  const double be = sc[S_BETA * R + col];
+  for (int64_t t = t0; t < n * R; t += stride) p[t] = fma(be, p[t], z[t]);
+}
+
+// true residual norm at exit: relres = ||b - M x|| / ||r_0||
+__global__ void k_fin_true(int nb, int R, const double* __restrict__ part, double* __restrict__ sc) {
+  __shared__ double sh[kBS];
+  for (int col = 0; col < R; ++col) {
+    const double rr = block_sum(part, nb, R, col, sh);
+    if (threadIdx.x == 0) {
+      const double r0 = sc[S_R0 * R + col];
+      sc[S_RELRES * R + col] = r0 > 0.0 ? sqrt(rr) / r0 : 0.0;
+    }
+  }
+}
+
+void cg_free(Ctx* c) {
+  CgState* g = c->cg;
+  if (!g) return;
+  for (auto& kv : g->graphs)
+    for (auto ge : kv.second) (void)hipGraphExecDestroy(ge);
+  double* bufs[] = {g->b, g->x, g->r, g->z, g->p, g->q, g->sc, g->part[0], g->part[1], g->part[2]};
+  for (double* p : bufs)
+    if (p) (void)hipFree(p);
+  if (g->ic) (void)hipFree(g->ic);
+  if (g->ic_host) (void)hipHostFree(g->ic_host);
+  if (g->sc_host) (void)hipHostFree(g->sc_host);
+  delete g;
+  c->cg = nullptr;
+}
+
+static int cg_alloc(Ctx* c, int R) {
+  if (c->cg && c->cg->R == R) return BRAS_OK;
+  cg_free(c);
+  CgState* g = new CgState();
+  c->cg = g;
+  g->R = R;
+  const size_t vec = sizeof(double) * (size_t)c->n * R;
+  double** vs[] = {&g->b, &g->x, &g->r, &g->z, &g->p, &g->q};
+  for (double** v : vs)
+    if (hipMalloc((void**)v, vec) != hipSuccess) return fail(BRAS_ENOMEM, "CG workspace allocation failed");
+  if (hipMalloc((void**)&g->sc, sizeof(double) * S_NSC * R) != hipSuccess ||
+      hipMalloc((void**)&g->ic, sizeof(int) * I_NIC * R) != hipSuccess)
+    return fail(BRAS_ENOMEM, "CG scalar allocation failed");
+  const int nb = reduce_blocks(c, R);
+  for (int k = 0; k < 3; ++k)
+    if (hipMalloc((void**)&g->part[k], sizeof(double) * (size_t)nb * R) != hipSuccess)
+      return fail(BRAS_ENOMEM, "CG partial allocation failed");
+  if (hipHostMalloc((void**)&g->ic_host, sizeof(int) * I_NIC * R, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&g->sc_host, sizeof(double) * S_NSC * R, hipHostMallocDefault) != hipSuccess)
+    return fail(BRAS_ENOMEM, "pinned host allocation failed");
+  return BRAS_OK;
+}
+
+__global__ void __launch_bounds__(kBS) k_identity_dot(int64_t n, int R, const double* __restrict__ r,
+                                                      double* __restrict__ z, double* __restrict__ partial,
+                                                      const int* __restrict__ active) {
+  __shared__ double sh[kBS];
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int col = (int)(t0 % R);
+  double d = 0.0;
+  if (!active || active[col])
+    for (int64_t t = t0; t < n * R; t += stride) {
+      z[t] = r[t];
+      d = fma(r[t], r[t], d);
+    }
+  sh[threadIdx.x] = d;
+  block_partials(sh, R, partial);
+}
+
+static int precond(Ctx* c, int pc, const double* r, double* z, int R, hipStream_t s, double* part, const int* active) {
+  if (pc == BRAS_PC_BRAS) return launch_bras(c, r, z, R, s, r, part, active);
+  if (pc == BRAS_PC_JACOBI) return launch_jacobi(c, r, z, R, s, r, part, active);
+  // identity preconditioner: z = r, partial r.r
+  k_identity_dot<<<reduce_blocks(c, R), kBS, 0, s>>>(c->n, R, r, z, part, active);
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+// One CG iteration (enqueued on s; also used under stream capture).
+static int iteration(Ctx* c, int pc, int flexible, int maxit, hipStream_t s) {
+  CgState* g = c->cg;
+  const int R = g->R;
+  const int nb = reduce_blocks(c, R);
+  int* active = g->ic + I_ACTIVE * R;
+  int st;
+  if ((st = launch_mass(c, g->p, g->q, R, s, g->p, g->part[0], active))) return st;
+  k_fin_alpha<<<1, kBS, 0, s>>>(nb, R, g->part[0], g->sc, g->ic);
+  k_update_xr<<<nb, kBS, 0, s>>>(c->n, R, g->x, g->r, g->p, g->q, g->z, g->sc, g->ic, g->part[1],
+                                 flexible ? g->part[2] : nullptr);
+  k_fin_conv<<<1, kBS, 0, s>>>(nb, R, g->part[1], flexible ? g->part[2] : nullptr, g->sc, g->ic, maxit);
+  if ((st = precond(c, pc, g->r, g->z, R, s, g->part[0], active))) return st;
+  k_fin_beta<<<1, kBS, 0, s>>>(nb, R, g->part[0], g->sc, g->ic, flexible);
+  k_update_p<<<nb, kBS, 0, s>>>(c->n, R, g->p, g->z, g->sc, g->ic);
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+static int start(Ctx* c, int pc, double rtol, int restart, hipStream_t s) {
+  CgState* g = c->cg;
+  const int R = g->R;
+  const int nb = reduce_blocks(c, R);
+  int st;
+  if ((st = launch_mass(c, g->x, g->q, R, s, nullptr, nullptr, nullptr))) return st;
+  k_residual<<<nb, kBS, 0, s>>>(c->n, R, g->b, g->q, g->r, g->part[1]);
+  k_fin_init<<<1, kBS, 0, s>>>(nb, R, g->part[1], g->sc, g->ic, rtol, restart);
+  int* active = g->ic + I_ACTIVE * R;
+  if ((st = precond(c, pc, g->r, g->z, R, s, g->part[0], active))) return st;
+  k_fin_rz<<<1, kBS, 0, s>>>(nb, R, g->part[0], g->sc, g->ic);
+  k_copy_active<<<nb, kBS, 0, s>>>(c->n, R, g->z, g->p, active);
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+static int read_state(Ctx* c, hipStream_t s) {
+  CgState* g = c->cg;
+  BRAS_HIP(hipMemcpyAsync(g->ic_host, g->ic, sizeof(int) * I_NIC * g->R, hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipMemcpyAsync(g->sc_host, g->sc, sizeof(double) * S_NSC * g->R, hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  return BRAS_OK;
+}
+
+static int get_graphs(Ctx* c, int pc, int flexible, int maxit, std::vector<hipGraphExec_t>** out) {
+  CgState* g = c->cg;
+  CgState::Key key{pc, flexible, maxit};
+  auto it = g->graphs.find(key);
+  if (it != g->graphs.end()) {
+    *out = &it->second;
+    return BRAS_OK;
+  }
+  std::vector<hipGraphExec_t> v;
+  hipStream_t s = c->s_int;
+  for (int k = 0; k < kNumGraphs; ++k) {
+    const int iters = 1 << k;
+    BRAS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int st = BRAS_OK;
+    for (int i = 0; i < iters && st == BRAS_OK; ++i) st = iteration(c, pc, flexible, maxit, s);
+    hipGraph_t graph;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st) return st;
+    if (e != hipSuccess) return fail(BRAS_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t ge;
+    e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(BRAS_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    v.push_back(ge);
+  }
+  g->graphs[key] = v;
+  *out = &g->graphs[key];
+  return BRAS_OK;
+}
+
+}  // namespace bras
+
+using namespace bras;
+
+extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, int nrhs, double rtol, int maxit,
+                         int* iters_h, double* relres_h, void* stream) {
+  clear_error();
+  BRAS_CHECK(h && b_d && x_d, "null argument");
+  Ctx* c = (Ctx*)h;
+  BRAS_CHECK(pc == BRAS_PC_NONE || pc == BRAS_PC_JACOBI || pc == BRAS_PC_BRAS, "unknown preconditioner %d", pc);
+  BRAS_CHECK(nrhs >= 1 && nrhs <= c->max_rhs, "nrhs %d outside 1..max_rhs=%d", nrhs, c->max_rhs);
+  BRAS_CHECK(rtol > 0.0 && rtol < 1.0, "rtol must be in (0, 1)");
+  BRAS_CHECK(maxit >= 1, "maxit must be >= 1");
+  int st = cg_alloc(c, nrhs);
+  if (st) return st;
+  CgState* g = c->cg;
+  hipStream_t us = (hipStream_t)stream, s = c->s_int;
+  const size_t vec = sizeof(double) * (size_t)c->n * nrhs;
+  // graphs are captured on the idle internal stream before any work is queued
+  const int flexible = (pc == BRAS_PC_BRAS && c->prec != BRAS_FP64) ? 1 : 0;
+  std::vector<hipGraphExec_t>* graphs = nullptr;
+  if ((st = get_graphs(c, pc, flexible, maxit, &graphs))) return st;
+  // order the internal stream after the caller's prior work
+  hipEvent_t ev;
+  BRAS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  BRAS_HIP(hipEventRecord(ev, us));
+  BRAS_HIP(hipStreamWaitEvent(s, ev, 0));
+  BRAS_HIP(hipMemcpyAsync(g->b, b_d, vec, hipMemcpyDeviceToDevice, s));
+  BRAS_HIP(hipMemcpyAsync(g->x, x_d, vec, hipMemcpyDeviceToDevice, s));
+  const int R = nrhs;
+  const int nb = reduce_blocks(c, R);
+  int restarts = 0;
+  int restart_mode = 0;
+  while (true) {
+    if ((st = start(c, pc, rtol, restart_mode, s))) break;
+    if ((st = read_state(c, s))) break;
+    // iterate: predict the remaining iterations from the observed rate
+    while (true) {
+      int any = 0, max_it = 0;
+      double worst_log = 0.0, worst_rate = 0.0;
+      for (int col = 0; col < R; ++col) {
+        if (!g->ic_host[I_ACTIVE * R + col]) continue;
+        any = 1;
+        const int it = g->ic_host[I_ITERS * R + col];
+        max_it = it > max_it ? it : max_it;
+        const double rel = g->sc_host[S_RELRES * R + col];
+        const double tgt = g->sc_host[S_TARGET * R + col] / g->sc_host[S_R0 * R + col];
+        if (it > 0 && rel > 0.0 && rel < 1.0) {
+          const double rate = std::log(rel) / it;   // per-iteration log reduction (< 0)
+          const double need = std::log(tgt / rel) / rate;
+          if (need > worst_log) worst_log = need;
+          if (rate > worst_rate || worst_rate == 0.0) worst_rate = rate;
+        } else {
+          if (4.0 > worst_log) worst_log = 4.0;
+        }
+      }
+      if (!any) break;
+      int chunk = (int)std::ceil(worst_log);
+      if (chunk < 1) chunk = 1;
+      if (chunk > 32) chunk = 32;
+      if (chunk > maxit - max_it + 1) chunk = maxit - max_it + 1;
+      if (chunk < 1) chunk = 1;
+      for (int k = kNumGraphs - 1; k >= 0 && st == BRAS_OK; --k)
+        if (chunk & (1 << k)) {
+          hipError_t e = hipGraphLaunch((*graphs)[k], s);
+          if (e != hipSuccess) st = fail(BRAS_EHIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
+        }
+      if (st) break;
+      if ((st = read_state(c, s))) break;
+    }
+    if (st) break;
+    // true residual
+    if ((st = launch_mass(c, g->x, g->q, R, s, nullptr, nullptr, nullptr))) break;
+    k_residual<<<nb, kBS, 0, s>>>(c->n, R, g->b, g->q, g->z, g->part[1]);
+    k_fin_true<<<1, kBS, 0, s>>>(nb, R, g->part[1], g->sc);
+    if ((st = read_state(c, s))) break;
+    bool again = false;
+    for (int col = 0; col < R; ++col)
+      if (g->ic_host[I_STATUS * R + col] == ST_OK && g->sc_host[S_RELRES * R + col] > rtol &&
+          g->ic_host[I_ITERS * R + col] < maxit)
+        again = true;
+    if (!again || !flexible || restarts >= c->max_restart) break;
+    ++restarts;
+    restart_mode = 1;
+  }
+  c->last_restarts = restarts;
+  if (st == BRAS_OK) {
+    hipError_t e = hipMemcpyAsync(x_d, g->x, vec, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) st = fail(BRAS_EHIP, "copy of the solution failed");
+    BRAS_HIP(hipEventRecord(ev, s));
+    BRAS_HIP(hipStreamWaitEvent(us, ev, 0));
+    BRAS_HIP(hipStreamSynchronize(s));
+  }
+  (void)hipEventDestroy(ev);
+  if (st) return st;
+  int result = BRAS_OK;
+  for (int col = 0; col < R; ++col) {
+    if (iters_h) iters_h[col] = g->ic_host[I_ITERS * R + col];
+    if (relres_h) relres_h[col] = g->sc_host[S_RELRES * R + col];
+    const int cs = g->ic_host[I_STATUS * R + col];
+    if (cs == ST_BREAK) result = BRAS_EBREAKDOWN;
+    else if (cs == ST_NOCONV && result == BRAS_OK) result = BRAS_ENOCONV;
+  }
+  if (result == BRAS_EBREAKDOWN) return fail(result, "PCG breakdown (p.q <= 0, r.z <= 0 or non-finite values)");
+  if (result == BRAS_ENOCONV) return fail(result, "PCG did not reach rtol=%g within maxit=%d", rtol, maxit);
+  return BRAS_OK;
+}

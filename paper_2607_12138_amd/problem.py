@@ -1,0 +1,110 @@
+"""A conforming mass system on a structured simplicial mesh, built and solved
+entirely by libbras (mesh, numbering and reference tables on the host side of
+the library; geometry, maps, element inverses, operators and PCG in HIP
+kernels).  torch provides device memory and the stream only.
+"""
+import numpy as np
+
+from . import _lib as L
+
+
+class MassProblem:
+    def __init__(self, family, dim, degree, N, jitter=0.0, seed=0, rho=None, prec="f64", max_rhs=1,
+                 device="cuda"):
+        import torch
+        self.family = L.FAMILY[family] if isinstance(family, str) else family
+        self.dim, self.degree, self.N = dim, degree, N
+        self.prec = L.PREC[prec] if isinstance(prec, str) else prec
+        self.max_rhs = max_rhs
+        self.device = torch.device(device)
+        self.coords, self.cells = L.bras_mesh_structured(dim, N, jitter, seed)
+        self.n, self.l2g = L.bras_dofmap(self.family, dim, degree, len(self.coords), self.cells)
+        self.n_loc, self.dofs_per_entity = L.bras_element_info(self.family, dim, degree)
+        self.E = len(self.cells)
+        self.ref = L.bras_reference_mass(self.family, dim, degree)
+        dev = self.device
+        self.coords_d = torch.from_numpy(self.coords).to(dev)
+        self.cells_d = torch.from_numpy(self.cells).to(dev)
+        self.l2g_d = torch.from_numpy(self.l2g).to(dev)
+        self.ref_d = torch.from_numpy(np.ascontiguousarray(self.ref)).to(dev)
+        if self.family == L.H1:
+            self.form, self.nsym = L.ELEM_SCALED_REF, 0
+            self.elem_d = torch.empty(self.E, dtype=torch.float64, device=dev)
+            self.dcoef_d = torch.empty(self.E, dtype=torch.float64, device=dev)
+            L.bras_geometry(self.family, dim, self.coords_d, self.cells_d, None, self.dcoef_d)
+        else:
+            self.form, self.nsym = L.ELEM_METRIC_REF, L.nsym(dim)
+            self.elem_d = torch.empty((self.E, self.nsym), dtype=torch.float64, device=dev)
+            self.dcoef_d = None
+        self.rho_d = None if rho is None else torch.as_tensor(np.asarray(rho, dtype=np.float64), device=dev)
+        L.bras_geometry(self.family, dim, self.coords_d, self.cells_d, self.rho_d, self.elem_d)
+        self.h = L.bras_setup(self.n, self.E, self.n_loc, self.l2g_d, self.form, self.ref_d, self.elem_d, self.nsym,
+                              self.prec, max_rhs)
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            L.bras_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- operators ---------------------------------------------------------
+    def vec(self, nrhs=1):
+        import torch
+        shape = (self.n,) if nrhs == 1 else (self.n, nrhs)
+        return torch.zeros(shape, dtype=torch.float64, device=self.device)
+
+    def bras(self, x, y=None):
+        y = self.vec(1 if x.dim() == 1 else x.shape[1]) if y is None else y
+        L.bras_apply(self.h, x, y)
+        return y
+
+    def mass(self, x, y=None):
+        y = self.vec(1 if x.dim() == 1 else x.shape[1]) if y is None else y
+        L.mass_apply(self.h, x, y)
+        return y
+
+    def jacobi(self, x, y=None):
+        y = self.vec(1 if x.dim() == 1 else x.shape[1]) if y is None else y
+        L.jacobi_apply(self.h, x, y)
+        return y
+
+    def solve(self, b, pc="bras", rtol=1e-10, maxit=5000, x0=None):
+        """Returns (x, status, iterations, true relative residuals)."""
+        pcode = {"none": L.PC_NONE, "jacobi": L.PC_JACOBI, "bras": L.PC_BRAS}[pc]
+        x = self.vec(1 if b.dim() == 1 else b.shape[1]) if x0 is None else x0.clone()
+        st, its, rel = L.pcg_solve(self.h, pcode, b, x, rtol, maxit)
+        return x, st, its, rel
+
+    def set_density(self, rho_d):
+        """Recompute element coefficients rho_K |det J_K| and the inverses (H1)."""
+        self.rho_d = rho_d
+        L.bras_geometry(self.family, self.dim, self.coords_d, self.cells_d, rho_d, self.elem_d)
+        L.bras_update(self.h, self.elem_d)
+
+    def rho_grad(self, x, lam, g=None):
+        import torch
+        g = torch.empty(self.E, dtype=torch.float64, device=self.device) if g is None else g
+        L.bras_rho_grad(self.h, x, lam, self.dcoef_d, g)
+        return g
+
+    def info(self, what):
+        return L.bras_info(self.h, what)
+
+    def export(self, what):
+        import torch
+        if what == L.EXPORT_MULT:
+            out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        elif what == L.EXPORT_ROWPTR:
+            out = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        elif what == L.EXPORT_SLOT:
+            out = torch.empty(self.E * self.n_loc, dtype=torch.int64, device=self.device)
+        else:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        L.bras_export(self.h, what, out)
+        return out

@@ -1,0 +1,79 @@
+"""C-ABI library: loads, exports what the header declares, and its host helpers
+(mesh, numbering, reference tables) agree with the oracle.  CPU only: no
+device call is made."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2607_12138_amd import _lib as L
+from oracle import mesh as omesh, dofmap as odofmap, fe as ofe
+
+
+def test_library_exports_every_header_symbol():
+    lib = L.lib()
+    names = L.header_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(L._SIGS) | {"bras_last_error"} == set(names)
+
+
+@pytest.mark.parametrize("dim,N,jit,seed", [(2, 7, 0.0, 0), (2, 9, 0.2, 123), (3, 5, 0.0, 0), (3, 6, 0.2, 99),
+                                            (3, 24, 0.2, 0x260712138 + 32)])
+def test_mesh_bit_exact(dim, N, jit, seed):
+    c1, t1 = L.bras_mesh_structured(dim, N, jit, seed)
+    c2, t2 = omesh.structured_mesh(dim, N, jitter=jit, seed=seed)
+    assert np.array_equal(t1, t2)
+    assert np.array_equal(c1.view(np.uint64), c2.view(np.uint64))
+
+
+CASES = [("P", 2, 1), ("P", 2, 3), ("P", 3, 1), ("P", 3, 3), ("P", 3, 4), ("N1curl", 3, 1), ("N1curl", 3, 2),
+         ("RT", 3, 1), ("RT", 3, 4), ("RT", 2, 2), ("N1curl", 2, 3), ("P", 2, 5)]
+
+
+@pytest.mark.parametrize("family,dim,deg", CASES)
+def test_element_info(family, dim, deg):
+    nl, counts = L.bras_element_info(L.FAMILY[family], dim, deg)
+    ref = ofe.reference_element(family, dim, deg)
+    assert nl == ref.n_loc
+    assert counts == tuple(ref.dofs_per_entity)
+
+
+@pytest.mark.parametrize("family,dim,deg", CASES)
+def test_dofmap_bit_exact(family, dim, deg):
+    coords, cells = omesh.structured_mesh(dim, 3, jitter=0.2, seed=4)
+    n1, l2g = L.bras_dofmap(L.FAMILY[family], dim, deg, len(coords), cells)
+    ref = ofe.reference_element(family, dim, deg)
+    pi, n2, _ = odofmap.build_dofmap(cells, len(coords), ref.dofs_per_entity)
+    assert n1 == n2
+    assert np.array_equal(l2g, pi.astype(np.int32))
+
+
+@pytest.mark.parametrize("family,dim,deg", CASES)
+def test_reference_mass_matches_oracle(family, dim, deg):
+    lib_tab = L.bras_reference_mass(L.FAMILY[family], dim, deg)
+    ref = ofe.reference_element(family, dim, deg)
+    if family == "P":
+        expect = ref.mass[None]
+        got = lib_tab[None]
+    else:
+        pairs = [(a, b) for a in range(dim) for b in range(a, dim)]
+        expect = np.array([ref.mass[a, a] if a == b else ref.mass[a, b] + ref.mass[b, a] for a, b in pairs])
+        got = lib_tab
+    scale = np.max(np.abs(expect))
+    assert np.max(np.abs(got - expect)) <= 2e-15 * scale * max(1, ref.n_loc / 10)
+
+
+def test_host_errors_are_reported():
+    with pytest.raises(L.BrasError) as e:
+        L.bras_mesh_size(4, 3)
+    assert e.value.code == L.BRAS_EINVAL and "dim" in str(e.value)
+    with pytest.raises(L.BrasError):
+        L.bras_element_info(L.HDIV, 3, 9)
+    bad = np.array([[0, 2, 1]], dtype=np.int32)          # not ascending
+    with pytest.raises(L.BrasError) as e:
+        L.bras_dofmap(L.H1, 2, 1, 3, bad)
+    assert "ascending" in str(e.value)
+    nv = ctypes.c_int64()
+    assert L.lib().bras_mesh_size(3, 2, None, ctypes.byref(nv)) == L.BRAS_EINVAL

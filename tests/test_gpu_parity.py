@@ -1,0 +1,231 @@
+"""GPU parity: the HIP library against the oracle on small seeded problems that
+span several tiles and a ragged tail.  Every call goes through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fe as ofe, mesh as omesh, assembly as oasm, pcg as opcg
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # family, dim, degree, N, jitter, density, prec
+    ("P", 2, 1, 11, 0.0, False, "f64"),
+    ("P", 2, 4, 7, 0.2, False, "f64"),
+    ("P", 3, 3, 5, 0.2, False, "f64"),
+    ("P", 3, 4, 4, 0.0, True, "f64"),
+    ("P", 3, 2, 3, 0.2, True, "f64"),
+    ("N1curl", 3, 2, 4, 0.2, False, "f64"),
+    ("N1curl", 3, 2, 4, 0.2, False, "f32"),
+    ("N1curl", 3, 1, 4, 0.2, False, "f64"),
+    ("RT", 3, 1, 5, 0.2, False, "f64"),
+    ("RT", 3, 4, 2, 0.2, False, "f64"),
+    ("RT", 2, 3, 6, 0.2, False, "f32"),
+]
+
+_cache = {}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def build(case, max_rhs=1):
+    key = case + (max_rhs,)
+    if key in _cache:
+        return _cache[key]
+    from paper_2607_12138_amd.problem import MassProblem
+    family, dim, deg, N, jit, dens, prec = case
+    seed = 1000 + N
+    coords, cells = omesh.structured_mesh(dim, N, jitter=jit, seed=seed)
+    rho = workloads.density(len(cells), seed + 1) if dens else None
+    ref = ofe.reference_element(family, dim, deg)
+    orc = oasm.Problem(ref, coords, cells, rho=rho)
+    say("setup %s max_rhs=%d" % (case, max_rhs))
+    gpu = MassProblem(family, dim, deg, N, jitter=jit, seed=seed, rho=rho, prec=prec, max_rhs=max_rhs)
+    _cache[key] = (orc, gpu)
+    return orc, gpu
+
+
+def ids(c):
+    return "%s%d-%dd-N%d-%s%s" % (c[0], c[2], c[1], c[3], c[6], "-rho" if c[5] else "")
+
+
+def to_t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_inf(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_maps_bit_exact(case):
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(case)
+    assert gpu.n == orc.n and np.array_equal(gpu.l2g, orc.pi.astype(np.int32))
+    say("export maps %s" % (case,))
+    mult = gpu.export(L.EXPORT_MULT).cpu().numpy()
+    rowptr = gpu.export(L.EXPORT_ROWPTR).cpu().numpy()
+    slot = gpu.export(L.EXPORT_SLOT).cpu().numpy()
+    assert np.array_equal(mult, orc.d)
+    assert np.array_equal(rowptr, np.concatenate([[0], np.cumsum(orc.d)]))
+    assert np.array_equal(slot, np.argsort(orc.pi.ravel(), kind="stable"))
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_diag_matches(case):
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(case)
+    say("diag %s" % (case,))
+    diag = gpu.export(L.EXPORT_DIAG).cpu().numpy()
+    assert rel_inf(diag, orc.diag) <= 1e-14
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_operators_match(case):
+    orc, gpu = build(case)
+    x = workloads.vector(orc.n, 31)
+    xd = to_t(x)
+    say("mass_apply %s" % (case,))
+    ym = gpu.mass(xd).cpu().numpy()
+    assert rel_inf(ym, orc.M @ x) <= 1e-13
+    say("jacobi_apply %s" % (case,))
+    yj = gpu.jacobi(xd).cpu().numpy()
+    assert rel_inf(yj, x / orc.diag) <= 1e-14
+    say("bras_apply %s" % (case,))
+    yb = gpu.bras(xd).cpu().numpy()
+    err = rel_inf(yb, orc.B @ x)
+    if case[6] == "f64":
+        assert err <= 1e-13
+    else:
+        # FP32 element inverses: error of order cond(M_K) * 2^-24
+        assert err <= 2e-4
+        say("  fp32 bras_apply rel. error vs fp64 oracle: %.3e" % err)
+
+
+@pytest.mark.parametrize("case", [CASES[2], CASES[5], CASES[8]], ids=ids)
+@pytest.mark.parametrize("R", [3, 4])
+def test_multi_rhs_columns(case, R):
+    orc, gpu = build(case, max_rhs=8)
+    X = workloads.rhs(orc.n, R, 77)
+    Xd = to_t(X)
+    say("multi-rhs R=%d %s" % (R, case))
+    Yb = gpu.bras(Xd).cpu().numpy()
+    Ym = gpu.mass(Xd).cpu().numpy()
+    for r in range(R):
+        assert rel_inf(Yb[:, r], orc.B @ X[:, r]) <= 1e-13
+        assert rel_inf(Ym[:, r], orc.M @ X[:, r]) <= 1e-13
+    # one column at a time gives bitwise the same as the batched call
+    y0 = gpu.bras(to_t(np.ascontiguousarray(X[:, 1]))).cpu().numpy()
+    assert rel_inf(y0, Yb[:, 1]) <= 1e-15
+
+
+@pytest.mark.parametrize("case", [CASES[2], CASES[6]], ids=ids)
+def test_deterministic(case):
+    orc, gpu = build(case)
+    xd = to_t(workloads.vector(orc.n, 5))
+    say("determinism %s" % (case,))
+    a = gpu.bras(xd).cpu().numpy()
+    b = gpu.bras(xd).cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    bd = to_t(workloads.rhs(orc.n, 1, 6))
+    x1, st1, i1, r1 = gpu.solve(bd, "bras", rtol=1e-8)
+    x2, st2, i2, r2 = gpu.solve(bd, "bras", rtol=1e-8)
+    assert np.array_equal(x1.cpu().numpy().view(np.uint64), x2.cpu().numpy().view(np.uint64))
+    assert list(i1) == list(i2)
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+@pytest.mark.parametrize("pc", ["bras", "jacobi"])
+def test_pcg_matches_oracle(case, pc):
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(case)
+    tol = 1e-10 if case[6] == "f64" else 1e-8
+    b = workloads.rhs(orc.n, 1, 41)
+    C = orc.B.dot if pc == "bras" else opcg.jacobi(orc.diag)
+    xo, ito, ok, _ = opcg.pcg(orc.M, b, C, tol=tol)
+    assert ok
+    say("pcg %s %s" % (pc, case))
+    x, st, its, rel = gpu.solve(to_t(b), pc, rtol=tol)
+    assert st == L.BRAS_OK
+    x = x.cpu().numpy()
+    true_rel = np.linalg.norm(b - orc.M @ x) / np.linalg.norm(b)
+    assert true_rel <= tol * 1.5 and abs(rel[0] - true_rel) <= 1e-3 * tol + 1e-15
+    if case[6] == "f64" or pc == "jacobi":
+        assert abs(int(its[0]) - ito) <= 1
+    assert np.linalg.norm(x - xo) <= 1e4 * tol * np.linalg.norm(xo)
+
+
+def test_pcg_multi_rhs_independent_columns():
+    case = CASES[5]
+    orc, gpu = build(case, max_rhs=8)
+    B = workloads.rhs(orc.n, 4, 51)
+    B[:, 2] *= 1e-3                        # columns converge independently
+    say("pcg multi-rhs %s" % (case,))
+    X, st, its, rel = gpu.solve(to_t(B), "bras", rtol=1e-10)
+    X = X.cpu().numpy()
+    for r in range(4):
+        xo, ito, ok, _ = opcg.pcg(orc.M, B[:, r], orc.B.dot, tol=1e-10)
+        assert abs(int(its[r]) - ito) <= 1
+        assert np.linalg.norm(B[:, r] - orc.M @ X[:, r]) <= 1.5e-10 * np.linalg.norm(B[:, r])
+
+
+def test_warm_start_and_zero_rhs():
+    from paper_2607_12138_amd import _lib as L
+    case = CASES[2]
+    orc, gpu = build(case)
+    say("warm start / zero rhs %s" % (case,))
+    bh = workloads.rhs(orc.n, 1, 3)
+    b = to_t(bh)
+    x, st, its, rel = gpu.solve(b, "bras", rtol=1e-4)
+    # resume from a saved iterate: the stopping test is relative to ||b - M x0||
+    x2, st2, its2, rel2 = gpu.solve(b, "bras", rtol=1e-6, x0=x)
+    xo, ito, ok, _ = opcg.pcg(orc.M, bh, orc.B.dot, x0=x.cpu().numpy(), tol=1e-6)
+    assert st2 == L.BRAS_OK and abs(int(its2[0]) - ito) <= 1
+    z = gpu.vec()
+    x3, st3, its3, rel3 = gpu.solve(z, "bras", rtol=1e-10)
+    assert st3 == L.BRAS_OK and its3[0] == 0 and float(x3.abs().max()) == 0.0
+
+
+def test_error_paths():
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    say("error paths")
+    orc, gpu = build(CASES[0])
+    n, E, nl = gpu.n, gpu.E, gpu.n_loc
+    ref = gpu.ref_d
+    elem = gpu.elem_d
+    bad = gpu.l2g.copy()
+    bad[3, 1] = n + 5
+    with pytest.raises(L.BrasError) as e:
+        L.bras_setup(n, E, nl, to_t(bad), L.ELEM_SCALED_REF, ref, elem, 0, L.FP64, 1)
+    assert e.value.code == L.BRAS_EINVAL and "element 3" in str(e.value)
+    dup = gpu.l2g.copy()
+    dup[5, 2] = dup[5, 0]
+    with pytest.raises(L.BrasError) as e:
+        L.bras_setup(n, E, nl, to_t(dup), L.ELEM_SCALED_REF, ref, elem, 0, L.FP64, 1)
+    assert e.value.code == L.BRAS_EINVAL
+    with pytest.raises(L.BrasError) as e:                      # DOF n has no copy
+        L.bras_setup(n + 1, E, nl, gpu.l2g_d, L.ELEM_SCALED_REF, ref, elem, 0, L.FP64, 1)
+    assert e.value.code == L.BRAS_EINVAL and "no broken copy" in str(e.value)
+    neg = elem.clone()
+    neg[7] = -1.0
+    with pytest.raises(L.BrasError) as e:
+        L.bras_setup(n, E, nl, gpu.l2g_d, L.ELEM_SCALED_REF, ref, neg, 0, L.FP64, 1)
+    assert e.value.code == L.BRAS_ENOTSPD and "element 7" in str(e.value)
+    b = to_t(workloads.rhs(n, 1, 2))
+    x = gpu.vec()
+    st, its, rel = L.pcg_solve(gpu.h, L.PC_JACOBI, b, x, 1e-10, 1)
+    assert st == L.BRAS_ENOCONV and its[0] == 1
+    with pytest.raises(L.BrasError):
+        L.bras_apply(gpu.h, b, b)                               # aliasing rejected
+    nanb = b.clone()
+    nanb[0] = float("nan")
+    st, its, rel = L.pcg_solve(gpu.h, L.PC_BRAS, nanb, gpu.vec(), 1e-10, 100)
+    assert st == L.BRAS_EBREAKDOWN
+    torch.cuda.synchronize()
