@@ -2,196 +2,361 @@
 // mhatinvbras_def, mass_and_bras_element_sums), the conforming mass
 // M = P^T M_br P (eq. M_PMbrP), diag(M)^-1, and the density gradient.
 //
-// Every operator is two passes:
-//   element pass  one thread per (element K, column r): gather the K-th
-//                 element's entries of x (optionally times D^-1), multiply by
-//                 the element matrix, write the broken result z_K to the
-//                 broken vector in element-fastest order (slot l*E + K), so a
-//                 wavefront's stores are contiguous;
-//   reduce pass   one thread per (conforming DOF i, column r): sum the broken
-//                 copies of i in the fixed order of the transpose map, scale
-//                 (D^-1 for BRAS), optionally accumulate a dot product with a
-//                 second vector into per-block partial sums (deterministic
-//                 tree in LDS, no atomics).
-// Vectors with several columns are [n][R] (column fastest): the R threads of
-// one element read R consecutive doubles per gathered DOF.
+// Every operator is two passes over device memory:
+//   element pass  a 256-thread work-group owns floor(256/n_loc) whole
+//                 elements, one thread per element row: the thread gathers
+//                 one entry of the input (optionally an axpy of two vectors,
+//                 times D^-1) into LDS, then forms its row of M_K w_K (or
+//                 M_K^-1 w_K) from the element's gathered vector and writes
+//                 it to the broken vector in element-major order K*n_loc + l,
+//                 so loads of the map and stores of the result are contiguous;
+//   reduce pass   one thread per (conforming DOF, column): sum the DOF's
+//                 broken copies in the fixed order of the transpose map, scale
+//                 by D^-1 (BRAS), and either store the result, or run the CG
+//                 update that consumes it, with dot products accumulated into
+//                 per-block partials that the last work-group sums in block
+//                 order (no floating-point atomics anywhere).
+// Vectors with several columns are [n][R] (column fastest).
 #include <cmath>
 
 #include "internal.h"
 #include "block_reduce.h"
+#include "cg_common.h"
 
 namespace bras {
 
-constexpr int kBS = 256;
-constexpr int kMaxReduceBlocks = 2048;
+constexpr int kBS = 256;                  // reduce / vector pass block size
+constexpr int kEB = 256;                  // element pass block size
+constexpr int kMaxVectorBlocks = 512;
+
+enum { FORM_SCALED = 0, FORM_PACKED = 1, FORM_METRIC = 2 };
+enum { OUT_PLAIN = 0, OUT_MASS_CG = 1, OUT_BRAS_CG = 2 };
+
+__device__ __forceinline__ int packed_index(int i, int j) {
+  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
 
 // ---------------------------------------------------------------------------
-// element passes
+// element pass
 // ---------------------------------------------------------------------------
+// A work-group owns 64 consecutive elements, one per lane.  Gather phase: all
+// 256 threads read the 64 elements' map entries (contiguous) and the gathered
+// input values into LDS, w[j][e] (row stride 65 to spread banks).  Product
+// phase: wave v computes rows v, v+4, v+8, ... of all 64 elements, so every
+// table entry it reads for a row is the same in all lanes (wave-uniform scalar
+// loads) and every store of a row is 64 consecutive elements of the
+// local-index-major broken vector zb[l][K] (column fastest).
+//   FORM_SCALED  z_l = coefK[K] sum_j A[l][j] w_j           (A shared)
+//   FORM_PACKED  z_l = sum_j P_K(l, j) w_j                   (P_K packed lower, [q][E])
+//   FORM_METRIC  z_l = sum_p G_p,K sum_j S_p[l][j] w_j       (S_p shared, G [p][E])
+// T is the arithmetic type (float for FP32 element inverses).
+constexpr int kEPB = 64;        // elements per work-group (one per lane)
+constexpr int kWS = kEPB + 1;   // LDS row stride
 
-// Shared reference matrix (affine H1): z_K = coef_K * A (w_K), w_K = (s x)[pi_K].
-template <int NL, bool SCALE_IN>
-__global__ void __launch_bounds__(kBS) k_scaled_elem(int64_t E, int R, const int32_t* __restrict__ l2gT,
-                                                     const double* __restrict__ x, const double* __restrict__ invd,
-                                                     const double* __restrict__ A, const double* __restrict__ coefK,
-                                                     double* __restrict__ zb, const int* __restrict__ active) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= E * R) return;
-  const int64_t K = t / R;
-  const int r = (int)(t - K * R);
-  if (active && !active[r]) return;
-  double w[NL];
-#pragma unroll
-  for (int j = 0; j < NL; ++j) {
-    const int32_t i = l2gT[(int64_t)j * E + K];
-    double v = x[(int64_t)i * R + r];
-    if (SCALE_IN) v *= invd[i];
-    w[j] = v;
-  }
-  const double s = coefK[K];
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) acc = fma(A[i * NL + j], w[j], acc);
-    zb[((int64_t)i * E + K) * R + r] = s * acc;
-  }
-}
-
-// Per-element packed symmetric matrix (lower triangle, SoA [q][E]):
-// z_K = A_K w_K with w_K = x[pi_K], in precision T.
-template <int NL, typename T, typename ZT>
-__global__ void __launch_bounds__(kBS) k_packed_elem(int64_t E, int R, const int32_t* __restrict__ l2gT,
-                                                     const double* __restrict__ x, const T* __restrict__ ap,
-                                                     ZT* __restrict__ zb, const int* __restrict__ active) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= E * R) return;
-  const int64_t K = t / R;
-  const int r = (int)(t - K * R);
-  if (active && !active[r]) return;
-  T w[NL], z[NL];
-#pragma unroll
-  for (int j = 0; j < NL; ++j) {
-    w[j] = (T)x[(int64_t)l2gT[(int64_t)j * E + K] * R + r];
-    z[j] = (T)0;
-  }
-  int q = 0;
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-#pragma unroll
-    for (int j = 0; j <= i; ++j, ++q) {
-      const T a = ap[(int64_t)q * E + K];
-      z[i] = fma(a, w[j], z[i]);
-      if (j < i) z[j] = fma(a, w[i], z[j]);
+template <int NL, int FORM, typename T, typename ZT>
+__global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* __restrict__ l2g, InArgs in,
+                                              const double* __restrict__ dscale, const double* __restrict__ A,
+                                              const double* __restrict__ coefK, const T* __restrict__ ap, int nsym,
+                                              ZT* __restrict__ zb) {
+  constexpr int RPW = (NL + 3) / 4;   // rows per wave
+  __shared__ T w[NL * kWS];
+  __shared__ double coef_s[256];      // per-column coefficient of x2 (alpha or beta)
+  __shared__ int act_s[256];          // per-column activity
+  __shared__ double red_s[kEB];
+  if (in.apart) {
+    alpha_prologue(in.apart, in.anb, R, in.sc, in.ic, coef_s, act_s, red_s);
+    for (int c = threadIdx.x; c < R; c += kEB) coef_s[c] *= in.sign;
+    __syncthreads();
+  } else {
+    for (int c = threadIdx.x; c < R; c += kEB) {
+      act_s[c] = in.active ? in.active[c] : 1;
+      coef_s[c] = in.cvec ? in.sign * in.cvec[c] : 0.0;
     }
+    __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < NL; ++i) zb[((int64_t)i * E + K) * R + r] = (ZT)z[i];
-}
-
-// Metric reference tables (Piola): z_K = sum_p G_p,K S_p w_K, float64.
-template <int NL>
-__global__ void __launch_bounds__(kBS) k_metric_elem(int64_t E, int R, int nsym, const int32_t* __restrict__ l2gT,
-                                                     const double* __restrict__ x, const double* __restrict__ S,
-                                                     const double* __restrict__ Gsoa, double* __restrict__ zb,
-                                                     const int* __restrict__ active) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= E * R) return;
-  const int64_t K = t / R;
-  const int r = (int)(t - K * R);
-  if (active && !active[r]) return;
-  double w[NL], g[6];
-#pragma unroll
-  for (int j = 0; j < NL; ++j) w[j] = x[(int64_t)l2gT[(int64_t)j * E + K] * R + r];
-  for (int p = 0; p < 6; ++p) g[p] = p < nsym ? Gsoa[(int64_t)p * E + K] : 0.0;
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    double acc = 0.0;
-    for (int p = 0; p < nsym; ++p) {
-      double sp = 0.0;
-#pragma unroll
-      for (int j = 0; j < NL; ++j) sp = fma(S[(p * NL + i) * NL + j], w[j], sp);
-      acc = fma(g[p], sp, acc);
-    }
-    zb[((int64_t)i * E + K) * R + r] = acc;
+  {
+    bool any = false;
+    for (int c = 0; c < R; ++c) any = any || act_s[c];
+    if (!any) return;   // uniform across the grid
   }
-}
-
-// Generic element pass for any n_loc: one wavefront per (element, column);
-// the gathered vector is staged in LDS, lane i computes row i.
-// kind 0: shared reference (A = ref, coefficient coefK[K], optional D^-1 in);
-// kind 1: packed per-element (T); kind 2: metric tables.
-template <typename T, typename ZT>
-__global__ void __launch_bounds__(64) k_generic_elem(int kind, int64_t E, int R, int nl, int nsym,
-                                                     const int32_t* __restrict__ l2gT, const double* __restrict__ x,
-                                                     const double* __restrict__ invd, const double* __restrict__ A,
-                                                     const double* __restrict__ coefK, const T* __restrict__ ap,
-                                                     const double* __restrict__ Gsoa, ZT* __restrict__ zb,
-                                                     const int* __restrict__ active) {
-  __shared__ double w[96];
-  const int64_t t = blockIdx.x;
-  const int64_t K = t / R;
-  const int r = (int)(t - K * R);
-  if (active && !active[r]) return;
-  for (int j = threadIdx.x; j < nl; j += 64) {
-    const int32_t i = l2gT[(int64_t)j * E + K];
-    double v = x[(int64_t)i * R + r];
-    if (kind == 0 && invd) v *= invd[i];
-    w[j] = v;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nl; i += 64) {
-    double acc = 0.0;
-    if (kind == 0) {
-      for (int j = 0; j < nl; ++j) acc = fma(A[i * nl + j], w[j], acc);
-      acc *= coefK[K];
-    } else if (kind == 1) {
-      for (int j = 0; j < nl; ++j) {
-        const int a = i > j ? i : j, b = i > j ? j : i;
-        acc += (double)ap[((int64_t)a * (a + 1) / 2 + b) * E + K] * (double)(T)w[j];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t K0 = (int64_t)blockIdx.x * kEPB;
+  const int ne = (int)((E - K0) < kEPB ? (E - K0) : kEPB);
+  const int64_t K = K0 + lane;
+  const bool on = lane < ne;
+  const double ck = (FORM == FORM_SCALED && on) ? coefK[K] : 1.0;
+  for (int col = 0; col < R; ++col) {
+    if (!act_s[col]) continue;   // uniform
+    const double cf = coef_s[col];
+    {
+      // all of this thread's map entries, then all gathers, then the LDS stores
+      constexpr int GPT = (NL * kEPB + kEB - 1) / kEB;
+      const int nq = ne * NL;
+      int32_t gi[GPT];
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) {
+        const int q = tid + u * kEB;
+        gi[u] = q < nq ? l2g[K0 * NL + q] : 0;
       }
-    } else {
-      for (int p = 0; p < nsym; ++p) {
-        double sp = 0.0;
-        for (int j = 0; j < nl; ++j) sp = fma(A[((int64_t)p * nl + i) * nl + j], w[j], sp);
-        acc = fma(Gsoa[(int64_t)p * E + K], sp, acc);
+      double v[GPT];
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) {
+        const int q = tid + u * kEB;
+        double t = 0.0;
+        if (q < nq) {
+          t = in.x[(int64_t)gi[u] * R + col];
+          if (in.x2) t = fma(cf, in.x2[(int64_t)gi[u] * R + col], t);
+          if (dscale) t *= dscale[gi[u]];
+        }
+        v[u] = t;
+      }
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) {
+        const int q = tid + u * kEB;
+        if (q < nq) {
+          const int e = q / NL, j = q - e * NL;
+          w[j * kWS + e] = (T)v[u];
+        }
       }
     }
-    zb[((int64_t)i * E + K) * R + r] = (ZT)acc;
+    __syncthreads();
+    if (on) {
+      // rows past n_loc (last wave, n_loc not a multiple of 4) read row n_loc-1
+      // and are not stored, so the product loops carry no branches
+      int row[RPW];
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) row[k] = (wv + 4 * k) < NL ? (wv + 4 * k) : NL - 1;
+      T acc[RPW];
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) acc[k] = (T)0;
+      if (FORM == FORM_METRIC) {
+        for (int p = 0; p < nsym; ++p) {
+          T t[RPW];
+#pragma unroll
+          for (int k = 0; k < RPW; ++k) t[k] = (T)0;
+          const double* Sp = A + (int64_t)p * NL * NL;
+#pragma unroll
+          for (int j = 0; j < NL; ++j) {
+            const T wj = w[j * kWS + lane];
+#pragma unroll
+            for (int k = 0; k < RPW; ++k) t[k] = fma((T)Sp[row[k] * NL + j], wj, t[k]);
+          }
+          const T gp = (T)coefK[(int64_t)p * E + K];
+#pragma unroll
+          for (int k = 0; k < RPW; ++k) acc[k] = fma(gp, t[k], acc[k]);
+        }
+      } else if (FORM == FORM_SCALED) {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+          const T wj = w[j * kWS + lane];
+#pragma unroll
+          for (int k = 0; k < RPW; ++k) acc[k] = fma((T)A[row[k] * NL + j], wj, acc[k]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+          const T wj = w[j * kWS + lane];
+#pragma unroll
+          for (int k = 0; k < RPW; ++k) acc[k] = fma(ap[(int64_t)packed_index(row[k], j) * E + K], wj, acc[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) {
+        const int i = wv + 4 * k;
+        if (i < NL) {
+          T v = acc[k];
+          if (FORM == FORM_SCALED) v *= (T)ck;
+          zb[((int64_t)i * E + K) * R + col] = (ZT)v;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// reduce pass with optional fused dot product
+// reduce pass, optionally fused with a CG update
 // ---------------------------------------------------------------------------
-template <typename ZT>
-__global__ void __launch_bounds__(kBS) k_reduce(int64_t n, int R, const int32_t* __restrict__ rowptr,
+// One work-group per row chunk: up to kChunkRows consecutive conforming DOFs
+// and their broken copies (at most kChunkCap): all threads load the chunk's
+// slot list and then one broken value per copy into LDS (independent loads,
+// so long rows do not serialise); each thread then sums its rows' copies from
+// LDS in transpose-map order.
+constexpr int kChunkRows = 512;
+constexpr int kChunkCap = 2048;
+constexpr int kRowsPerThread = kChunkRows / kBS;
+
+template <typename ZT, int OUT>
+__global__ void __launch_bounds__(kBS) k_reduce(int R, const int32_t* __restrict__ chunk,
+                                                const int32_t* __restrict__ rowptr,
                                                 const int32_t* __restrict__ slot, const ZT* __restrict__ zb,
                                                 const double* __restrict__ scale, double* __restrict__ y,
                                                 const double* __restrict__ dotv, double* __restrict__ partial,
-                                                const int* __restrict__ active) {
-  __shared__ double sh[kBS];
-  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;   // a multiple of R
-  const int r = (int)(t0 % R);
-  double dot = 0.0;
-  if (!active || active[r]) {
-    for (int64_t t = t0; t < n * R; t += stride) {
-      const int64_t i = t / R;
-      double acc = 0.0;
-      const int32_t a = rowptr[i], b = rowptr[i + 1];
-      for (int32_t p = a; p < b; ++p) acc += (double)zb[(int64_t)slot[p] * R + r];
-      if (scale) acc *= scale[i];
-      y[t] = acc;
-      if (dotv) dot = fma(acc, dotv[t], dot);
+                                                CgArgs cg) {
+  __shared__ int32_t sl[kChunkCap];
+  __shared__ double vals[kChunkCap];
+  __shared__ double sh0[kBS], sh1[kBS], sh2[kBS];
+  if (OUT != OUT_PLAIN) {
+    bool any = false;
+    for (int c = 0; c < R; ++c) any = any || cg.ic[I_ACTIVE * R + c];
+    if (!any) return;   // uniform across the grid
+  }
+  const int tid = threadIdx.x;
+  const int32_t i0 = chunk[blockIdx.x], i1 = chunk[blockIdx.x + 1];
+  const int32_t p0 = rowptr[i0], p1 = rowptr[i1];
+  const int cnt = p1 - p0;
+  const bool big = cnt > kChunkCap;   // a single row longer than the chunk capacity
+  constexpr int LPT = kChunkCap / kBS;   // copies per thread
+  if (!big) {
+    int32_t sv[LPT];
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int t = tid + u * kBS;
+      sv[u] = t < cnt ? slot[p0 + t] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int t = tid + u * kBS;
+      if (t < cnt) sl[t] = sv[u];
     }
   }
-  if (!partial) return;
-  sh[threadIdx.x] = dot;
-  block_partials(sh, R, partial);
+  int32_t ra[kRowsPerThread], rb[kRowsPerThread];
+  double scv[kRowsPerThread];
+#pragma unroll
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int32_t i = i0 + tid + k * kBS;
+    const bool own = i < i1;
+    ra[k] = own ? rowptr[i] - p0 : 0;
+    rb[k] = own ? rowptr[i + 1] - p0 : 0;
+    scv[k] = (own && scale) ? scale[i] : 1.0;
+  }
+  __syncthreads();
+  for (int col = 0; col < R; ++col) {
+    const bool act = OUT == OUT_PLAIN ? true : cg.ic[I_ACTIVE * R + col] != 0;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    if (act) {
+      if (!big) {
+        double vv[LPT];
+#pragma unroll
+        for (int u = 0; u < LPT; ++u) {
+          const int t = tid + u * kBS;
+          vv[u] = t < cnt ? (double)zb[(int64_t)sl[t] * R + col] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < LPT; ++u) {
+          const int t = tid + u * kBS;
+          if (t < cnt) vals[t] = vv[u];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        const int32_t i = i0 + tid + k * kBS;
+        if (i >= i1) continue;
+        double acc = 0.0;
+        if (!big)
+          for (int32_t q = ra[k]; q < rb[k]; ++q) acc += vals[q];
+        else
+          for (int32_t q = ra[k]; q < rb[k]; ++q) acc += (double)zb[(int64_t)slot[p0 + q] * R + col];
+        acc *= scv[k];
+        const int64_t t = (int64_t)i * R + col;
+        if (OUT == OUT_PLAIN) {
+          y[t] = acc;
+          if (dotv) d0 = fma(acc, dotv[t], d0);
+        } else if (OUT == OUT_MASS_CG) {
+          // q = M p_new with p_new = z + beta p_old (the element pass used the same p_new)
+          const double pn = fma(cg.sc[S_BETA * R + col], cg.p[t], cg.z[t]);
+          cg.p[t] = pn;
+          cg.q[t] = acc;
+          d0 = fma(pn, acc, d0);
+        } else {
+          // z_new = C r_new with r_new = r - alpha q; x += alpha p
+          const double al = cg.sc[S_ALPHA * R + col];
+          const double rn = fma(-al, cg.q[t], cg.r[t]);
+          cg.x[t] = fma(al, cg.p[t], cg.x[t]);
+          if (cg.flexible) d2 = fma(rn, cg.z[t], d2);
+          cg.z[t] = acc;
+          cg.r[t] = rn;
+          d0 = fma(rn, rn, d0);
+          d1 = fma(rn, acc, d1);
+        }
+      }
+    }
+    // per-column partials of this block (fixed tree order)
+    double* out0 = OUT == OUT_PLAIN ? partial : cg.part0;
+    if (out0 && (OUT != OUT_PLAIN || dotv)) {
+      sh0[tid] = d0;
+      if (OUT == OUT_BRAS_CG) {
+        sh1[tid] = d1;
+        sh2[tid] = d2;
+      }
+      __syncthreads();
+      for (int off = kBS / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+          sh0[tid] += sh0[tid + off];
+          if (OUT == OUT_BRAS_CG) {
+            sh1[tid] += sh1[tid + off];
+            sh2[tid] += sh2[tid + off];
+          }
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        out0[(int64_t)blockIdx.x * R + col] = sh0[0];
+        if (OUT == OUT_BRAS_CG) {
+          cg.part1[(int64_t)blockIdx.x * R + col] = sh1[0];
+          if (cg.flexible) cg.part2[(int64_t)blockIdx.x * R + col] = sh2[0];
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
-// y = s .* x (diagonal scaling) with optional fused dot product y . dotv
+// Diagonal (or identity) preconditioner fused with the CG update:
+// alpha from the p.q partials, r_new = r - alpha q, x += alpha p,
+// z = s .* r_new (s = diag(M)^-1, or 1), partials of r.r, r.z (and r.z_old).
+__global__ void __launch_bounds__(kBS) k_diag_cg(int64_t n, int R, const double* __restrict__ s, CgArgs cg) {
+  __shared__ double sh0[kBS], sh1[kBS], sh2[kBS];
+  __shared__ double coef_s[256];
+  __shared__ int act_s[256];
+  alpha_prologue(cg.apart, cg.anb, R, cg.sc, cg.ic, coef_s, act_s, sh0);
+  {
+    bool any = false;
+    for (int c = 0; c < R; ++c) any = any || act_s[c];
+    if (!any) return;
+  }
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;   // a multiple of R
+  const int col = (int)(t0 % R);
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  if (act_s[col]) {
+    const double alpha = coef_s[col];
+    for (int64_t t = t0; t < n * R; t += stride) {
+      const int64_t i = R == 1 ? t : t / R;
+      const double rn = fma(-alpha, cg.q[t], cg.r[t]);
+      cg.x[t] = fma(alpha, cg.p[t], cg.x[t]);
+      const double zv = s ? rn * s[i] : rn;
+      if (cg.flexible) d2 = fma(rn, cg.z[t], d2);
+      cg.z[t] = zv;
+      cg.r[t] = rn;
+      d0 = fma(rn, rn, d0);
+      d1 = fma(rn, zv, d1);
+    }
+  }
+  sh0[threadIdx.x] = d0;
+  block_partials(sh0, R, cg.part0);
+  sh1[threadIdx.x] = d1;
+  block_partials(sh1, R, cg.part1);
+  if (cg.flexible) {
+    sh2[threadIdx.x] = d2;
+    block_partials(sh2, R, cg.part2);
+  }
+}
+
+// y = s .* x with optional fused dot product y . dotv (plain Jacobi apply)
 __global__ void __launch_bounds__(kBS) k_diag_scale(int64_t n, int R, const double* __restrict__ s,
                                                     const double* __restrict__ x, double* __restrict__ y,
                                                     const double* __restrict__ dotv, double* __restrict__ partial,
@@ -203,7 +368,7 @@ __global__ void __launch_bounds__(kBS) k_diag_scale(int64_t n, int R, const doub
   double dot = 0.0;
   if (!active || active[r]) {
     for (int64_t t = t0; t < n * R; t += stride) {
-      const double v = x[t] * s[t / R];
+      const double v = x[t] * s[R == 1 ? t : t / R];
       y[t] = v;
       if (dotv) dot = fma(v, dotv[t], dot);
     }
@@ -213,181 +378,190 @@ __global__ void __launch_bounds__(kBS) k_diag_scale(int64_t n, int R, const doub
   block_partials(sh, R, partial);
 }
 
-// g_K = -dcoef_K sum_r lam_K,r^T Mhat x_K,r  (density gradient, affine H1)
+// g_K = -dcoef_K sum_r lam_K,r^T Mhat x_K,r  (density gradient, affine H1),
+// one thread per element row, row sums reduced in LDS per element.
 template <int NL>
-__global__ void __launch_bounds__(kBS) k_rho_grad(int64_t E, int R, const int32_t* __restrict__ l2gT,
+__global__ void __launch_bounds__(kEB) k_rho_grad(int64_t E, int R, const int32_t* __restrict__ l2g,
                                                   const double* __restrict__ x, const double* __restrict__ lam,
                                                   const double* __restrict__ Mhat, const double* __restrict__ dcoef,
                                                   double* __restrict__ g) {
-  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (K >= E) return;
-  double tot = 0.0;
-  for (int r = 0; r < R; ++r) {
-    double w[NL];
+  constexpr int EPB = kEB / NL;
+  __shared__ double w[kEB];
+  __shared__ double part[kEB];
+  const int tid = threadIdx.x;
+  const int e = tid / NL, l = tid - e * NL;
+  const bool lane = e < EPB;
+  double a[NL];
+  if (lane) {
 #pragma unroll
-    for (int j = 0; j < NL; ++j) w[j] = x[(int64_t)l2gT[(int64_t)j * E + K] * R + r];
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      double acc = 0.0;
-#pragma unroll
-      for (int j = 0; j < NL; ++j) acc = fma(Mhat[i * NL + j], w[j], acc);
-      tot = fma(lam[(int64_t)l2gT[(int64_t)i * E + K] * R + r], acc, tot);
-    }
+    for (int j = 0; j < NL; ++j) a[j] = Mhat[l * NL + j];
   }
-  g[K] = -dcoef[K] * tot;
-}
-
-__global__ void __launch_bounds__(kBS) k_rho_grad_generic(int64_t E, int R, int nl, const int32_t* __restrict__ l2gT,
-                                                          const double* __restrict__ x, const double* __restrict__ lam,
-                                                          const double* __restrict__ Mhat,
-                                                          const double* __restrict__ dcoef, double* __restrict__ g) {
-  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (K >= E) return;
-  double tot = 0.0;
-  for (int r = 0; r < R; ++r)
-    for (int i = 0; i < nl; ++i) {
-      double acc = 0.0;
-      for (int j = 0; j < nl; ++j) acc += Mhat[i * nl + j] * x[(int64_t)l2gT[(int64_t)j * E + K] * R + r];
-      tot += lam[(int64_t)l2gT[(int64_t)i * E + K] * R + r] * acc;
+  for (int64_t K0 = (int64_t)blockIdx.x * EPB; K0 < E; K0 += (int64_t)gridDim.x * EPB) {
+    const int64_t K = K0 + e;
+    const bool on = lane && K < E;
+    const int32_t gi = on ? l2g[K * NL + l] : 0;
+    double tot = 0.0;
+    for (int r = 0; r < R; ++r) {
+      if (on) w[tid] = x[(int64_t)gi * R + r];
+      __syncthreads();
+      if (on) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) acc = fma(a[j], w[e * NL + j], acc);
+        tot = fma(lam[(int64_t)gi * R + r], acc, tot);
+      }
+      __syncthreads();
     }
-  g[K] = -dcoef[K] * tot;
+    part[tid] = on ? tot : 0.0;
+    __syncthreads();
+    if (on && l == 0) {
+      double s = 0.0;
+      for (int j = 0; j < NL; ++j) s += part[e * NL + j];
+      g[K] = -dcoef[K] * s;
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
-
-int reduce_blocks(Ctx* c, int R) {
+int vector_blocks(Ctx* c, int R) {
   int64_t want = (c->n * R + kBS - 1) / kBS;
-  int64_t nb = want < kMaxReduceBlocks ? want : kMaxReduceBlocks;
+  int64_t nb = want < kMaxVectorBlocks ? want : kMaxVectorBlocks;
   if (nb < 1) nb = 1;
   // grid * kBS must be a multiple of R so that each thread keeps one column
   while (((int64_t)nb * kBS) % R) ++nb;
   return (int)nb;
 }
 
-#define SCALED_CASES(X) X(3) X(4) X(6) X(10) X(15) X(20) X(21) X(28) X(35)
-#define PACKED_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(24)
-#define METRIC_CASES(X) X(3) X(4) X(6) X(8) X(15) X(20)
+#define NL_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(21) X(24) X(28) X(35) X(36) X(45) X(56) X(70) X(84)
 
-static int scaled_elem(Ctx* c, const double* x, bool bras_in, const double* A, const double* coefK, int R,
-                       hipStream_t s, const int* active) {
-  double* zb = (double*)c->zb;
-  const int64_t work = c->E * R;
-#define CASE(N)                                                                                                  \
-  case N:                                                                                                        \
-    if (bras_in)                                                                                                 \
-      k_scaled_elem<N, true><<<nblk(work), kBS, 0, s>>>(c->E, R, c->l2gT, x, c->invd, A, coefK, zb, active);     \
-    else                                                                                                         \
-      k_scaled_elem<N, false><<<nblk(work), kBS, 0, s>>>(c->E, R, c->l2gT, x, c->invd, A, coefK, zb, active);    \
-    break;
-  if (c->variant != 1) {
-    switch (c->nl) {
-      SCALED_CASES(CASE)
-      default:
-        k_generic_elem<double, double><<<(unsigned)work, 64, 0, s>>>(0, c->E, R, c->nl, 0, c->l2gT, x,
-                                                                     bras_in ? c->invd : nullptr, A, coefK, nullptr,
-                                                                     nullptr, zb, active);
-    }
-  } else {
-    k_generic_elem<double, double><<<(unsigned)work, 64, 0, s>>>(0, c->E, R, c->nl, 0, c->l2gT, x,
-                                                                 bras_in ? c->invd : nullptr, A, coefK, nullptr,
-                                                                 nullptr, zb, active);
-  }
-#undef CASE
+template <int NL, int FORM, typename T, typename ZT>
+static int elem_launch(Ctx* c, int R, const InArgs& in, const double* dscale, const double* A, const double* coefK,
+                       const T* ap, ZT* zb, hipStream_t s) {
+  const unsigned nb = (unsigned)((c->E + kEPB - 1) / kEPB);
+  const int nsym = FORM == FORM_METRIC ? c->nsym : 0;
+  k_elem<NL, FORM, T, ZT><<<nb, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, ap, nsym, zb);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
 
-template <typename T, typename ZT>
-static int packed_elem(Ctx* c, const double* x, const T* ap, ZT* zb, int R, hipStream_t s, const int* active) {
-  const int64_t work = c->E * R;
+template <int FORM, typename T, typename ZT>
+static int elem_dispatch(Ctx* c, int R, const InArgs& in, const double* dscale, const double* A,
+                         const double* coefK, const T* ap, ZT* zb, hipStream_t s) {
 #define CASE(N) \
-  case N: k_packed_elem<N, T, ZT><<<nblk(work), kBS, 0, s>>>(c->E, R, c->l2gT, x, ap, zb, active); break;
-  if (c->variant != 1) {
-    switch (c->nl) {
-      PACKED_CASES(CASE)
-      default:
-        k_generic_elem<T, ZT><<<(unsigned)work, 64, 0, s>>>(1, c->E, R, c->nl, 0, c->l2gT, x, nullptr, nullptr,
-                                                            nullptr, ap, nullptr, zb, active);
-    }
-  } else {
-    k_generic_elem<T, ZT><<<(unsigned)work, 64, 0, s>>>(1, c->E, R, c->nl, 0, c->l2gT, x, nullptr, nullptr, nullptr,
-                                                        ap, nullptr, zb, active);
+  case N: return elem_launch<N, FORM, T, ZT>(c, R, in, dscale, A, coefK, ap, zb, s);
+  switch (c->nl) {
+    NL_CASES(CASE)
+    default: return fail(BRAS_EINVAL, "n_loc %d has no element kernel", c->nl);
   }
 #undef CASE
-  BRAS_HIP(hipGetLastError());
-  return BRAS_OK;
 }
 
-static int metric_elem(Ctx* c, const double* x, int R, hipStream_t s, const int* active) {
-  const int64_t work = c->E * R;
+// element pass of the mass operator (float64)
+static int mass_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
   double* zb = (double*)c->zb;
-#define CASE(N)                                                                                                  \
-  case N:                                                                                                        \
-    k_metric_elem<N><<<nblk(work), kBS, 0, s>>>(c->E, R, c->nsym, c->l2gT, x, c->ref, c->coef, zb, active);      \
-    break;
-  if (c->variant != 1) {
-    switch (c->nl) {
-      METRIC_CASES(CASE)
-      default:
-        k_generic_elem<double, double><<<(unsigned)work, 64, 0, s>>>(2, c->E, R, c->nl, c->nsym, c->l2gT, x, nullptr,
-                                                                     c->ref, nullptr, nullptr, c->coef, zb, active);
-    }
-  } else {
-    k_generic_elem<double, double><<<(unsigned)work, 64, 0, s>>>(2, c->E, R, c->nl, c->nsym, c->l2gT, x, nullptr,
-                                                                 c->ref, nullptr, nullptr, c->coef, zb, active);
-  }
-#undef CASE
+  if (c->form == BRAS_ELEM_SCALED_REF)
+    return elem_dispatch<FORM_SCALED, double, double>(c, R, in, nullptr, c->ref, c->coef, nullptr, zb, s);
+  if (c->mpack)
+    return elem_dispatch<FORM_PACKED, double, double>(c, R, in, nullptr, nullptr, nullptr, c->mpack, zb, s);
+  return elem_dispatch<FORM_METRIC, double, double>(c, R, in, nullptr, c->ref, c->coef, nullptr, zb, s);
+}
+
+// element pass of the BRAS operator; reports whether the broken vector is float32
+static int bras_elem(Ctx* c, const InArgs& in, int R, hipStream_t s, bool* zb_float) {
+  *zb_float = false;
+  if (c->form == BRAS_ELEM_SCALED_REF)
+    return elem_dispatch<FORM_SCALED, double, double>(c, R, in, c->invd, c->refinv, c->icoef, nullptr,
+                                                       (double*)c->zb, s);
+  if (c->prec == BRAS_FP64)
+    return elem_dispatch<FORM_PACKED, double, double>(c, R, in, nullptr, nullptr, nullptr, (const double*)c->ainv,
+                                                       (double*)c->zb, s);
+  *zb_float = true;
+  return elem_dispatch<FORM_PACKED, float, float>(c, R, in, nullptr, nullptr, nullptr, (const float*)c->ainv,
+                                                   (float*)c->zb, s);
+}
+
+template <typename ZT, int OUT>
+static int reduce_launch(Ctx* c, const ZT* zb, const double* scale, double* y, int R, hipStream_t s,
+                         const double* dotv, double* partial, const CgArgs& cg) {
+  k_reduce<ZT, OUT><<<(unsigned)c->nchunk, kBS, 0, s>>>(R, c->chunk, c->rowptr, c->slot, zb, scale, y, dotv, partial,
+                                                        cg);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
 
-template <typename ZT>
-static int reduce(Ctx* c, const ZT* zb, const double* scale, double* y, int R, hipStream_t s, const double* dotv,
-                  double* partial, const int* active) {
-  k_reduce<ZT><<<reduce_blocks(c, R), kBS, 0, s>>>(c->n, R, c->rowptr, c->slot, zb, scale, y, dotv, partial, active);
-  BRAS_HIP(hipGetLastError());
-  return BRAS_OK;
+int reduce_blocks(Ctx* c, int R) {
+  (void)R;
+  return c->nchunk;
 }
 
-// The mass pass is float64 throughout (it defines the problem being solved).
 int launch_mass(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
                 const int* active) {
-  int st;
-  double* zb = (double*)c->zb;
-  if (c->form == BRAS_ELEM_SCALED_REF) {
-    if ((st = scaled_elem(c, x, false, c->ref, c->coef, R, s, active))) return st;
-  } else if (c->form == BRAS_ELEM_METRIC_REF) {
-    if ((st = metric_elem(c, x, R, s, active))) return st;
-  } else {
-    if ((st = packed_elem<double, double>(c, x, c->coef, zb, R, s, active))) return st;
-  }
-  return reduce<double>(c, zb, nullptr, y, R, s, dotv, dotpart, active);
+  InArgs in;
+  in.x = x;
+  in.active = active;
+  int st = mass_elem(c, in, R, s);
+  if (st) return st;
+  return reduce_launch<double, OUT_PLAIN>(c, (const double*)c->zb, nullptr, y, R, s, dotv, dotpart, CgArgs());
 }
 
 int launch_bras(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
                 const int* active) {
-  int st;
-  if (c->form == BRAS_ELEM_SCALED_REF) {
-    if ((st = scaled_elem(c, x, true, c->refinv, c->icoef, R, s, active))) return st;
-    return reduce<double>(c, (const double*)c->zb, c->invd, y, R, s, dotv, dotpart, active);
-  }
-  if (c->prec == BRAS_FP64) {
-    if ((st = packed_elem<double, double>(c, x, (const double*)c->ainv, (double*)c->zb, R, s, active))) return st;
-    return reduce<double>(c, (const double*)c->zb, nullptr, y, R, s, dotv, dotpart, active);
-  }
-  if (c->prec == BRAS_FP32) {
-    if ((st = packed_elem<float, float>(c, x, (const float*)c->ainv, (float*)c->zb, R, s, active))) return st;
-    return reduce<float>(c, (const float*)c->zb, nullptr, y, R, s, dotv, dotpart, active);
-  }
-  return launch_bras_bf16(c, x, y, R, s, dotv, dotpart, active);
+  if (c->prec == BRAS_BF16) return launch_bras_bf16(c, x, y, R, s, dotv, dotpart, active);
+  InArgs in;
+  in.x = x;
+  in.active = active;
+  bool zf;
+  int st = bras_elem(c, in, R, s, &zf);
+  if (st) return st;
+  const double* scale = c->form == BRAS_ELEM_SCALED_REF ? c->invd : nullptr;
+  if (zf) return reduce_launch<float, OUT_PLAIN>(c, (const float*)c->zb, scale, y, R, s, dotv, dotpart, CgArgs());
+  return reduce_launch<double, OUT_PLAIN>(c, (const double*)c->zb, scale, y, R, s, dotv, dotpart, CgArgs());
 }
 
 int launch_jacobi(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
                   const int* active) {
-  k_diag_scale<<<reduce_blocks(c, R), kBS, 0, s>>>(c->n, R, c->invdiag, x, y, dotv, dotpart, active);
+  k_diag_scale<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, c->invdiag, x, y, dotv, dotpart, active);
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+// q = M (z + beta p), p <- z + beta p, alpha = rho / p.q
+int cg_mass_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
+  InArgs in;
+  in.x = cg.z;
+  in.x2 = cg.p;
+  in.cvec = cg.sc + S_BETA * R;
+  in.sign = 1.0;
+  in.active = cg.ic + I_ACTIVE * R;
+  int st = mass_elem(c, in, R, s);
+  if (st) return st;
+  return reduce_launch<double, OUT_MASS_CG>(c, (const double*)c->zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
+}
+
+// r <- r - alpha q, x <- x + alpha p, z = C r, dot products, convergence, beta
+int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
+  if (pc == BRAS_PC_BRAS && c->prec != BRAS_BF16) {
+    InArgs in;
+    in.x = cg.r;
+    in.x2 = cg.q;
+    in.sign = -1.0;
+    in.apart = cg.apart;   // alpha from the p.q partials, in the element pass's prologue
+    in.anb = cg.anb;
+    in.sc = cg.sc;
+    in.ic = cg.ic;
+    bool zf;
+    int st = bras_elem(c, in, R, s, &zf);
+    if (st) return st;
+    const double* scale = c->form == BRAS_ELEM_SCALED_REF ? c->invd : nullptr;
+    if (zf)
+      return reduce_launch<float, OUT_BRAS_CG>(c, (const float*)c->zb, scale, nullptr, R, s, nullptr, nullptr, cg);
+    return reduce_launch<double, OUT_BRAS_CG>(c, (const double*)c->zb, scale, nullptr, R, s, nullptr, nullptr, cg);
+  }
+  if (pc == BRAS_PC_BRAS) return cg_bras_bf16_step(c, cg, R, s);
+  k_diag_cg<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, pc == BRAS_PC_JACOBI ? c->invdiag : nullptr, cg);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
@@ -434,13 +608,17 @@ extern "C" int bras_rho_grad(bras_handle h, const double* x_d, const double* lam
   BRAS_CHECK(c->form == BRAS_ELEM_SCALED_REF, "bras_rho_grad needs the SCALED_REF form");
   BRAS_CHECK(nrhs >= 1 && nrhs <= c->max_rhs, "nrhs %d outside 1..max_rhs", nrhs);
   hipStream_t s = (hipStream_t)stream;
-  const unsigned nb = (unsigned)((c->E + kBS - 1) / kBS);
-#define CASE(N) \
-  case N: k_rho_grad<N><<<nb, kBS, 0, s>>>(c->E, nrhs, c->l2gT, x_d, lam_d, c->ref, dcoef_d, g_d); break;
+#define CASE(N)                                                                                          \
+  case N: {                                                                                              \
+    constexpr int EPB = kEB / N;                                                                         \
+    const int64_t groups = (c->E + EPB - 1) / EPB;                                                      \
+    const unsigned nb = (unsigned)(groups < 65536 ? groups : 65536);                                     \
+    k_rho_grad<N><<<nb, kEB, 0, s>>>(c->E, nrhs, c->l2g, x_d, lam_d, c->ref, dcoef_d, g_d);              \
+    break;                                                                                               \
+  }
   switch (c->nl) {
-    SCALED_CASES(CASE)
-    default:
-      k_rho_grad_generic<<<nb, kBS, 0, s>>>(c->E, nrhs, c->nl, c->l2gT, x_d, lam_d, c->ref, dcoef_d, g_d);
+    NL_CASES(CASE)
+    default: return fail(BRAS_EINVAL, "n_loc %d has no gradient kernel", c->nl);
   }
 #undef CASE
   BRAS_HIP(hipGetLastError());

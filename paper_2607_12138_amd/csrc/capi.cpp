@@ -89,7 +89,7 @@ extern "C" int bras_export(bras_handle h, int what, void* dst_d, void* stream) {
       BRAS_HIP(hipMemcpyAsync(in.data(), c->slot, sizeof(int32_t) * c->nbr, hipMemcpyDeviceToHost, s));
       BRAS_HIP(hipStreamSynchronize(s));
       for (int64_t p = 0; p < c->nbr; ++p) {
-        int64_t l = in[p] / c->E, K = in[p] % c->E;
+        const int64_t l = in[p] / c->E, K = in[p] - l * c->E;
         out[p] = K * c->nl + l;
       }
       BRAS_HIP(hipMemcpyAsync(dst_d, out.data(), sizeof(int64_t) * c->nbr, hipMemcpyHostToDevice, s));

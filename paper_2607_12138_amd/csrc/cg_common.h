@@ -1,0 +1,180 @@
+// Device-side CG state shared by the operator passes and the CG driver.
+//
+// Scalars of every column live in device memory (sc: float64 [S_NSC][R],
+// ic: int [I_NIC][R]).  Every dot product is written as per-block partials
+// [blocks][R] by the pass that produces its terms and summed in block order
+// by the next kernel (a kernel boundary separates writers and readers), so
+// results are bitwise reproducible and no atomics are involved.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bras {
+
+enum { S_RZ = 0, S_R0, S_TARGET, S_ALPHA, S_BETA, S_RZOLD, S_RELRES, S_RR, S_NSC };
+enum { I_ACTIVE = 0, I_ITERS, I_STATUS, I_NIC };
+enum { ST_RUN = 0, ST_OK = 1, ST_NOCONV = 2, ST_BREAK = 3 };
+
+// Input of an element pass: w = x + sign * c_r * x2 (x2 optional), where c_r
+// is cvec[r], or, when apart is set, alpha_r = rho_r / (sum of the p.q
+// partials apart[anb][R]) computed in the pass's own prologue (block 0 stores
+// alpha and any breakdown in sc / ic for the kernels that follow).
+struct InArgs {
+  const double* x = nullptr;
+  const double* x2 = nullptr;
+  const double* cvec = nullptr;
+  double sign = 0.0;
+  const int* active = nullptr;   // per-column flags (nullptr: all columns)
+  const double* apart = nullptr;
+  int anb = 0;
+  double* sc = nullptr;
+  int* ic = nullptr;
+};
+
+// Buffers and scalars of a fused CG pass.
+struct CgArgs {
+  double *x = nullptr, *r = nullptr, *p = nullptr, *z = nullptr, *q = nullptr;
+  double* sc = nullptr;
+  int* ic = nullptr;
+  double *part0 = nullptr, *part1 = nullptr, *part2 = nullptr;
+  const double* apart = nullptr;  // p.q partials for the alpha prologue
+  int anb = 0;
+  int flexible = 0;
+  int maxit = 0;
+};
+
+// Fixed-order sum of partial[b*R + col], b < nb, by one block.
+__device__ inline double block_sum(const double* partial, int nb, int R, int col, double* sh) {
+  // loads in batches of 8 per thread (independent), summed in index order
+  double s = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += 8 * (int)blockDim.x) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + (int)threadIdx.x + u * (int)blockDim.x;
+      v[u] = b < nb ? partial[(int64_t)b * R + col] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double v = sh[0];
+  __syncthreads();
+  return v;
+}
+
+// Three fixed-order sums at once (c may be null): one pass over the partials.
+// sh must hold 3 * blockDim.x doubles.
+__device__ inline void block_sum3(const double* a, const double* b, const double* c, int nb, int R, int col,
+                                  double* sh, double* ra, double* rb, double* rc) {
+  double sa = 0.0, sb = 0.0, scv = 0.0;
+  for (int k0 = 0; k0 < nb; k0 += 4 * (int)blockDim.x) {
+    double va[4], vb[4], vc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + (int)threadIdx.x + u * (int)blockDim.x;
+      const bool ok = k < nb;
+      va[u] = ok ? a[(int64_t)k * R + col] : 0.0;
+      vb[u] = ok ? b[(int64_t)k * R + col] : 0.0;
+      vc[u] = (ok && c) ? c[(int64_t)k * R + col] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sa += va[u];
+      sb += vb[u];
+      scv += vc[u];
+    }
+  }
+  // three trees side by side in sh[0..3*blockDim)
+  const int bs = blockDim.x, t = threadIdx.x;
+  sh[t] = sa;
+  sh[bs + t] = sb;
+  sh[2 * bs + t] = scv;
+  __syncthreads();
+  for (int off = bs / 2; off > 0; off >>= 1) {
+    if (t < off) {
+      sh[t] += sh[t + off];
+      sh[bs + t] += sh[bs + t + off];
+      sh[2 * bs + t] += sh[2 * bs + t + off];
+    }
+    __syncthreads();
+  }
+  *ra = sh[0];
+  *rb = sh[bs];
+  *rc = c ? sh[2 * bs] : 0.0;
+  __syncthreads();
+}
+
+// alpha_r = rho_r / p.q for every column, into coef[R] (0 for stopped
+// columns) and act[R]; block 0 records alpha and breakdowns.  Every block
+// derives the same values from the same partials.
+__device__ inline void alpha_prologue(const double* apart, int anb, int R, double* sc, int* ic, double* coef,
+                                      int* act, double* sh) {
+  for (int col = 0; col < R; ++col) {
+    const int a0 = ic[I_ACTIVE * R + col];
+    double pq = 0.0;
+    if (a0) pq = block_sum(apart, anb, R, col, sh);
+    if (threadIdx.x == 0) {
+      if (!a0) {
+        coef[col] = 0.0;
+        act[col] = 0;
+      } else if (!(pq > 0.0) || !isfinite(pq)) {
+        coef[col] = 0.0;
+        act[col] = 0;
+        if (blockIdx.x == 0) {
+          ic[I_ACTIVE * R + col] = 0;
+          ic[I_STATUS * R + col] = ST_BREAK;
+        }
+      } else {
+        const double a = sc[S_RZ * R + col] / pq;
+        coef[col] = a;
+        act[col] = 1;
+        if (blockIdx.x == 0) sc[S_ALPHA * R + col] = a;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Convergence test on the updated recursive residual, then beta and rho
+// (one block, after the residual / preconditioner pass).
+__device__ inline void finish_iteration(const double* part0, const double* part1, const double* part2, int nb,
+                                        int R, double* sc, int* ic, int flexible, int maxit, double* sh) {
+  for (int col = 0; col < R; ++col) {
+    if (!ic[I_ACTIVE * R + col]) continue;
+    double rr, rz, rzo;
+    block_sum3(part0, part1, flexible ? part2 : nullptr, nb, R, col, sh, &rr, &rz, &rzo);
+    if (threadIdx.x == 0) {
+      const int it = ic[I_ITERS * R + col] + 1;
+      ic[I_ITERS * R + col] = it;
+      const double nrm = sqrt(rr);
+      sc[S_RR * R + col] = rr;
+      sc[S_RELRES * R + col] = nrm / sc[S_R0 * R + col];
+      const double old = sc[S_RZ * R + col];
+      if (!isfinite(nrm)) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
+      } else if (nrm <= sc[S_TARGET * R + col]) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_OK;
+      } else if (it >= maxit) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_NOCONV;
+      } else if (!(rz > 0.0) || !isfinite(rz)) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
+      } else {
+        sc[S_BETA * R + col] = flexible ? (rz - rzo) / old : rz / old;
+        sc[S_RZ * R + col] = rz;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace bras

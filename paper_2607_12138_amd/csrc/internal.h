@@ -33,8 +33,9 @@ int element_counts(int family, int dim, int degree, int* n_loc, int counts[4]);
 int nsym_of(int dim);
 
 // ---- device state ---------------------------------------------------------
-// Broken vectors live in "element-fastest" order: slot (K, l) is at l*E + K, so
-// a thread owning element K touches consecutive addresses across a wavefront.
+// Broken vectors (and every per-element table) are stored local-index-major:
+// slot (K, l) is at l*E + K (times nrhs columns, column fastest), so the 64
+// lanes of a wavefront, one element each, touch consecutive addresses.
 
 struct CgState;   // pcg.hip
 
@@ -49,20 +50,23 @@ struct Ctx {
   int64_t last_restarts = 0;
 
   // maps
-  int32_t* l2gT = nullptr;   // [nl][E]
+  int32_t* l2g = nullptr;    // [E][nl]
   int32_t* mult = nullptr;   // [n]
   double* invd = nullptr;    // [n]
   int32_t* rowptr = nullptr; // [n+1]
-  int32_t* slot = nullptr;   // [nbr] internal broken index l*E + K, rows ascending by K*nl + l
+  int32_t* chunk = nullptr;  // [nchunk+1] first DOF of each reduce chunk (<= 512 rows, <= 2048 copies)
+  int64_t nchunk = 0;
+  int32_t* slot = nullptr;   // [nbr] internal index l*E + K of each copy, rows ordered by K*nl + l
 
   // element data
   double* ref = nullptr;     // SCALED_REF: Mhat [nl*nl]; METRIC_REF: S [nsym][nl*nl]
   double* refinv = nullptr;  // SCALED_REF: Mhat^-1 [nl*nl]
-  double* coef = nullptr;    // SCALED_REF: c_K [E]; METRIC_REF: G [nsym][E]; EXPLICIT: packed M_K [npack][E]
+  double* coef = nullptr;    // SCALED_REF: c_K [E]; METRIC_REF: G [nsym][E]
   double* icoef = nullptr;   // SCALED_REF: 1 / c_K [E]
   void* ainv = nullptr;      // METRIC/EXPLICIT: folded inverse, packed lower [npack][E] in prec,
-                             // or (BF16) the Gram factor in MFMA tile layout
+                             // or (BF16) the Gram factor
   size_t ainv_bytes = 0;
+  double* mpack = nullptr;   // packed float64 M_K [npack][E] for the mass pass (EXPLICIT, or METRIC with large n_loc)
   double* diag = nullptr;    // diag(M) [n]
   double* invdiag = nullptr; // [n]
 
@@ -87,8 +91,15 @@ int launch_jacobi(Ctx* c, const double* x, double* y, int nrhs, hipStream_t s, c
                   const int* active);
 int launch_bras_bf16(Ctx* c, const double* x, double* y, int nrhs, hipStream_t s, const double* dotv,
                      double* dotpart, const int* active);
-int reduce_blocks(Ctx* c, int nrhs);
+int reduce_blocks(Ctx* c, int nrhs);   // blocks (= partials per column) of a reduce pass
+int vector_blocks(Ctx* c, int nrhs);   // blocks of a grid-stride vector pass (grid * 256 % nrhs == 0)
 void cg_free(Ctx* c);
+
+// Fused CG passes (apply.hip, bf16.hip): see cg_common.h for CgArgs.
+struct CgArgs;
+int cg_mass_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
+int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int nrhs, hipStream_t s);
+int cg_bras_bf16_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
 
 // setup internals (setup.hip)
 int element_setup(Ctx* c, const double* elem_d, hipStream_t s);

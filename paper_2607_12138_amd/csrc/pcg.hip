@@ -1,20 +1,27 @@
 // Preconditioned conjugate gradients (Section 3), one independent CG per
 // column, entirely on the device:
 //
-//   x = x0; r = b - M x; z = C r; p = z; rho = r.z
-//   repeat: q = M p; alpha = rho / p.q; x += alpha p; r -= alpha q;
-//           stop when ||r|| <= rtol ||r_0|| (or maxit products M p);
-//           z = C r; rho' = r.z; beta = rho'/rho; p = z + beta p; rho = rho'
+//   x = x0; r = b - M x; z = C r; p = 0; beta = 0; rho = r.z
+//   repeat: p = z + beta p; q = M p; alpha = rho / p.q;
+//           x += alpha p; r -= alpha q; stop when ||r|| <= rtol ||r_0||
+//           (or after maxit products M p); z = C r; rho' = r.z;
+//           beta = rho'/rho; rho = rho'
 //
-// alpha, beta, rho and the convergence flags live in device memory; every
-// dot product is a fixed-order two-stage reduction (per-block partials from
-// the producing kernel, then one block that sums them), so results are
-// bitwise reproducible.  Iterations are captured into hipGraphs of 1, 2, 4,
-// 8, 16 and 32 iterations; columns that have stopped are skipped by every
-// kernel, and the host reads the flags only between graph launches.
-// When the stored BRAS inverses are FP32/BF16 the flexible
-// beta = r_new.(z_new - z_old)/rho_old is used and, at exit, CG restarts
-// from x while the true residual is above the tolerance.
+// Each iteration is two fused operator passes (apply.hip):
+//   mass pass    element pass on z + beta p, reduce pass writes q and the new
+//                p and finishes alpha = rho / p.q in its last work-group;
+//   precond pass element pass on r - alpha q (BRAS), reduce pass updates
+//                x and r, writes z and finishes ||r||, the stopping test,
+//                beta and rho in its last work-group (Jacobi / none: one
+//                vector pass).
+// Scalars and convergence flags stay in device memory; every dot product is
+// a fixed-order two-stage reduction, so results are bitwise reproducible.
+// Iterations are captured into hipGraphs of 1, 2, 4, 8, 16 and 32
+// iterations; columns that have stopped are skipped by every kernel, and the
+// host reads the flags only between graph launches.  When the stored BRAS
+// inverses are FP32/BF16 the flexible beta = r_new.(z_new - z_old)/rho_old
+// is used and, at exit, CG restarts from x while the true residual is above
+// the tolerance.
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -22,22 +29,20 @@
 
 #include "internal.h"
 #include "block_reduce.h"
+#include "cg_common.h"
 
 namespace bras {
 
 constexpr int kBS = 256;
 constexpr int kNumGraphs = 6;   // 1, 2, 4, 8, 16, 32 iterations
 
-enum { S_RZ = 0, S_R0, S_TARGET, S_ALPHA, S_BETA, S_RZOLD, S_RELRES, S_RR, S_NSC };
-enum { I_ACTIVE = 0, I_ITERS, I_STATUS, I_NIC };
-enum { ST_RUN = 0, ST_OK = 1, ST_NOCONV = 2, ST_BREAK = 3 };
 
 struct CgState {
   int R = 0;
   double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double* sc = nullptr;      // [S_NSC][R]
   int* ic = nullptr;         // [I_NIC][R]
-  double* part[3] = {nullptr, nullptr, nullptr};   // partials [blocks][R]
+  double* part[4] = {nullptr, nullptr, nullptr, nullptr};   // partials [blocks][R]: r.r, r.z, r.z_old, p.q
   int* ic_host = nullptr;    // pinned copy of ic
   double* sc_host = nullptr;
   struct Key {
@@ -50,21 +55,6 @@ struct CgState {
   };
   std::map<Key, std::vector<hipGraphExec_t>> graphs;
 };
-
-// Fixed-order sum of partial[b*R + col] over b < nb by one block.
-__device__ double block_sum(const double* __restrict__ partial, int nb, int R, int col, double* sh) {
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[(int64_t)b * R + col];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-    __syncthreads();
-  }
-  double v = sh[0];
-  __syncthreads();
-  return v;
-}
 
 // r = b - q (q = M x), partial r.r
 __global__ void __launch_bounds__(kBS) k_residual(int64_t n, int R, const double* __restrict__ b,
@@ -121,6 +111,7 @@ __global__ void k_fin_rz(int nb, int R, const double* __restrict__ part, double*
     const double rz = block_sum(part, nb, R, col, sh);
     if (threadIdx.x == 0 && ic[I_ACTIVE * R + col]) {
       sc[S_RZ * R + col] = rz;
+      sc[S_BETA * R + col] = 0.0;
       if (!(rz > 0.0) || !isfinite(rz)) {
         ic[I_ACTIVE * R + col] = 0;
         ic[I_STATUS * R + col] = ST_BREAK;
@@ -129,120 +120,18 @@ __global__ void k_fin_rz(int nb, int R, const double* __restrict__ part, double*
   }
 }
 
-__global__ void __launch_bounds__(kBS) k_copy_active(int64_t n, int R, const double* __restrict__ src,
-                                                     double* __restrict__ dst, const int* __restrict__ active) {
+__global__ void __launch_bounds__(kBS) k_zero(int64_t n, double* __restrict__ v) {
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int r = (int)(t0 % R);
-  if (!active[r]) return;
-  for (int64_t t = t0; t < n * R; t += stride) dst[t] = src[t];
+  for (int64_t t = t0; t < n; t += stride) v[t] = 0.0;
 }
 
-// alpha = rho / p.q
-__global__ void k_fin_alpha(int nb, int R, const double* __restrict__ part, double* __restrict__ sc,
-                            int* __restrict__ ic) {
-  __shared__ double sh[kBS];
-  for (int col = 0; col < R; ++col) {
-    if (!ic[I_ACTIVE * R + col]) continue;   // uniform across the block
-    const double pq = block_sum(part, nb, R, col, sh);
-    if (threadIdx.x == 0) {
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_BREAK;
-      } else {
-        sc[S_ALPHA * R + col] = sc[S_RZ * R + col] / pq;
-      }
-    }
-  }
-}
-
-// x += alpha p; r -= alpha q; partials r.r (and r.z_old when flexible)
-__global__ void __launch_bounds__(kBS) k_update_xr(int64_t n, int R, double* __restrict__ x, double* __restrict__ r,
-                                                   const double* __restrict__ p, const double* __restrict__ q,
-                                                   const double* __restrict__ z, const double* __restrict__ sc,
-                                                   const int* __restrict__ ic, double* __restrict__ part_rr,
-                                                   double* __restrict__ part_rz) {
-  __shared__ double sh[kBS];
-  __shared__ double sh2[kBS];
-  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int col = (int)(t0 % R);
-  double d1 = 0.0, d2 = 0.0;
-  if (ic[I_ACTIVE * R + col]) {
-    const double a = sc[S_ALPHA * R + col];
-    for (int64_t t = t0; t < n * R; t += stride) {
-      x[t] = fma(a, p[t], x[t]);
-      const double rv = fma(-a, q[t], r[t]);
-      r[t] = rv;
-      d1 = fma(rv, rv, d1);
-      if (part_rz) d2 = fma(rv, z[t], d2);
-    }
-  }
-  sh[threadIdx.x] = d1;
-  sh2[threadIdx.x] = d2;
-  block_partials(sh, R, part_rr);
-  if (part_rz) block_partials(sh2, R, part_rz);
-}
-
-// convergence test on the recursive residual
-__global__ void k_fin_conv(int nb, int R, const double* __restrict__ part_rr, const double* __restrict__ part_rz,
-                           double* __restrict__ sc, int* __restrict__ ic, int maxit) {
-  __shared__ double sh[kBS];
-  for (int col = 0; col < R; ++col) {
-    if (!ic[I_ACTIVE * R + col]) continue;
-    const double rr = block_sum(part_rr, nb, R, col, sh);
-    const double rzo = part_rz ? block_sum(part_rz, nb, R, col, sh) : 0.0;
-    if (threadIdx.x == 0) {
-      const int it = ic[I_ITERS * R + col] + 1;
-      ic[I_ITERS * R + col] = it;
-      const double nrm = sqrt(rr);
-      sc[S_RR * R + col] = rr;
-      sc[S_RZOLD * R + col] = rzo;
-      sc[S_RELRES * R + col] = nrm / sc[S_R0 * R + col];
-      if (!isfinite(nrm)) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_BREAK;
-      } else if (nrm <= sc[S_TARGET * R + col]) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_OK;
-      } else if (it >= maxit) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_NOCONV;
-      }
-    }
-  }
-}
-
-// beta = rho'/rho (or flexible), rho = rho'
-__global__ void k_fin_beta(int nb, int R, const double* __restrict__ part, double* __restrict__ sc,
-                           int* __restrict__ ic, int flexible) {
-  __shared__ double sh[kBS];
-  for (int col = 0; col < R; ++col) {
-    if (!ic[I_ACTIVE * R + col]) continue;
-    const double rz = block_sum(part, nb, R, col, sh);
-    if (threadIdx.x == 0) {
-      const double old = sc[S_RZ * R + col];
-      if (!(rz > 0.0) || !isfinite(rz)) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_BREAK;
-      } else {
-        sc[S_BETA * R + col] = flexible ? (rz - sc[S_RZOLD * R + col]) / old : rz / old;
-        sc[S_RZ * R + col] = rz;
-      }
-    }
-  }
-}
-
-// p = z + beta p
-__global__ void __launch_bounds__(kBS) k_update_p(int64_t n, int R, double* __restrict__ p,
-                                                  const double* __restrict__ z, const double* __restrict__ sc,
-                                                  const int* __restrict__ ic) {
-  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int col = (int)(t0 % R);
-  if (!ic[I_ACTIVE * R + col]) return;
-  const double be = sc[S_BETA * R + col];
-  for (int64_t t = t0; t < n * R; t += stride) p[t] = fma(be, p[t], z[t]);
+// convergence test, beta and rho after the preconditioner pass of an iteration
+__global__ void k_fin_iter(int nb, int R, const double* __restrict__ p0, const double* __restrict__ p1,
+                           const double* __restrict__ p2, double* __restrict__ sc, int* __restrict__ ic, int flexible,
+                           int maxit) {
+  __shared__ double sh[3 * kBS];
+  finish_iteration(p0, p1, p2, nb, R, sc, ic, flexible, maxit, sh);
 }
 
 // true residual norm at exit: relres = ||b - M x|| / ||r_0||
@@ -262,7 +151,7 @@ void cg_free(Ctx* c) {
   if (!g) return;
   for (auto& kv : g->graphs)
     for (auto ge : kv.second) (void)hipGraphExecDestroy(ge);
-  double* bufs[] = {g->b, g->x, g->r, g->z, g->p, g->q, g->sc, g->part[0], g->part[1], g->part[2]};
+  double* bufs[] = {g->b, g->x, g->r, g->z, g->p, g->q, g->sc, g->part[0], g->part[1], g->part[2], g->part[3]};
   for (double* p : bufs)
     if (p) (void)hipFree(p);
   if (g->ic) (void)hipFree(g->ic);
@@ -285,8 +174,9 @@ static int cg_alloc(Ctx* c, int R) {
   if (hipMalloc((void**)&g->sc, sizeof(double) * S_NSC * R) != hipSuccess ||
       hipMalloc((void**)&g->ic, sizeof(int) * I_NIC * R) != hipSuccess)
     return fail(BRAS_ENOMEM, "CG scalar allocation failed");
-  const int nb = reduce_blocks(c, R);
-  for (int k = 0; k < 3; ++k)
+  const int nb_r = reduce_blocks(c, R), nb_v = vector_blocks(c, R);
+  const int nb = nb_r > nb_v ? nb_r : nb_v;
+  for (int k = 0; k < 4; ++k)
     if (hipMalloc((void**)&g->part[k], sizeof(double) * (size_t)nb * R) != hipSuccess)
       return fail(BRAS_ENOMEM, "CG partial allocation failed");
   if (hipHostMalloc((void**)&g->ic_host, sizeof(int) * I_NIC * R, hipHostMallocDefault) != hipSuccess ||
@@ -316,26 +206,48 @@ static int precond(Ctx* c, int pc, const double* r, double* z, int R, hipStream_
   if (pc == BRAS_PC_BRAS) return launch_bras(c, r, z, R, s, r, part, active);
   if (pc == BRAS_PC_JACOBI) return launch_jacobi(c, r, z, R, s, r, part, active);
   // identity preconditioner: z = r, partial r.r
-  k_identity_dot<<<reduce_blocks(c, R), kBS, 0, s>>>(c->n, R, r, z, part, active);
+  k_identity_dot<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, r, z, part, active);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
+}
+
+// partials per column written by the preconditioner pass (and its start-up apply)
+static int precond_blocks(Ctx* c, int pc, int R) {
+  return pc == BRAS_PC_BRAS && c->prec != BRAS_BF16 ? reduce_blocks(c, R) : vector_blocks(c, R);
+}
+
+static CgArgs cg_args(Ctx* c, int flexible, int maxit) {
+  CgState* g = c->cg;
+  CgArgs a;
+  a.x = g->x;
+  a.r = g->r;
+  a.p = g->p;
+  a.z = g->z;
+  a.q = g->q;
+  a.sc = g->sc;
+  a.ic = g->ic;
+  a.flexible = flexible;
+  a.maxit = maxit;
+  return a;
 }
 
 // One CG iteration (enqueued on s; also used under stream capture).
 static int iteration(Ctx* c, int pc, int flexible, int maxit, hipStream_t s) {
   CgState* g = c->cg;
   const int R = g->R;
-  const int nb = reduce_blocks(c, R);
-  int* active = g->ic + I_ACTIVE * R;
-  int st;
-  if ((st = launch_mass(c, g->p, g->q, R, s, g->p, g->part[0], active))) return st;
-  k_fin_alpha<<<1, kBS, 0, s>>>(nb, R, g->part[0], g->sc, g->ic);
-  k_update_xr<<<nb, kBS, 0, s>>>(c->n, R, g->x, g->r, g->p, g->q, g->z, g->sc, g->ic, g->part[1],
-                                 flexible ? g->part[2] : nullptr);
-  k_fin_conv<<<1, kBS, 0, s>>>(nb, R, g->part[1], flexible ? g->part[2] : nullptr, g->sc, g->ic, maxit);
-  if ((st = precond(c, pc, g->r, g->z, R, s, g->part[0], active))) return st;
-  k_fin_beta<<<1, kBS, 0, s>>>(nb, R, g->part[0], g->sc, g->ic, flexible);
-  k_update_p<<<nb, kBS, 0, s>>>(c->n, R, g->p, g->z, g->sc, g->ic);
+  CgArgs m = cg_args(c, flexible, maxit);
+  m.part0 = g->part[3];                       // p.q partials
+  int st = cg_mass_step(c, m, R, s);
+  if (st) return st;
+  CgArgs pcg = cg_args(c, flexible, maxit);
+  pcg.part0 = g->part[0];                     // r.r
+  pcg.part1 = g->part[1];                     // r.z
+  pcg.part2 = g->part[2];                     // r.z_old (flexible)
+  pcg.apart = g->part[3];
+  pcg.anb = reduce_blocks(c, R);
+  if ((st = cg_precond_step(c, pc, pcg, R, s))) return st;
+  k_fin_iter<<<1, kBS, 0, s>>>(precond_blocks(c, pc, R), R, g->part[0], g->part[1], g->part[2], g->sc, g->ic,
+                               flexible, maxit);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
@@ -343,15 +255,15 @@ static int iteration(Ctx* c, int pc, int flexible, int maxit, hipStream_t s) {
 static int start(Ctx* c, int pc, double rtol, int restart, hipStream_t s) {
   CgState* g = c->cg;
   const int R = g->R;
-  const int nb = reduce_blocks(c, R);
+  const int nbv = vector_blocks(c, R);
   int st;
   if ((st = launch_mass(c, g->x, g->q, R, s, nullptr, nullptr, nullptr))) return st;
-  k_residual<<<nb, kBS, 0, s>>>(c->n, R, g->b, g->q, g->r, g->part[1]);
-  k_fin_init<<<1, kBS, 0, s>>>(nb, R, g->part[1], g->sc, g->ic, rtol, restart);
+  k_residual<<<nbv, kBS, 0, s>>>(c->n, R, g->b, g->q, g->r, g->part[1]);
+  k_fin_init<<<1, kBS, 0, s>>>(nbv, R, g->part[1], g->sc, g->ic, rtol, restart);
   int* active = g->ic + I_ACTIVE * R;
   if ((st = precond(c, pc, g->r, g->z, R, s, g->part[0], active))) return st;
-  k_fin_rz<<<1, kBS, 0, s>>>(nb, R, g->part[0], g->sc, g->ic);
-  k_copy_active<<<nb, kBS, 0, s>>>(c->n, R, g->z, g->p, active);
+  k_fin_rz<<<1, kBS, 0, s>>>(precond_blocks(c, pc, R), R, g->part[0], g->sc, g->ic);
+  k_zero<<<nbv, kBS, 0, s>>>(c->n * R, g->p);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
@@ -424,7 +336,7 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   BRAS_HIP(hipMemcpyAsync(g->b, b_d, vec, hipMemcpyDeviceToDevice, s));
   BRAS_HIP(hipMemcpyAsync(g->x, x_d, vec, hipMemcpyDeviceToDevice, s));
   const int R = nrhs;
-  const int nb = reduce_blocks(c, R);
+  const int nb = vector_blocks(c, R);
   int restarts = 0;
   int restart_mode = 0;
   while (true) {

@@ -87,9 +87,9 @@ __global__ void k_geometry(int family, int dim, const double* __restrict__ X, co
 // ---------------------------------------------------------------------------
 // maps
 // ---------------------------------------------------------------------------
-// Per element: range and distinctness checks, transpose to [nl][E], counts.
+// Per element: range and distinctness checks, copy, counts.
 __global__ void k_map_check(const int32_t* __restrict__ l2g, int64_t E, int nl, int64_t n,
-                            int32_t* __restrict__ l2gT, int32_t* __restrict__ cnt, int* __restrict__ flag) {
+                            int32_t* __restrict__ l2g_out, int32_t* __restrict__ cnt, int* __restrict__ flag) {
   int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (K >= E) return;
   const int32_t* row = l2g + K * nl;
@@ -108,7 +108,7 @@ __global__ void k_map_check(const int32_t* __restrict__ l2g, int64_t E, int nl, 
     return;
   }
   for (int l = 0; l < nl; ++l) {
-    l2gT[(int64_t)l * E + K] = row[l];
+    l2g_out[K * nl + l] = row[l];
     atomicAdd(cnt + row[l], 1);   // integer: exact and order independent
   }
 }
@@ -175,18 +175,17 @@ __global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* 
   out[i] += bsum[i / ((int64_t)kScanBlock * kScanItems)];
 }
 
-__global__ void k_fill_slots(const int32_t* __restrict__ l2gT, int64_t E, int nl, const int32_t* __restrict__ rowptr,
+__global__ void k_fill_slots(const int32_t* __restrict__ l2g, int64_t nbr, const int32_t* __restrict__ rowptr,
                              int32_t* __restrict__ fill, int32_t* __restrict__ key) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= E * nl) return;
-  int64_t l = t / E, K = t % E;
-  int32_t i = l2gT[t];
+  if (t >= nbr) return;
+  int32_t i = l2g[t];
   int32_t pos = rowptr[i] + atomicAdd(fill + i, 1);
-  key[pos] = (int32_t)(K * nl + l);   // canonical broken index
+  key[pos] = (int32_t)t;   // canonical broken index K*nl + l
 }
 
 // Sort each row by canonical broken index K*nl + l, then store the internal
-// element-fastest index l*E + K.
+// local-index-major index l*E + K of each copy.
 __global__ void k_sort_rows(const int32_t* __restrict__ rowptr, int64_t n, int nl, int64_t E,
                             int32_t* __restrict__ key, int32_t* __restrict__ slot) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -202,10 +201,18 @@ __global__ void k_sort_rows(const int32_t* __restrict__ rowptr, int64_t n, int n
     key[q + 1] = v;
   }
   for (int32_t p = a; p < b; ++p) {
-    int32_t k = key[p];
-    int32_t K = k / nl, l = k % nl;
+    const int32_t k = key[p];
+    const int32_t K = k / nl, l = k - K * nl;
     slot[p] = (int32_t)((int64_t)l * E + K);
   }
+}
+
+// AoS [E][nsym] -> SoA [nsym][E]
+__global__ void k_transpose_coef(const double* __restrict__ in, int64_t E, int nsym, double* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= E * nsym) return;
+  int64_t K = t / nsym, p = t % nsym;
+  out[p * E + K] = in[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -222,14 +229,6 @@ __global__ void k_scaled_coef(const double* __restrict__ c, int64_t E, double* _
   }
   coef[K] = v;
   icoef[K] = 1.0 / v;
-}
-
-// AoS [E][nsym] -> SoA [nsym][E]
-__global__ void k_transpose_coef(const double* __restrict__ in, int64_t E, int nsym, double* __restrict__ out) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= E * nsym) return;
-  int64_t K = t / nsym, p = t % nsym;
-  out[p * E + K] = in[t];
 }
 
 // One work-group (one wavefront) per element: form M_K in LDS, Cholesky
@@ -256,7 +255,7 @@ __device__ inline void unpack_lower(int q, int& i, int& j) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl, int nsym,
                                                     const double* __restrict__ S, const double* __restrict__ Gsoa,
-                                                    const double* __restrict__ Mexp, const int32_t* __restrict__ l2gT,
+                                                    const double* __restrict__ Mexp, const int32_t* __restrict__ l2g,
                                                     const double* __restrict__ invd, double* __restrict__ diagb,
                                                     double* __restrict__ mpack, T* __restrict__ out, int gram,
                                                     int* __restrict__ flag) {
@@ -267,10 +266,10 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
   __shared__ int bad;
   const int64_t K = blockIdx.x;
   const int t = threadIdx.x, nt = blockDim.x;
-  const int npk = nl * (nl + 1) / 2;
+  const int npk = nl * (nl + 1) / 2;   // packed lower triangle, stored [q][E]
   if (t == 0) bad = 0;
   if (mode == 0 && t < nsym) g[t] = Gsoa[(int64_t)t * E + K];
-  for (int l = t; l < nl; l += nt) dinv[l] = invd[l2gT[(int64_t)l * E + K]];
+  for (int l = t; l < nl; l += nt) dinv[l] = invd[l2g[K * nl + l]];
   __syncthreads();
   const int nn = nl * nl;
   for (int q = t; q < npk; q += nt) {
@@ -398,8 +397,8 @@ __global__ void k_diag_scaled(const int32_t* __restrict__ rowptr, const int32_t*
   if (i >= n) return;
   double s = 0.0;
   for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-    int64_t idx = slot[p];
-    int64_t l = idx / E, K = idx % E;
+    const int64_t idx = slot[p];
+    const int64_t l = idx / E, K = idx - l * E;
     s += coef[K] * Mhat[l * nl + l];
   }
   diag[i] = s;
@@ -455,7 +454,6 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
   const double* G = nullptr;
   const double* Mexp = nullptr;
   int mode;
-  double* mpack = nullptr;
   if (c->form == BRAS_ELEM_METRIC_REF) {
     k_transpose_coef<<<blocks_for(E * c->nsym, 256), 256, 0, s>>>(elem_d, E, c->nsym, c->coef);
     BRAS_HIP(hipGetLastError());
@@ -464,21 +462,21 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
   } else {
     Mexp = elem_d;
     mode = 1;
-    mpack = c->coef;
   }
+  double* mpack = c->mpack;   // non-null when the mass pass reads packed M_K
   double* diagb = nullptr;
   BRAS_HIP(hipMalloc((void**)&diagb, sizeof(double) * c->nbr));
   size_t lds = sizeof(double) * (nl * nl + 8 + nl);
   const int gram = c->prec == BRAS_BF16 ? 1 : 0;
   if (lds > 64 * 1024) return fail(BRAS_EINVAL, "n_loc %d too large for the element factorisation", nl);
   if (c->prec == BRAS_FP64)
-    k_elem_factor<double><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2gT, c->invd, diagb,
+    k_elem_factor<double><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
                                                         mpack, (double*)c->ainv, 0, c->flag);
   else if (c->prec == BRAS_FP32)
-    k_elem_factor<float><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2gT, c->invd, diagb,
+    k_elem_factor<float><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
                                                        mpack, (float*)c->ainv, 0, c->flag);
   else
-    k_elem_factor<float><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2gT, c->invd, diagb,
+    k_elem_factor<float><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
                                                        mpack, (float*)c->ainv, gram, c->flag);
   BRAS_HIP(hipGetLastError());
   k_diag_broken<<<blocks_for(c->n, 256), 256, 0, s>>>(c->rowptr, c->slot, c->n, diagb, c->diag, c->invdiag);
@@ -493,8 +491,8 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
 
 static void free_ctx(Ctx* c) {
   if (!c) return;
-  void* ptrs[] = {c->l2gT, c->mult, c->invd, c->rowptr, c->slot, c->ref, c->refinv, c->coef, c->icoef, c->ainv,
-                  c->diag, c->invdiag, c->zb, c->partial, c->flag};
+  void* ptrs[] = {c->l2g, c->mult, c->invd, c->rowptr, c->chunk, c->slot, c->ref, c->refinv, c->coef, c->icoef, c->ainv,
+                  c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   cg_free(c);
@@ -574,7 +572,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     delete c;
     return fail(BRAS_EHIP, "hipStreamCreateWithFlags failed");
   }
-  TRY(dalloc(&c->l2gT, c->nbr));
+  TRY(dalloc(&c->l2g, c->nbr));
   TRY(dalloc(&c->mult, n));
   TRY(dalloc(&c->invd, n));
   TRY(dalloc(&c->rowptr, n + 1));
@@ -585,7 +583,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
   // maps
   k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>(c->mult, n, 0);
   if ((st = reset_flag(c, s))) { free_ctx(c); return st; }
-  k_map_check<<<blocks_for(E, 256), 256, 0, s>>>(l2g_d, E, n_loc, n, c->l2gT, c->mult, c->flag);
+  k_map_check<<<blocks_for(E, 256), 256, 0, s>>>(l2g_d, E, n_loc, n, c->l2g, c->mult, c->flag);
   if (hipGetLastError() != hipSuccess) { free_ctx(c); return fail(BRAS_EHIP, "map check launch failed"); }
   int f;
   TRY(read_flag(c, s, &f));
@@ -613,7 +611,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     k_scan_sums<<<1, 64, 0, s>>>(bsum, nb, c->rowptr + n);
     k_scan_add<<<blocks_for(n, 256), 256, 0, s>>>(c->rowptr, n, bsum);
     k_fill_int<<<blocks_for(n, 256), 256, 0, s>>>(fill, n, 0);
-    k_fill_slots<<<blocks_for(c->nbr, 256), 256, 0, s>>>(c->l2gT, E, n_loc, c->rowptr, fill, key);
+    k_fill_slots<<<blocks_for(c->nbr, 256), 256, 0, s>>>(c->l2g, c->nbr, c->rowptr, fill, key);
     k_sort_rows<<<blocks_for(n, 256), 256, 0, s>>>(c->rowptr, n, n_loc, E, key, c->slot);
     hipError_t e = hipGetLastError();
     (void)hipStreamSynchronize(s);
@@ -621,6 +619,34 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     (void)hipFree(fill);
     (void)hipFree(key);
     if (e != hipSuccess) { free_ctx(c); return fail(BRAS_EHIP, "transpose-map kernels failed: %s", hipGetErrorString(e)); }
+  }
+  {
+    // reduce chunks: consecutive rows, at most 512 rows and 2048 broken
+    // copies each (a longer single row gets a chunk of its own)
+    std::vector<int32_t> rp(n + 1);
+    if (hipMemcpy(rp.data(), c->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost) != hipSuccess) {
+      free_ctx(c);
+      return fail(BRAS_EHIP, "copy of the transpose map failed");
+    }
+    std::vector<int32_t> ch;
+    ch.push_back(0);
+    int64_t i = 0;
+    while (i < n) {
+      int rows = 0;
+      int64_t cnt = 0;
+      while (i < n && rows < 512 && (rows == 0 || cnt + (rp[i + 1] - rp[i]) <= 2048)) {
+        cnt += rp[i + 1] - rp[i];
+        ++i;
+        ++rows;
+      }
+      ch.push_back((int32_t)i);
+    }
+    c->nchunk = (int64_t)ch.size() - 1;
+    TRY(dalloc(&c->chunk, ch.size()));
+    if (hipMemcpy(c->chunk, ch.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      free_ctx(c);
+      return fail(BRAS_EHIP, "copy of the reduce chunks failed");
+    }
   }
   // element data
   const int nn = n_loc * n_loc;
@@ -649,8 +675,11 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
         return fail(BRAS_EHIP, "copy of reference tables failed");
       }
       TRY(dalloc(&c->coef, (size_t)c->nsym * E));
+      // the mass pass recomputes M_K from the tables in LDS when they fit,
+      // otherwise it reads a packed float64 copy of M_K made at setup
+      if (sizeof(double) * (size_t)c->nsym * nn > 24 * 1024) TRY(dalloc(&c->mpack, (size_t)npack_of(n_loc) * E));
     } else {
-      TRY(dalloc(&c->coef, (size_t)npack_of(n_loc) * E));
+      TRY(dalloc(&c->mpack, (size_t)npack_of(n_loc) * E));
     }
     size_t esz = apply_prec == BRAS_FP64 ? 8 : 4;
     c->ainv_bytes = esz * (size_t)npack_of(n_loc) * E;
@@ -660,7 +689,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
   // workspace
   size_t zbytes = sizeof(double) * (size_t)c->nbr * max_rhs;
   TRY(dalloc((char**)&c->zb, zbytes));
-  TRY(dalloc(&c->partial, (size_t)4096 * max_rhs * 4));
+  TRY(dalloc(&c->partial, (size_t)(c->nchunk + 1024) * max_rhs));
   if (hipStreamSynchronize(s) != hipSuccess) { free_ctx(c); return fail(BRAS_EHIP, "setup synchronisation failed"); }
 #undef TRY
   *h = (bras_handle)c;
