@@ -114,3 +114,34 @@ class Problem:
     @property
     def n_br(self):
         return self.pi.size
+
+
+def operator_rows(ref, coords, cells, pi, n, rows, x, which, rho=None):
+    """Selected rows of M x ("mass") or M_bras^-1 x ("bras") computed one by one
+    from the element-sum definitions (eqs. M_PMbrP, mass_and_bras_element_sums):
+        (M x)_i        = sum_{(K,l): pi(K,l) = i} (M_K x[pi_K])_l
+        (Mbras^-1 x)_i = d_i^-1 sum_{(K,l): pi(K,l) = i} (M_K^-1 (x/d)[pi_K])_l
+    Only the elements touching the requested rows are formed (for sampled
+    checks at full size).  x is [n] or [n, R]."""
+    from .mesh import jacobians
+    pi = np.asarray(pi)
+    rows = np.asarray(rows)
+    d = np.bincount(pi.ravel(), minlength=n).astype(float)
+    x = np.asarray(x, dtype=float)
+    xs = x / (d if x.ndim == 1 else d[:, None]) if which == "bras" else x
+    flat = pi.ravel()
+    order = np.argsort(flat, kind="stable")
+    starts = np.searchsorted(flat[order], rows, side="left")
+    stops = np.searchsorted(flat[order], rows, side="right")
+    out = np.zeros((len(rows),) + x.shape[1:])
+    for t, (a, b) in enumerate(zip(starts, stops)):
+        for j in order[a:b]:
+            K, l = divmod(int(j), pi.shape[1])
+            sub_rho = None if rho is None else np.asarray(rho)[K:K + 1]
+            MK = element_matrices(ref, coords, cells[K:K + 1], sub_rho)[0]
+            if which == "bras":
+                MK = element_inverses(MK[None])[0]
+            out[t] += MK[l] @ xs[pi[K]]
+        if which == "bras":
+            out[t] /= d[rows[t]]
+    return out

@@ -191,3 +191,19 @@ def test_two_dimensional_curl_and_div_are_rotations():
         kda = spectral.kappa_hat(a.M, sp.diags(1.0 / a.diag))[0]
         kdb = spectral.kappa_hat(b.M, sp.diags(1.0 / b.diag))[0]
         assert abs(ka - kb) < 1e-9 * ka and abs(kda - kdb) < 1e-9 * kda
+
+
+@pytest.mark.parametrize("family,dim,deg,N,R", [("P", 3, 3, 3, 1), ("N1curl", 3, 2, 2, 1), ("RT", 3, 2, 2, 3), ("P", 2, 4, 5, 2)])
+def test_operator_rows_one_by_one(family, dim, deg, N, R):
+    # row-by-row element sums (used for sampled checks at full size) agree with
+    # the assembled matrices
+    ref = fe.reference_element(family, dim, deg)
+    coords, cells = mesh.structured_mesh(dim, N, jitter=0.2, seed=2)
+    rho = workloads.density(len(cells), 3)
+    pr = assembly.Problem(ref, coords, cells, rho=rho)
+    x = workloads.rhs(pr.n, R, 3)
+    rows = workloads.sample(pr.n, 12, 4)
+    for which, A in (("mass", pr.M), ("bras", pr.B)):
+        got = assembly.operator_rows(ref, coords, cells, pr.pi, pr.n, rows, x, which, rho=rho)
+        want = (A @ x)[rows]
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(A @ x))
