@@ -497,6 +497,15 @@ int reduce_blocks(Ctx* c, int R) {
   return c->nchunk;
 }
 
+int reduce_float_plain(Ctx* c, const float* zb, double* y, int R, hipStream_t s, const double* dotv,
+                       double* dotpart) {
+  return reduce_launch<float, OUT_PLAIN>(c, zb, nullptr, y, R, s, dotv, dotpart, CgArgs());
+}
+
+int reduce_float_cg(Ctx* c, const float* zb, int R, hipStream_t s, const CgArgs& cg) {
+  return reduce_launch<float, OUT_BRAS_CG>(c, zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
+}
+
 int launch_mass(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
                 const int* active) {
   InArgs in;

@@ -64,7 +64,7 @@ struct Ctx {
   double* coef = nullptr;    // SCALED_REF: c_K [E]; METRIC_REF: G [nsym][E]
   double* icoef = nullptr;   // SCALED_REF: 1 / c_K [E]
   void* ainv = nullptr;      // METRIC/EXPLICIT: folded inverse, packed lower [npack][E] in prec,
-                             // or (BF16) the Gram factor
+                             // or (BF16) the Gram factor, packed lower, element-major [E][npack]
   size_t ainv_bytes = 0;
   double* mpack = nullptr;   // packed float64 M_K [npack][E] for the mass pass (EXPLICIT, or METRIC with large n_loc)
   double* diag = nullptr;    // diag(M) [n]
@@ -100,6 +100,10 @@ struct CgArgs;
 int cg_mass_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
 int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int nrhs, hipStream_t s);
 int cg_bras_bf16_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
+// reduce passes over a float32 broken vector (apply.hip)
+int reduce_float_plain(Ctx* c, const float* zb, double* y, int nrhs, hipStream_t s, const double* dotv,
+                       double* dotpart);
+int reduce_float_cg(Ctx* c, const float* zb, int nrhs, hipStream_t s, const CgArgs& cg);
 
 // setup internals (setup.hip)
 int element_setup(Ctx* c, const double* elem_d, hipStream_t s);

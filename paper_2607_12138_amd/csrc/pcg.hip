@@ -213,7 +213,7 @@ static int precond(Ctx* c, int pc, const double* r, double* z, int R, hipStream_
 
 // partials per column written by the preconditioner pass (and its start-up apply)
 static int precond_blocks(Ctx* c, int pc, int R) {
-  return pc == BRAS_PC_BRAS && c->prec != BRAS_BF16 ? reduce_blocks(c, R) : vector_blocks(c, R);
+  return pc == BRAS_PC_BRAS ? reduce_blocks(c, R) : vector_blocks(c, R);
 }
 
 static CgArgs cg_args(Ctx* c, int flexible, int maxit) {

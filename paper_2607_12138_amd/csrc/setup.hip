@@ -243,6 +243,8 @@ template <>
 __device__ inline double cast_out<double>(double v) { return v; }
 template <>
 __device__ inline float cast_out<float>(double v) { return (float)v; }
+template <>
+__device__ inline __bf16 cast_out<__bf16>(double v) { return (__bf16)(float)v; }   // RNE twice, as the oracle emulates
 
 __device__ inline void unpack_lower(int q, int& i, int& j) {
   int r = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
@@ -329,10 +331,11 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
     __syncthreads();
   }
   if (gram) {
+    // element-major: the BF16 element pass reads one element per work-group
     for (int q = t; q < npk; q += nt) {
       int i, j;
       unpack_lower(q, i, j);
-      out[(int64_t)q * E + K] = cast_out<T>(A[i * nl + j] * dinv[j]);
+      out[K * npk + q] = cast_out<T>(A[i * nl + j] * dinv[j]);
     }
     return;
   }
@@ -476,8 +479,8 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
     k_elem_factor<float><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
                                                        mpack, (float*)c->ainv, 0, c->flag);
   else
-    k_elem_factor<float><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
-                                                       mpack, (float*)c->ainv, gram, c->flag);
+    k_elem_factor<__bf16><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
+                                                        mpack, (__bf16*)c->ainv, gram, c->flag);
   BRAS_HIP(hipGetLastError());
   k_diag_broken<<<blocks_for(c->n, 256), 256, 0, s>>>(c->rowptr, c->slot, c->n, diagb, c->diag, c->invdiag);
   BRAS_HIP(hipGetLastError());
@@ -543,7 +546,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
   BRAS_CHECK(form != BRAS_ELEM_METRIC_REF || (nsym >= 1 && nsym <= 6), "nsym must be in 1..6 for METRIC_REF");
   BRAS_CHECK(apply_prec == BRAS_FP64 || apply_prec == BRAS_FP32 || apply_prec == BRAS_BF16, "unknown precision %d",
              apply_prec);
-  BRAS_CHECK(apply_prec != BRAS_BF16, "BF16 element inverses are not available in this build");
+  BRAS_CHECK(!(apply_prec == BRAS_BF16 && form == BRAS_ELEM_SCALED_REF), "BF16 requires METRIC_REF or EXPLICIT");
   BRAS_CHECK(!(apply_prec != BRAS_FP64 && form == BRAS_ELEM_SCALED_REF), "SCALED_REF applies in FP64 only");
   BRAS_CHECK(max_rhs >= 1 && max_rhs <= 256, "max_rhs must be in 1..256");
   hipStream_t s = (hipStream_t)stream;
@@ -681,7 +684,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     } else {
       TRY(dalloc(&c->mpack, (size_t)npack_of(n_loc) * E));
     }
-    size_t esz = apply_prec == BRAS_FP64 ? 8 : 4;
+    size_t esz = apply_prec == BRAS_FP64 ? 8 : (apply_prec == BRAS_FP32 ? 4 : 2);
     c->ainv_bytes = esz * (size_t)npack_of(n_loc) * E;
     TRY(dalloc((char**)&c->ainv, c->ainv_bytes));
   }

@@ -12,6 +12,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 FULL = [w for w in workloads.WORKLOADS if w.prec != "bf16"]
+BF16 = [w for w in workloads.WORKLOADS if w.prec == "bf16"]
 
 
 def say(msg):
@@ -71,4 +72,61 @@ def test_iteration_counts_match_oracle_at_full_size(name):
         assert abs(int(its[0]) - ito) <= 1
         xg = x.cpu().numpy()
         assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
+    gpu.close()
+
+
+def _bf16_rows(ref, coords, cells, pi, n, rows, X):
+    """Rows of the emulated BF16 Gram-factor apply, from the elements touching them."""
+    from oracle import reduced
+    flat = pi.ravel()
+    touch = np.unique(np.nonzero(np.isin(flat, rows))[0] // pi.shape[1])
+    mats = oasm.element_matrices(ref, coords, cells[touch])
+    d = np.bincount(flat, minlength=n)
+    G = reduced.round_bf16(reduced.gram_factors(mats, pi[touch], d))
+    w = reduced.round_bf16(X[pi[touch]])
+    U = reduced.round_bf16(np.einsum("kij,kjr->kir", G, w))
+    Z = np.einsum("kji,kjr->kir", G, U)
+    out = np.zeros((len(rows), X.shape[1]))
+    where = {int(r): t for t, r in enumerate(rows)}
+    for e, K in enumerate(touch):
+        for l, i in enumerate(pi[K]):
+            if int(i) in where:
+                out[where[int(i)]] += Z[e, l]
+    return out
+
+
+@pytest.mark.parametrize("w", BF16, ids=lambda w: w.name)
+def test_bf16_multi_rhs_full_size(w):
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    from paper_2607_12138_amd.problem import MassProblem
+    ref = ofe.reference_element(w.family, w.dim, w.degree)
+    coords, cells = omesh.structured_mesh(w.dim, w.N, jitter=w.jitter, seed=w.mesh_seed)
+    pi, n, _ = odofmap.build_dofmap(cells, len(coords), ref.dofs_per_entity)
+    say("full-size setup %s n=%d E=%d R=%d" % (w.name, n, len(cells), w.nrhs))
+    gpu = MassProblem(w.family, w.dim, w.degree, w.N, jitter=w.jitter, seed=w.mesh_seed, prec=w.prec,
+                      max_rhs=w.nrhs)
+    assert gpu.n == n
+    X = workloads.rhs(n, w.nrhs, w.seed(4))
+    rows = workloads.sample(n, 24, w.seed(4))
+    Xt = torch.from_numpy(X).cuda()
+    say("  sampled rows (bf16 emulation, float64 mass)")
+    Yb = gpu.bras(Xt).cpu().numpy()
+    Ym = gpu.mass(Xt).cpu().numpy()
+    eb = _bf16_rows(ref, coords, cells, pi, n, rows, X)
+    diff = np.abs(Yb[rows] - eb)
+    assert np.mean(diff > 1e-5 * np.max(np.abs(Yb))) < 0.02
+    assert np.max(diff) <= 1e-2 * np.max(np.abs(Yb))
+    om = oasm.operator_rows(ref, coords, cells, pi, n, rows, X, "mass")
+    assert np.max(np.abs(Ym[rows] - om)) <= 1e-13 * np.max(np.abs(Ym))
+    del Yb, Ym
+    b = workloads.rhs(n, w.nrhs, w.seed(1))
+    bt = torch.from_numpy(b).cuda()
+    say("  flexible pcg, %d columns" % w.nrhs)
+    xs, st, its, rel = gpu.solve(bt, "bras", rtol=w.tol)
+    assert st == L.BRAS_OK
+    r = bt - gpu.mass(xs)
+    true_rel = (torch.linalg.norm(r, dim=0) / torch.linalg.norm(bt, dim=0)).cpu().numpy()
+    assert np.all(true_rel <= w.tol * 1.5)
+    say("  iterations %s restarts %d" % (list(its), gpu.info("restarts")))
     gpu.close()

@@ -229,3 +229,48 @@ def test_error_paths():
     st, its, rel = L.pcg_solve(gpu.h, L.PC_BRAS, nanb, gpu.vec(), 1e-10, 100)
     assert st == L.BRAS_EBREAKDOWN
     torch.cuda.synchronize()
+
+
+BF16_CASES = [("RT", 3, 4, 2, 0.2, False, "bf16"), ("RT", 3, 2, 3, 0.2, False, "bf16"),
+              ("N1curl", 3, 2, 3, 0.2, False, "bf16")]
+
+
+@pytest.mark.parametrize("case", BF16_CASES, ids=ids)
+@pytest.mark.parametrize("R", [32, 5])
+def test_bf16_gram_apply(case, R):
+    from oracle import reduced
+    orc, gpu = build(case, max_rhs=32)
+    X = workloads.rhs(orc.n, R, 61)
+    say("bf16 apply R=%d %s" % (R, case))
+    Y = gpu.bras(to_t(X)).cpu().numpy()
+    emu = reduced.bras_apply_bf16_emulated(orc.pi, orc.mats, orc.d, X)
+    ref = orc.B @ X
+    # against the BF16 emulation: the bulk agrees to float32 accumulation
+    # order; where the float32 and the exact accumulation of U fall on
+    # different sides of a BF16 rounding boundary one entry of U moves by one
+    # BF16 ulp (2^-8 relative), so a few outputs differ by about that much
+    diff = np.abs(Y - emu)
+    scale = np.max(np.abs(emu))
+    assert np.mean(diff > 1e-5 * scale) < 0.02
+    assert np.max(diff) <= 1e-2 * scale
+    err = np.max(np.abs(Y - ref)) / np.max(np.abs(ref))
+    assert err <= 3e-2
+    say("  bf16 bras_apply rel. error vs fp64 oracle: %.3e" % err)
+    for r in range(R):
+        assert X[:, r] @ Y[:, r] > 0          # Gram form keeps the preconditioner positive
+
+
+@pytest.mark.parametrize("case", BF16_CASES[:2], ids=ids)
+def test_bf16_flexible_pcg(case):
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(case, max_rhs=32)
+    B = workloads.rhs(orc.n, 32, 62)
+    say("bf16 flexible pcg %s" % (case,))
+    X, st, its, rel = gpu.solve(to_t(B), "bras", rtol=1e-8)
+    assert st == L.BRAS_OK
+    X = X.cpu().numpy()
+    for r in range(0, 32, 7):
+        true_rel = np.linalg.norm(B[:, r] - orc.M @ X[:, r]) / np.linalg.norm(B[:, r])
+        assert true_rel <= 1.5e-8 and abs(true_rel - rel[r]) <= 1e-10
+        xo, ito, ok, _ = opcg.pcg(orc.M, B[:, r], orc.B.dot, tol=1e-8)
+        assert int(its[r]) <= ito + 3                   # BF16 preconditioner costs at most a few iterations

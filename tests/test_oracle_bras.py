@@ -207,3 +207,23 @@ def test_operator_rows_one_by_one(family, dim, deg, N, R):
         got = assembly.operator_rows(ref, coords, cells, pr.pi, pr.n, rows, x, which, rho=rho)
         want = (A @ x)[rows]
         assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(A @ x))
+
+
+def test_gram_factor_identity_and_bf16_emulation_error():
+    from oracle import reduced
+    pr = problem("RT", 3, 2, 2, 0.2)
+    G = reduced.gram_factors(pr.mats, pr.pi, pr.d)
+    # G^T G = D_K^-1 M_K^-1 D_K^-1: the factor form reproduces BRAS exactly in float64
+    x = workloads.rhs(pr.n, 2, 8)
+    Z = np.einsum("kji,kjr->kir", G, np.einsum("kij,kjr->kir", G, x[pr.pi]))
+    y = np.zeros_like(x)
+    np.add.at(y, pr.pi.ravel(), Z.reshape(-1, 2))
+    assert np.max(np.abs(y - pr.B @ x)) <= 1e-13 * np.max(np.abs(pr.B @ x))
+    # BF16 emulation: error of order 2^-8 relative, and r^T B_bf16 r > 0
+    yb = reduced.bras_apply_bf16_emulated(pr.pi, pr.mats, pr.d, x)
+    err = np.max(np.abs(yb - pr.B @ x)) / np.max(np.abs(pr.B @ x))
+    assert 1e-5 < err < 3e-2
+    for r in range(2):
+        assert x[:, r] @ yb[:, r] > 0
+    assert reduced.round_bf16(np.array([1.0 + 2.0 ** -9]))[0] == 1.0          # tie to even
+    assert reduced.round_bf16(np.array([1.0 + 3 * 2.0 ** -9]))[0] == 1.0 + 2.0 ** -7
