@@ -142,9 +142,10 @@ int bras_geometry(int family, int dim, int64_t nvert, const double* coords_d,
  * folds D^-1 on both sides and stores it in apply_prec.  BRAS_BF16 requires
  * METRIC_REF or EXPLICIT and stores the Gram factor G_K = L_K^-1 D_K^-1
  * (M_K = L_K L_K^T) so that D_K^-1 M_K^-1 D_K^-1 = G_K^T G_K.
- * max_rhs bounds nrhs in later calls and sizes the workspace.  Every input
- * is copied; the caller may free its buffers when the call returns.
- * Synchronous. */
+ * max_rhs (1..256) bounds nrhs in later calls and sizes the workspace; one
+ * [n][max_rhs] float64 block must stay below 4 GiB (EINVAL otherwise).
+ * Every input is copied; the caller may free its buffers when the call
+ * returns.  Synchronous. */
 int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const int32_t* l2g_d,
                int form, const double* ref_d, const double* elem_d, int nsym,
                int apply_prec, int max_rhs, void* stream);

@@ -22,6 +22,7 @@
 #include "internal.h"
 #include "block_reduce.h"
 #include "cg_common.h"
+#include "elem_lane.h"
 
 namespace bras {
 
@@ -29,7 +30,6 @@ constexpr int kBS = 256;                  // reduce / vector pass block size
 constexpr int kEB = 256;                  // element pass block size
 constexpr int kMaxVectorBlocks = 512;
 
-enum { FORM_SCALED = 0, FORM_PACKED = 1, FORM_METRIC = 2 };
 enum { OUT_PLAIN = 0, OUT_MASS_CG = 1, OUT_BRAS_CG = 2 };
 
 __device__ __forceinline__ int packed_index(int i, int j) {
@@ -48,7 +48,6 @@ __device__ __forceinline__ int packed_index(int i, int j) {
 // local-index-major broken vector zb[l][K] (column fastest).
 //   FORM_SCALED  z_l = coefK[K] sum_j A[l][j] w_j           (A shared)
 //   FORM_PACKED  z_l = sum_j P_K(l, j) w_j                   (P_K packed lower, [q][E])
-//   FORM_METRIC  z_l = sum_p G_p,K sum_j S_p[l][j] w_j       (S_p shared, G [p][E])
 // T is the arithmetic type (float for FP32 element inverses).
 constexpr int kEPB = 64;        // elements per work-group (one per lane)
 constexpr int kWS = kEPB + 1;   // LDS row stride
@@ -56,7 +55,7 @@ constexpr int kWS = kEPB + 1;   // LDS row stride
 template <int NL, int FORM, typename T, typename ZT>
 __global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* __restrict__ l2g, InArgs in,
                                               const double* __restrict__ dscale, const double* __restrict__ A,
-                                              const double* __restrict__ coefK, const T* __restrict__ ap, int nsym,
+                                              const double* __restrict__ coefK, const T* __restrict__ ap,
                                               ZT* __restrict__ zb) {
   constexpr int RPW = (NL + 3) / 4;   // rows per wave
   __shared__ T w[NL * kWS];
@@ -131,23 +130,7 @@ __global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* _
       T acc[RPW];
 #pragma unroll
       for (int k = 0; k < RPW; ++k) acc[k] = (T)0;
-      if (FORM == FORM_METRIC) {
-        for (int p = 0; p < nsym; ++p) {
-          T t[RPW];
-#pragma unroll
-          for (int k = 0; k < RPW; ++k) t[k] = (T)0;
-          const double* Sp = A + (int64_t)p * NL * NL;
-#pragma unroll
-          for (int j = 0; j < NL; ++j) {
-            const T wj = w[j * kWS + lane];
-#pragma unroll
-            for (int k = 0; k < RPW; ++k) t[k] = fma((T)Sp[row[k] * NL + j], wj, t[k]);
-          }
-          const T gp = (T)coefK[(int64_t)p * E + K];
-#pragma unroll
-          for (int k = 0; k < RPW; ++k) acc[k] = fma(gp, t[k], acc[k]);
-        }
-      } else if (FORM == FORM_SCALED) {
+      if (FORM == FORM_SCALED) {
 #pragma unroll
         for (int j = 0; j < NL; ++j) {
           const T wj = w[j * kWS + lane];
@@ -322,7 +305,15 @@ __global__ void __launch_bounds__(kBS) k_diag_cg(int64_t n, int R, const double*
   __shared__ double sh0[kBS], sh1[kBS], sh2[kBS];
   __shared__ double coef_s[256];
   __shared__ int act_s[256];
-  alpha_prologue(cg.apart, cg.anb, R, cg.sc, cg.ic, coef_s, act_s, sh0);
+  if (cg.apart) {
+    alpha_prologue(cg.apart, cg.anb, R, cg.sc, cg.ic, coef_s, act_s, sh0);
+  } else {
+    for (int c = threadIdx.x; c < R; c += kBS) {
+      act_s[c] = cg.ic[I_ACTIVE * R + c];
+      coef_s[c] = cg.sc[S_ALPHA * R + c];
+    }
+    __syncthreads();
+  }
   {
     bool any = false;
     for (int c = 0; c < R; ++c) any = any || act_s[c];
@@ -441,8 +432,7 @@ template <int NL, int FORM, typename T, typename ZT>
 static int elem_launch(Ctx* c, int R, const InArgs& in, const double* dscale, const double* A, const double* coefK,
                        const T* ap, ZT* zb, hipStream_t s) {
   const unsigned nb = (unsigned)((c->E + kEPB - 1) / kEPB);
-  const int nsym = FORM == FORM_METRIC ? c->nsym : 0;
-  k_elem<NL, FORM, T, ZT><<<nb, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, ap, nsym, zb);
+  k_elem<NL, FORM, T, ZT><<<nb, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, ap, zb);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
@@ -459,14 +449,44 @@ static int elem_dispatch(Ctx* c, int R, const InArgs& in, const double* dscale, 
 #undef CASE
 }
 
+#define LANE_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(21) X(24) X(28) X(35) X(36)
+
+// work-group size of the per-lane element pass: one wavefront
+constexpr int lane_epb(int) { return 64; }
+
+template <int NL, int FORM, int NSYM, typename T, typename ZT>
+static int lane_launch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {
+  constexpr int EPB = lane_epb(FORM);
+  const unsigned nb = (unsigned)((c->E + EPB - 1) / EPB);
+  k_elem_lane<NL, FORM, NSYM, T, ZT, EPB><<<nb, EPB, 0, s>>>(c->E, R, c->l2g, in, c->symtab, c->coef, c->nsym, ap,
+                                                              zb);
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+template <int FORM, int NSYM, typename T, typename ZT>
+static int lane_dispatch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {
+#define CASE(N) \
+  case N: return lane_launch<N, FORM, NSYM, T, ZT>(c, R, in, ap, zb, s);
+  switch (c->nl) {
+    LANE_CASES(CASE)
+    default: return fail(BRAS_EINVAL, "n_loc %d has no per-lane element kernel", c->nl);
+  }
+#undef CASE
+}
+
 // element pass of the mass operator (float64)
 static int mass_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
   double* zb = (double*)c->zb;
   if (c->form == BRAS_ELEM_SCALED_REF)
     return elem_dispatch<FORM_SCALED, double, double>(c, R, in, nullptr, c->ref, c->coef, nullptr, zb, s);
-  if (c->mpack)
+  if (c->mpack) {
+    if (c->nl <= kLaneMaxNL) return lane_dispatch<FORM_PACKED, 0, double, double>(c, R, in, c->mpack, zb, s);
     return elem_dispatch<FORM_PACKED, double, double>(c, R, in, nullptr, nullptr, nullptr, c->mpack, zb, s);
-  return elem_dispatch<FORM_METRIC, double, double>(c, R, in, nullptr, c->ref, c->coef, nullptr, zb, s);
+  }
+  // metric tables (setup keeps them only for n_loc <= kLaneMaxNL)
+  if (c->nsym <= 3) return lane_dispatch<FORM_METRIC, 3, double, double>(c, R, in, nullptr, zb, s);
+  return lane_dispatch<FORM_METRIC, 6, double, double>(c, R, in, nullptr, zb, s);
 }
 
 // element pass of the BRAS operator; reports whether the broken vector is float32
@@ -475,10 +495,14 @@ static int bras_elem(Ctx* c, const InArgs& in, int R, hipStream_t s, bool* zb_fl
   if (c->form == BRAS_ELEM_SCALED_REF)
     return elem_dispatch<FORM_SCALED, double, double>(c, R, in, c->invd, c->refinv, c->icoef, nullptr,
                                                        (double*)c->zb, s);
-  if (c->prec == BRAS_FP64)
+  const bool lane = c->nl <= kLaneMaxNL;
+  if (c->prec == BRAS_FP64) {
+    if (lane) return lane_dispatch<FORM_PACKED, 0, double, double>(c, R, in, (const double*)c->ainv, (double*)c->zb, s);
     return elem_dispatch<FORM_PACKED, double, double>(c, R, in, nullptr, nullptr, nullptr, (const double*)c->ainv,
                                                        (double*)c->zb, s);
+  }
   *zb_float = true;
+  if (lane) return lane_dispatch<FORM_PACKED, 0, float, float>(c, R, in, (const float*)c->ainv, (float*)c->zb, s);
   return elem_dispatch<FORM_PACKED, float, float>(c, R, in, nullptr, nullptr, nullptr, (const float*)c->ainv,
                                                    (float*)c->zb, s);
 }
@@ -537,6 +561,33 @@ int launch_jacobi(Ctx* c, const double* x, double* y, int R, hipStream_t s, cons
   return BRAS_OK;
 }
 
+// Element-pass input r - alpha q of the preconditioner step: alpha either
+// from the p.q partials in the pass's own prologue (cg.apart set) or as
+// already stored in sc by a one-block kernel.
+InArgs precond_input(const CgArgs& cg, int R) {
+  InArgs in;
+  in.x = cg.r;
+  in.x2 = cg.q;
+  in.sign = -1.0;
+  if (cg.apart) {
+    in.apart = cg.apart;
+    in.anb = cg.anb;
+    in.sc = cg.sc;
+    in.ic = cg.ic;
+  } else {
+    in.cvec = cg.sc + S_ALPHA * R;
+    in.active = cg.ic + I_ACTIVE * R;
+  }
+  return in;
+}
+
+// Work-groups of the pass that consumes alpha (each one would sum the p.q
+// partials in its prologue).
+int precond_consumer_blocks(Ctx* c, int pc, int R) {
+  if (pc == BRAS_PC_BRAS) return c->prec == BRAS_BF16 ? (int)c->E : (int)((c->E + kEPB - 1) / kEPB);
+  return vector_blocks(c, R);
+}
+
 // q = M (z + beta p), p <- z + beta p, alpha = rho / p.q
 int cg_mass_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
   InArgs in;
@@ -553,14 +604,7 @@ int cg_mass_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
 // r <- r - alpha q, x <- x + alpha p, z = C r, dot products, convergence, beta
 int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
   if (pc == BRAS_PC_BRAS && c->prec != BRAS_BF16) {
-    InArgs in;
-    in.x = cg.r;
-    in.x2 = cg.q;
-    in.sign = -1.0;
-    in.apart = cg.apart;   // alpha from the p.q partials, in the element pass's prologue
-    in.anb = cg.anb;
-    in.sc = cg.sc;
-    in.ic = cg.ic;
+    InArgs in = precond_input(cg, R);
     bool zf;
     int st = bras_elem(c, in, R, s, &zf);
     if (st) return st;

@@ -179,14 +179,7 @@ int launch_bras_bf16(Ctx* c, const double* x, double* y, int R, hipStream_t s, c
 }
 
 int cg_bras_bf16_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
-  InArgs in;
-  in.x = cg.r;
-  in.x2 = cg.q;
-  in.sign = -1.0;
-  in.apart = cg.apart;
-  in.anb = cg.anb;
-  in.sc = cg.sc;
-  in.ic = cg.ic;
+  InArgs in = precond_input(cg, R);
   int st = bf16_elem(c, in, R, s);
   if (st) return st;
   return reduce_float_cg(c, (const float*)c->zb, R, s, cg);

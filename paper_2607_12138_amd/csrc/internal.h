@@ -66,7 +66,11 @@ struct Ctx {
   void* ainv = nullptr;      // METRIC/EXPLICIT: folded inverse, packed lower [npack][E] in prec,
                              // or (BF16) the Gram factor, packed lower, element-major [E][npack]
   size_t ainv_bytes = 0;
-  double* mpack = nullptr;   // packed float64 M_K [npack][E] for the mass pass (EXPLICIT, or METRIC with large n_loc)
+  int agroup = 1;            // entry group of ainv (packed_group), 1 for the element-major BF16 factor
+  int mgroup = 1;            // entry group of mpack
+  double* symtab = nullptr;  // METRIC_REF, n_loc <= kLaneMaxNL: pair tables packed [npack][sym_stride(nsym)]
+  double* mpack = nullptr;   // packed float64 M_K [npack][E] for the mass pass (EXPLICIT, or METRIC with
+                             // n_loc > kLaneMaxNL)
   double* diag = nullptr;    // diag(M) [n]
   double* invdiag = nullptr; // [n]
 
@@ -79,6 +83,17 @@ struct Ctx {
 };
 
 inline int npack_of(int nl) { return nl * (nl + 1) / 2; }
+
+// Largest n_loc whose element passes keep a whole element in one lane's registers.
+constexpr int kLaneMaxNL = 36;
+// Packed per-element matrices are stored in groups of g consecutive entries q
+// (16 bytes when the per-lane pass reads them, else g = 1):
+// entry (q, K) at ((q / g) * E + K) * g + q % g, the entry count padded to a
+// multiple of g.
+inline int packed_group(int nl, size_t esz) { return nl <= kLaneMaxNL ? (int)(16 / esz) : 1; }
+inline size_t packed_slots(int nl, int g) { return (size_t)((npack_of(nl) + g - 1) / g) * g; }
+// Row stride of the packed pair tables: 3 (up to 3 pairs, 2D) or 6 (3D), zero padded.
+inline int sym_stride(int nsym) { return nsym <= 3 ? 3 : 6; }
 
 // Launch helpers (apply.hip).  dotv/dotpart (optional): accumulate y . dotv
 // into per-block partial sums [blocks][nrhs]; active (optional): per-column
@@ -100,6 +115,9 @@ struct CgArgs;
 int cg_mass_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
 int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int nrhs, hipStream_t s);
 int cg_bras_bf16_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
+struct InArgs;
+InArgs precond_input(const CgArgs& cg, int nrhs);
+int precond_consumer_blocks(Ctx* c, int pc, int nrhs);
 // reduce passes over a float32 broken vector (apply.hip)
 int reduce_float_plain(Ctx* c, const float* zb, double* y, int nrhs, hipStream_t s, const double* dotv,
                        double* dotpart);

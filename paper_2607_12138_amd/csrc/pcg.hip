@@ -126,6 +126,32 @@ __global__ void __launch_bounds__(kBS) k_zero(int64_t n, double* __restrict__ v)
   for (int64_t t = t0; t < n; t += stride) v[t] = 0.0;
 }
 
+// alpha = rho / p.q for every running column (one block); used instead of the
+// consumers' prologue when every consumer work-group re-reading the partials
+// would cost more than this extra launch
+__global__ void k_fin_alpha(int nb, int R, const double* __restrict__ part, double* __restrict__ sc,
+                            int* __restrict__ ic) {
+  __shared__ double sh[kBS];
+  for (int col = 0; col < R; ++col) {
+    if (!ic[I_ACTIVE * R + col]) continue;   // uniform
+    const double pq = block_sum(part, nb, R, col, sh);
+    if (threadIdx.x == 0) {
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        sc[S_ALPHA * R + col] = 0.0;
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
+      } else {
+        sc[S_ALPHA * R + col] = sc[S_RZ * R + col] / pq;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// partial sums the alpha prologues of one iteration may re-read before a
+// separate alpha kernel is cheaper
+constexpr double kPrologueReadsMax = 4.0e6;
+
 // convergence test, beta and rho after the preconditioner pass of an iteration
 __global__ void k_fin_iter(int nb, int R, const double* __restrict__ p0, const double* __restrict__ p1,
                            const double* __restrict__ p2, double* __restrict__ sc, int* __restrict__ ic, int flexible,
@@ -243,8 +269,14 @@ static int iteration(Ctx* c, int pc, int flexible, int maxit, hipStream_t s) {
   pcg.part0 = g->part[0];                     // r.r
   pcg.part1 = g->part[1];                     // r.z
   pcg.part2 = g->part[2];                     // r.z_old (flexible)
-  pcg.apart = g->part[3];
-  pcg.anb = reduce_blocks(c, R);
+  const int anb = reduce_blocks(c, R);
+  if ((double)precond_consumer_blocks(c, pc, R) * anb * R > kPrologueReadsMax) {
+    k_fin_alpha<<<1, kBS, 0, s>>>(anb, R, g->part[3], g->sc, g->ic);
+    BRAS_HIP(hipGetLastError());
+  } else {
+    pcg.apart = g->part[3];
+    pcg.anb = anb;
+  }
   if ((st = cg_precond_step(c, pc, pcg, R, s))) return st;
   k_fin_iter<<<1, kBS, 0, s>>>(precond_blocks(c, pc, R), R, g->part[0], g->part[1], g->part[2], g->sc, g->ic,
                                flexible, maxit);

@@ -207,6 +207,19 @@ __global__ void k_sort_rows(const int32_t* __restrict__ rowptr, int64_t n, int n
   }
 }
 
+// S [nsym][nl][nl] (symmetric pair tables) -> packed lower [q][ss], q = i(i+1)/2 + j,
+// entries p >= nsym zero
+__global__ void k_pack_sym(const double* __restrict__ S, int nl, int nsym, int ss, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npk = (int64_t)nl * (nl + 1) / 2;
+  if (t >= npk * ss) return;
+  const int q = (int)(t / ss), p = (int)(t % ss);
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= q) ++i;
+  const int j = q - i * (i + 1) / 2;
+  out[t] = p < nsym ? S[(int64_t)p * nl * nl + i * nl + j] : 0.0;
+}
+
 // AoS [E][nsym] -> SoA [nsym][E]
 __global__ void k_transpose_coef(const double* __restrict__ in, int64_t E, int nsym, double* __restrict__ out) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -259,8 +272,8 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
                                                     const double* __restrict__ S, const double* __restrict__ Gsoa,
                                                     const double* __restrict__ Mexp, const int32_t* __restrict__ l2g,
                                                     const double* __restrict__ invd, double* __restrict__ diagb,
-                                                    double* __restrict__ mpack, T* __restrict__ out, int gram,
-                                                    int* __restrict__ flag) {
+                                                    double* __restrict__ mpack, int mg, T* __restrict__ out, int og,
+                                                    int gram, int* __restrict__ flag) {
   extern __shared__ double lds[];
   double* A = lds;               // nl*nl (lower triangle used)
   double* g = A + nl * nl;       // nsym (<= 6)
@@ -285,7 +298,7 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
       v = Mexp[K * nn + i * nl + j];
     }
     A[i * nl + j] = v;
-    if (mpack) mpack[(int64_t)q * E + K] = v;
+    if (mpack) mpack[((int64_t)(q / mg) * E + K) * mg + q % mg] = v;
     if (i == j) diagb[(int64_t)i * E + K] = v;
   }
   __syncthreads();
@@ -345,7 +358,7 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
     unpack_lower(q, i, j);
     double s = 0.0;
     for (int k = i; k < nl; ++k) s += A[k * nl + i] * A[k * nl + j];
-    out[(int64_t)q * E + K] = cast_out<T>(s * dinv[i] * dinv[j]);
+    out[((int64_t)(q / og) * E + K) * og + q % og] = cast_out<T>(s * dinv[i] * dinv[j]);
   }
 }
 
@@ -474,13 +487,14 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
   if (lds > 64 * 1024) return fail(BRAS_EINVAL, "n_loc %d too large for the element factorisation", nl);
   if (c->prec == BRAS_FP64)
     k_elem_factor<double><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
-                                                        mpack, (double*)c->ainv, 0, c->flag);
+                                                        mpack, c->mgroup, (double*)c->ainv, c->agroup, 0, c->flag);
   else if (c->prec == BRAS_FP32)
     k_elem_factor<float><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
-                                                       mpack, (float*)c->ainv, 0, c->flag);
+                                                       mpack, c->mgroup, (float*)c->ainv, c->agroup, 0, c->flag);
   else
     k_elem_factor<__bf16><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
-                                                        mpack, (__bf16*)c->ainv, gram, c->flag);
+                                                        mpack, c->mgroup, (__bf16*)c->ainv, c->agroup, gram,
+                                                        c->flag);
   BRAS_HIP(hipGetLastError());
   k_diag_broken<<<blocks_for(c->n, 256), 256, 0, s>>>(c->rowptr, c->slot, c->n, diagb, c->diag, c->invdiag);
   BRAS_HIP(hipGetLastError());
@@ -495,7 +509,7 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
 static void free_ctx(Ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->l2g, c->mult, c->invd, c->rowptr, c->chunk, c->slot, c->ref, c->refinv, c->coef, c->icoef, c->ainv,
-                  c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag};
+                  c->symtab, c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   cg_free(c);
@@ -549,6 +563,8 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
   BRAS_CHECK(!(apply_prec == BRAS_BF16 && form == BRAS_ELEM_SCALED_REF), "BF16 requires METRIC_REF or EXPLICIT");
   BRAS_CHECK(!(apply_prec != BRAS_FP64 && form == BRAS_ELEM_SCALED_REF), "SCALED_REF applies in FP64 only");
   BRAS_CHECK(max_rhs >= 1 && max_rhs <= 256, "max_rhs must be in 1..256");
+  BRAS_CHECK((uint64_t)n * (uint64_t)max_rhs * 8u < (1ull << 32),
+             "n * max_rhs * 8 bytes must stay below 4 GiB (a conforming block vector)");
   hipStream_t s = (hipStream_t)stream;
   Ctx* c = new Ctx();
   int st = BRAS_OK;
@@ -678,15 +694,34 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
         return fail(BRAS_EHIP, "copy of reference tables failed");
       }
       TRY(dalloc(&c->coef, (size_t)c->nsym * E));
-      // the mass pass recomputes M_K from the tables in LDS when they fit,
-      // otherwise it reads a packed float64 copy of M_K made at setup
-      if (sizeof(double) * (size_t)c->nsym * nn > 24 * 1024) TRY(dalloc(&c->mpack, (size_t)npack_of(n_loc) * E));
+      // the mass pass rebuilds M_K from packed pair tables when one lane can
+      // hold an element, otherwise it reads a packed float64 copy of M_K
+      if (n_loc <= kLaneMaxNL) {
+        const int ss = sym_stride(c->nsym);
+        const int64_t cnt = (int64_t)npack_of(n_loc) * ss;
+        TRY(dalloc(&c->symtab, (size_t)cnt));
+        k_pack_sym<<<blocks_for(cnt, 256), 256, 0, s>>>(c->ref, n_loc, c->nsym, ss, c->symtab);
+        if (hipGetLastError() != hipSuccess) { free_ctx(c); return fail(BRAS_EHIP, "pair table packing failed"); }
+      } else {
+        TRY(dalloc(&c->mpack, (size_t)npack_of(n_loc) * E));
+      }
     } else {
-      TRY(dalloc(&c->mpack, (size_t)npack_of(n_loc) * E));
+      c->mgroup = packed_group(n_loc, sizeof(double));
+      const size_t cnt = packed_slots(n_loc, c->mgroup) * E;
+      TRY(dalloc(&c->mpack, cnt));
+      if (hipMemsetAsync(c->mpack, 0, sizeof(double) * cnt, s) != hipSuccess) {
+        free_ctx(c);
+        return fail(BRAS_EHIP, "clearing packed element matrices failed");
+      }
     }
     size_t esz = apply_prec == BRAS_FP64 ? 8 : (apply_prec == BRAS_FP32 ? 4 : 2);
-    c->ainv_bytes = esz * (size_t)npack_of(n_loc) * E;
+    c->agroup = apply_prec == BRAS_BF16 ? 1 : packed_group(n_loc, esz);
+    c->ainv_bytes = esz * packed_slots(n_loc, c->agroup) * E;
     TRY(dalloc((char**)&c->ainv, c->ainv_bytes));
+    if (hipMemsetAsync(c->ainv, 0, c->ainv_bytes, s) != hipSuccess) {
+      free_ctx(c);
+      return fail(BRAS_EHIP, "clearing packed element inverses failed");
+    }
   }
   TRY(element_setup(c, elem_d, s));
   // workspace
