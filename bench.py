@@ -7,9 +7,15 @@ Jacobi-PCG solve of the same system, the BRAS apply bandwidth against the
 HBM roofline and the CPU oracle (same workload, bounded sample) are reported
 beside it.
 
+Default workload: H(curl) Nedelec (first kind) degree 2 on 48^3 x 6 jittered
+tetrahedra (4.27M DOFs), BRAS inverses stored in FP32 inside FP64 CG, tolerance
+1e-8 (the tolerance the metric names).
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -24,12 +30,15 @@ import workloads  # noqa: E402
 
 METRIC = "BRAS-PCG time to 1e-8 rel. residual vs Jacobi-PCG; BRAS apply HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-DEFAULT = "h1p3_3d_24_jit"
+DEFAULT = "n1curl2_3d_48_jit"
 
 
 def algorithmic_bytes(w, n, E, n_loc, R, prec):
-    """Bytes one BRAS apply must move: x in, y out (float64), the map
-    (int32 per broken DOF), element data, and D^-1 when it is not folded."""
+    """Bytes one BRAS apply must move (the unit of the roofline): x in and
+    y out (float64), the map (int32 per broken DOF), the element data, and
+    D^-1 when it is not folded into the stored inverses.  The broken
+    intermediate and the transpose map are implementation traffic and are
+    not counted."""
     nbr = E * n_loc
     vec = 8.0 * n * R
     if w.family == "P":
@@ -40,6 +49,31 @@ def algorithmic_bytes(w, n, E, n_loc, R, prec):
         elem = esz * E * n_loc * (n_loc + 1) / 2.0
         dinv = 0.0              # folded into the stored inverses
     return 2 * vec + 4.0 * nbr + elem + dinv
+
+
+def source_digest():
+    """sha256 over the library's kernel sources (to tell whether a stored
+    counter measurement still describes the kernels being run)."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2607_12138_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(f, "rb") as fh:
+                h.update(os.path.basename(f).encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload):
+    """HBM bytes per BRAS apply from the committed rocprofv3 counter summary
+    of this workload, or None when the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "bras_apply_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("hbm_bytes_per_apply")
 
 
 def time_solves(prob, b, pc, tol, steps):
@@ -54,6 +88,8 @@ def time_solves(prob, b, pc, tol, steps):
 
 
 def time_apply(fn, x, y, reps):
+    """Average duration of fn on the current torch stream (the stream the
+    library launches on), from HIP events around reps back-to-back calls."""
     import torch
     s = torch.cuda.current_stream()
     for _ in range(3):
@@ -67,31 +103,45 @@ def time_apply(fn, x, y, reps):
     return e0.elapsed_time(e1) / reps * 1e3   # microseconds
 
 
-def cpu_baseline(w, b_host, budget_s=25.0):
-    """The oracle's BRAS-PCG on the same workload (assembly excluded, as the
-    paper excludes preconditioner construction)."""
-    from oracle import fe, mesh, assembly, pcg
-    ref = fe.reference_element(w.family, w.dim, w.degree)
-    coords, cells = mesh.structured_mesh(w.dim, w.N, jitter=w.jitter, seed=w.mesh_seed)
-    rho = workloads.density(len(cells), w.seed(2)) if w.density else None
-    pr = assembly.Problem(ref, coords, cells, rho=rho)
-    b = b_host if b_host.ndim == 1 else b_host[:, 0]
-    times, its = [], None
-    t_start = time.perf_counter()
-    while True:
+def cpu_baseline(w, its_gpu, budget_s=20.0):
+    """The oracle's BRAS-PCG on the same workload, matrix-free (its element
+    route), one thread.  Setup (mesh, numbering, element matrices and
+    inverses) is excluded, as the paper excludes preconditioner
+    construction.  A bounded sample: at most budget_s of iterations; the
+    time per iteration is scaled to the GPU's iteration count."""
+    from threadpoolctl import threadpool_limits
+    from oracle import fe, mesh, dofmap, assembly, pcg
+    with threadpool_limits(1):
+        ref = fe.reference_element(w.family, w.dim, w.degree)
+        coords, cells = mesh.structured_mesh(w.dim, w.N, jitter=w.jitter, seed=w.mesh_seed)
+        rho = workloads.density(len(cells), w.seed(2)) if w.density else None
+        pi, n, _ = dofmap.build_dofmap(cells, len(coords), ref.dofs_per_entity)
+        mats = assembly.element_matrices(ref, coords, cells, rho)
+        inv = assembly.element_inverses(mats)
+        d = np.bincount(pi.ravel(), minlength=n).astype(float)
+        b = workloads.rhs(n, 1, w.seed(1))
+        b = b if b.ndim == 1 else b[:, 0]
+        M = lambda v: assembly.mass_apply_matrix_free(pi, mats, v)        # noqa: E731
+        C = lambda v: assembly.bras_apply_matrix_free(pi, inv, d, v)     # noqa: E731
         t0 = time.perf_counter()
-        _, its, ok, _ = pcg.pcg(pr.M, b, pr.B.dot, tol=w.tol)
-        times.append(time.perf_counter() - t0)
-        if len(times) >= 3 or time.perf_counter() - t_start + times[-1] > budget_s:
-            break
-    cols = 1 if b_host.ndim == 1 else b_host.shape[1]
+        M(b)
+        C(b)
+        est = time.perf_counter() - t0                  # about one iteration
+        k = int(max(1, min(its_gpu, budget_s / max(est, 1e-6) - 1)))
+        t0 = time.perf_counter()
+        _, done, ok, _ = pcg.pcg(M, b, C, tol=w.tol, maxit=k)
+        dt = time.perf_counter() - t0
+    per_it = dt / max(done, 1)
+    full = bool(ok)
     return {
-        "value": float(np.mean(times) * 1e3 * cols),
-        "unit": "ms per solve",
+        "value": round(per_it * (done if full else its_gpu) * 1e3, 3),
+        "unit": "ms per solve (BRAS-PCG, one right-hand side)",
         "cores": 1,
         "kind": "oracle",
-        "sample": "full workload, %d BRAS-PCG solve(s) of column 0 (scaled x%d columns), scipy CSR, "
-                  "1 thread; %d iterations" % (len(times), cols, its),
+        "sample": ("full solve, %d iterations" % done) if full else
+                  ("%d of %d iterations of the oracle's matrix-free BRAS-PCG on column 0 of the same "
+                   "workload (numpy, 1 thread; setup excluded), %.1f s, scaled to %d iterations"
+                   % (done, its_gpu, dt, its_gpu)),
     }
 
 
@@ -103,6 +153,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(workloads.BY_NAME))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--mode", choices=["full", "apply", "copy"], default="full",
+                    help="apply: only back-to-back BRAS applies (for counter runs); "
+                         "copy: a device copy of known size (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on exactly one GPU: the method has no multi-GPU path in this library "
@@ -111,6 +164,16 @@ def main():
     import torch
     from paper_2607_12138_amd import _lib as L
     from paper_2607_12138_amd.problem import MassProblem
+
+    if a.mode == "copy":
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(a.apply_reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "reps": a.apply_reps}))
+        return
 
     w = workloads.BY_NAME[a.workload]
     rho = workloads.density(w.n_cells, w.seed(2)) if w.density else None
@@ -123,6 +186,14 @@ def main():
           flush=True)
     b_host = workloads.rhs(prob.n, w.nrhs, w.seed(1))
     b = torch.from_numpy(b_host).cuda()
+    if a.mode == "apply":
+        y = prob.vec(w.nrhs)
+        us = time_apply(lambda u, v: L.bras_apply(prob.h, u, v), b, y, a.apply_reps)
+        prob.close()
+        print(json.dumps({"mode": "apply", "workload": w.name, "reps": a.apply_reps, "us_per_apply": round(us, 3),
+                          "bytes_per_apply": int(algorithmic_bytes(w, prob.n, prob.E, prob.n_loc, w.nrhs, w.prec)),
+                          "source_digest": source_digest()}), flush=True)
+        return
     for _ in range(a.warmup):
         prob.solve(b, "bras", rtol=w.tol)
         prob.solve(b, "jacobi", rtol=w.tol)
@@ -138,6 +209,7 @@ def main():
     mass_us = time_apply(lambda u, v: L.mass_apply(prob.h, u, v), x, y, a.apply_reps)
     nbytes = algorithmic_bytes(w, prob.n, prob.E, prob.n_loc, w.nrhs, w.prec)
     achieved = nbytes / (bras_us * 1e-6) / 1e9
+    traffic = stored_traffic(w.name)
     out = {
         "metric": METRIC,
         "value": round(bras_ms, 4),
@@ -164,14 +236,15 @@ def main():
         "mass_apply_us": round(mass_us, 3),
         "bras_apply_gbs": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "bras_apply (element pass + transpose-map reduce)",
-                     "bytes_per_launch": int(nbytes)},
+                     "bytes_per_launch": int(nbytes), "us_per_launch": round(bras_us, 3)},
+        "source_digest": source_digest(),
         "setup_s": round(setup_s, 3),
     }
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, b_host)
+        out["cpu_baseline"] = cpu_baseline(w, int(max(its_b)))
     prob.close()
     print(json.dumps(out), flush=True)
 
