@@ -20,6 +20,11 @@ SOURCES = [
     ("capi.cpp", []),
     ("setup.hip", []),
     ("apply.hip", []),
+    ("lane_packed_f64.hip", []),
+    ("lane_packed_f32.hip", []),
+    ("lane_metric3.hip", []),
+    ("lane_metric6.hip", []),
+    ("elem_mfma.hip", []),
     ("pcg.hip", []),
     ("bf16.hip", []),
 ]

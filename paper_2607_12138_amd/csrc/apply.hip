@@ -32,12 +32,10 @@ constexpr int kMaxVectorBlocks = 512;
 
 enum { OUT_PLAIN = 0, OUT_MASS_CG = 1, OUT_BRAS_CG = 2 };
 
-__device__ __forceinline__ int packed_index(int i, int j) {
-  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
-}
-
 // ---------------------------------------------------------------------------
-// element pass
+// element pass, affine H1 (a shared reference matrix times one coefficient per
+// element; eq. piola_mass_pullbacks).  Per-element matrices use the per-lane
+// pass (elem_lane.h) or, for large n_loc, the matrix-core pass (elem_mfma.hip).
 // ---------------------------------------------------------------------------
 // A work-group owns 64 consecutive elements, one per lane.  Gather phase: all
 // 256 threads read the 64 elements' map entries (contiguous) and the gathered
@@ -46,17 +44,16 @@ __device__ __forceinline__ int packed_index(int i, int j) {
 // table entry it reads for a row is the same in all lanes (wave-uniform scalar
 // loads) and every store of a row is 64 consecutive elements of the
 // local-index-major broken vector zb[l][K] (column fastest).
-//   FORM_SCALED  z_l = coefK[K] sum_j A[l][j] w_j           (A shared)
-//   FORM_PACKED  z_l = sum_j P_K(l, j) w_j                   (P_K packed lower, [q][E])
-// T is the arithmetic type (float for FP32 element inverses).
+//   z_l = coefK[K] sum_j A[l][j] w_j    (A shared; BRAS: A = Mhat^-1, coefK = 1/c_K,
+//                                        and the input is scaled by dscale = D^-1)
 constexpr int kEPB = 64;        // elements per work-group (one per lane)
 constexpr int kWS = kEPB + 1;   // LDS row stride
 
-template <int NL, int FORM, typename T, typename ZT>
+template <int NL, bool DS>
 __global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* __restrict__ l2g, InArgs in,
                                               const double* __restrict__ dscale, const double* __restrict__ A,
-                                              const double* __restrict__ coefK, const T* __restrict__ ap,
-                                              ZT* __restrict__ zb) {
+                                              const double* __restrict__ coefK, double* __restrict__ zb) {
+  typedef double T;
   constexpr int RPW = (NL + 3) / 4;   // rows per wave
   __shared__ T w[NL * kWS];
   __shared__ double coef_s[256];      // per-column coefficient of x2 (alpha or beta)
@@ -85,36 +82,37 @@ __global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* _
   const int ne = (int)((E - K0) < kEPB ? (E - K0) : kEPB);
   const int64_t K = K0 + lane;
   const bool on = lane < ne;
-  const double ck = (FORM == FORM_SCALED && on) ? coefK[K] : 1.0;
+  const double ck = on ? coefK[K] : 1.0;
   for (int col = 0; col < R; ++col) {
     if (!act_s[col]) continue;   // uniform
     const double cf = coef_s[col];
     {
-      // all of this thread's map entries, then all gathers, then the LDS stores
+      // all of this thread's map entries, then all gathers, then the LDS
+      // stores; entries past the last element repeat its last map entry, so
+      // no load needs a branch.  Without a second vector the first one is
+      // read twice with weight 0.
       constexpr int GPT = (NL * kEPB + kEB - 1) / kEB;
-      const int nq = ne * NL;
+      const int qmax = ne * NL - 1;
       int32_t gi[GPT];
 #pragma unroll
       for (int u = 0; u < GPT; ++u) {
         const int q = tid + u * kEB;
-        gi[u] = q < nq ? l2g[K0 * NL + q] : 0;
+        gi[u] = l2g[K0 * NL + (q < qmax ? q : qmax)];
       }
+      const double* x2 = in.x2 ? in.x2 : in.x;
+      const double c2 = in.x2 ? cf : 0.0;
       double v[GPT];
 #pragma unroll
       for (int u = 0; u < GPT; ++u) {
-        const int q = tid + u * kEB;
-        double t = 0.0;
-        if (q < nq) {
-          t = in.x[(int64_t)gi[u] * R + col];
-          if (in.x2) t = fma(cf, in.x2[(int64_t)gi[u] * R + col], t);
-          if (dscale) t *= dscale[gi[u]];
-        }
+        const int64_t g = (int64_t)gi[u] * R + col;
+        double t = fma(c2, x2[g], in.x[g]);
+        if (DS) t *= dscale[gi[u]];
         v[u] = t;
       }
 #pragma unroll
       for (int u = 0; u < GPT; ++u) {
         const int q = tid + u * kEB;
-        if (q < nq) {
+        if (q < NL * kEPB) {   // only the last batch can pass the end (NL * 64 not a multiple of 256)
           const int e = q / NL, j = q - e * NL;
           w[j * kWS + e] = (T)v[u];
         }
@@ -130,28 +128,19 @@ __global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* _
       T acc[RPW];
 #pragma unroll
       for (int k = 0; k < RPW; ++k) acc[k] = (T)0;
-      if (FORM == FORM_SCALED) {
 #pragma unroll
-        for (int j = 0; j < NL; ++j) {
-          const T wj = w[j * kWS + lane];
+      for (int j = 0; j < NL; ++j) {
+        const T wj = w[j * kWS + lane];
 #pragma unroll
-          for (int k = 0; k < RPW; ++k) acc[k] = fma((T)A[row[k] * NL + j], wj, acc[k]);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < NL; ++j) {
-          const T wj = w[j * kWS + lane];
-#pragma unroll
-          for (int k = 0; k < RPW; ++k) acc[k] = fma(ap[(int64_t)packed_index(row[k], j) * E + K], wj, acc[k]);
-        }
+        for (int k = 0; k < RPW; ++k) acc[k] = fma((T)A[row[k] * NL + j], wj, acc[k]);
       }
 #pragma unroll
       for (int k = 0; k < RPW; ++k) {
         const int i = wv + 4 * k;
         if (i < NL) {
           T v = acc[k];
-          if (FORM == FORM_SCALED) v *= (T)ck;
-          zb[((int64_t)i * E + K) * R + col] = (ZT)v;
+          v *= (T)ck;
+          zb[((int64_t)i * E + K) * R + col] = v;
         }
       }
     }
@@ -162,137 +151,217 @@ __global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* _
 // ---------------------------------------------------------------------------
 // reduce pass, optionally fused with a CG update
 // ---------------------------------------------------------------------------
-// One work-group per row chunk: up to kChunkRows consecutive conforming DOFs
-// and their broken copies (at most kChunkCap): all threads load the chunk's
-// slot list and then one broken value per copy into LDS (independent loads,
-// so long rows do not serialise); each thread then sums its rows' copies from
-// LDS in transpose-map order.
+// y_i = scale_i * sum of DOF i's broken copies, in the fixed order of the
+// transpose map.  Work is cut into row chunks of at most kChunkRows
+// consecutive conforming DOFs and kChunkCap copies; a grid of at most
+// kMaxReduceBlocks work-groups strides over the chunks, so the per-block dot
+// product partials stay few.  The fused epilogues:
+//   OUT_MASS_CG  p_new = z + beta p (the element pass used the same p_new),
+//                q = M p_new, partial p_new.q
+//   OUT_BRAS_CG  r_new = r - alpha q, x += alpha p, z = C r_new, partials
+//                r_new.r_new, r_new.z and (flexible) r_new.z_old
 constexpr int kChunkRows = 512;
 constexpr int kChunkCap = 2048;
 constexpr int kRowsPerThread = kChunkRows / kBS;
+constexpr int kMaxReduceBlocks = 2048;    // several columns
+constexpr int kMaxReduceBlocks1 = 16384;  // one column
 
+// CG epilogue of one output entry t (column col, sum acc); accumulates dots
+template <int OUT>
+__device__ __forceinline__ void reduce_epilogue(int64_t t, double acc, double coef, const CgArgs& cg, double* y,
+                                                const double* dotv, double& d0, double& d1, double& d2) {
+  if (OUT == OUT_PLAIN) {
+    y[t] = acc;
+    if (dotv) d0 = fma(acc, dotv[t], d0);
+  } else if (OUT == OUT_MASS_CG) {
+    const double pn = fma(coef, cg.p[t], cg.z[t]);
+    cg.p[t] = pn;
+    cg.q[t] = acc;
+    d0 = fma(pn, acc, d0);
+  } else {
+    const double rn = fma(-coef, cg.q[t], cg.r[t]);
+    cg.x[t] = fma(coef, cg.p[t], cg.x[t]);
+    if (cg.flexible) d2 = fma(rn, cg.z[t], d2);
+    cg.z[t] = acc;
+    cg.r[t] = rn;
+    d0 = fma(rn, rn, d0);
+    d1 = fma(rn, acc, d1);
+  }
+}
+
+// One column: all threads load a chunk's broken values into LDS (independent
+// loads, so long rows do not serialise), then each thread sums its rows.
 template <typename ZT, int OUT>
-__global__ void __launch_bounds__(kBS) k_reduce(int R, const int32_t* __restrict__ chunk,
+__global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __restrict__ chunk,
                                                 const int32_t* __restrict__ rowptr,
                                                 const int32_t* __restrict__ slot, const ZT* __restrict__ zb,
                                                 const double* __restrict__ scale, double* __restrict__ y,
                                                 const double* __restrict__ dotv, double* __restrict__ partial,
                                                 CgArgs cg) {
-  __shared__ int32_t sl[kChunkCap];
   __shared__ double vals[kChunkCap];
   __shared__ double sh0[kBS], sh1[kBS], sh2[kBS];
-  if (OUT != OUT_PLAIN) {
-    bool any = false;
-    for (int c = 0; c < R; ++c) any = any || cg.ic[I_ACTIVE * R + c];
-    if (!any) return;   // uniform across the grid
-  }
+  if (OUT != OUT_PLAIN && !cg.ic[I_ACTIVE]) return;   // uniform across the grid
+  const double coef = OUT == OUT_MASS_CG ? cg.sc[S_BETA] : (OUT == OUT_BRAS_CG ? cg.sc[S_ALPHA] : 0.0);
   const int tid = threadIdx.x;
-  const int32_t i0 = chunk[blockIdx.x], i1 = chunk[blockIdx.x + 1];
-  const int32_t p0 = rowptr[i0], p1 = rowptr[i1];
-  const int cnt = p1 - p0;
-  const bool big = cnt > kChunkCap;   // a single row longer than the chunk capacity
   constexpr int LPT = kChunkCap / kBS;   // copies per thread
-  if (!big) {
-    int32_t sv[LPT];
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int32_t i0 = chunk[ch], i1 = chunk[ch + 1];
+    const int32_t p0 = rowptr[i0];
+    const int cnt = rowptr[i1] - p0;
+    const bool big = cnt > kChunkCap;   // a single row longer than the chunk capacity
+    if (!big) {
+      int32_t sv[LPT];
 #pragma unroll
-    for (int u = 0; u < LPT; ++u) {
-      const int t = tid + u * kBS;
-      sv[u] = t < cnt ? slot[p0 + t] : 0;
-    }
+      for (int u = 0; u < LPT; ++u) {
+        const int t = tid + u * kBS;
+        sv[u] = t < cnt ? slot[p0 + t] : 0;
+      }
+      double vv[LPT];
 #pragma unroll
-    for (int u = 0; u < LPT; ++u) {
-      const int t = tid + u * kBS;
-      if (t < cnt) sl[t] = sv[u];
+      for (int u = 0; u < LPT; ++u) {
+        const int t = tid + u * kBS;
+        vv[u] = t < cnt ? (double)zb[sv[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < LPT; ++u) {
+        const int t = tid + u * kBS;
+        if (t < cnt) vals[t] = vv[u];
+      }
     }
+    int32_t ra[kRowsPerThread], rb[kRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; ++k) {
+      const int32_t i = i0 + tid + k * kBS;
+      const bool own = i < i1;
+      ra[k] = own ? rowptr[i] - p0 : 0;
+      rb[k] = own ? rowptr[i + 1] - p0 : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; ++k) {
+      const int32_t i = i0 + tid + k * kBS;
+      if (i >= i1) continue;
+      double acc = 0.0;
+      if (!big)
+        for (int32_t q = ra[k]; q < rb[k]; ++q) acc += vals[q];
+      else
+        for (int32_t q = ra[k]; q < rb[k]; ++q) acc += (double)zb[slot[p0 + q]];
+      if (scale) acc *= scale[i];
+      reduce_epilogue<OUT>(i, acc, coef, cg, y, dotv, d0, d1, d2);
+    }
+    __syncthreads();
   }
-  int32_t ra[kRowsPerThread], rb[kRowsPerThread];
-  double scv[kRowsPerThread];
-#pragma unroll
-  for (int k = 0; k < kRowsPerThread; ++k) {
-    const int32_t i = i0 + tid + k * kBS;
-    const bool own = i < i1;
-    ra[k] = own ? rowptr[i] - p0 : 0;
-    rb[k] = own ? rowptr[i + 1] - p0 : 0;
-    scv[k] = (own && scale) ? scale[i] : 1.0;
+  // partials of this block (fixed tree order)
+  double* out0 = OUT == OUT_PLAIN ? partial : cg.part0;
+  if (OUT == OUT_PLAIN && !(dotv && partial)) return;
+  sh0[tid] = d0;
+  if (OUT == OUT_BRAS_CG) {
+    sh1[tid] = d1;
+    sh2[tid] = d2;
   }
   __syncthreads();
-  for (int col = 0; col < R; ++col) {
-    const bool act = OUT == OUT_PLAIN ? true : cg.ic[I_ACTIVE * R + col] != 0;
-    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-    if (act) {
-      if (!big) {
-        double vv[LPT];
-#pragma unroll
-        for (int u = 0; u < LPT; ++u) {
-          const int t = tid + u * kBS;
-          vv[u] = t < cnt ? (double)zb[(int64_t)sl[t] * R + col] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < LPT; ++u) {
-          const int t = tid + u * kBS;
-          if (t < cnt) vals[t] = vv[u];
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k) {
-        const int32_t i = i0 + tid + k * kBS;
-        if (i >= i1) continue;
-        double acc = 0.0;
-        if (!big)
-          for (int32_t q = ra[k]; q < rb[k]; ++q) acc += vals[q];
-        else
-          for (int32_t q = ra[k]; q < rb[k]; ++q) acc += (double)zb[(int64_t)slot[p0 + q] * R + col];
-        acc *= scv[k];
-        const int64_t t = (int64_t)i * R + col;
-        if (OUT == OUT_PLAIN) {
-          y[t] = acc;
-          if (dotv) d0 = fma(acc, dotv[t], d0);
-        } else if (OUT == OUT_MASS_CG) {
-          // q = M p_new with p_new = z + beta p_old (the element pass used the same p_new)
-          const double pn = fma(cg.sc[S_BETA * R + col], cg.p[t], cg.z[t]);
-          cg.p[t] = pn;
-          cg.q[t] = acc;
-          d0 = fma(pn, acc, d0);
-        } else {
-          // z_new = C r_new with r_new = r - alpha q; x += alpha p
-          const double al = cg.sc[S_ALPHA * R + col];
-          const double rn = fma(-al, cg.q[t], cg.r[t]);
-          cg.x[t] = fma(al, cg.p[t], cg.x[t]);
-          if (cg.flexible) d2 = fma(rn, cg.z[t], d2);
-          cg.z[t] = acc;
-          cg.r[t] = rn;
-          d0 = fma(rn, rn, d0);
-          d1 = fma(rn, acc, d1);
-        }
+  for (int off = kBS / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      sh0[tid] += sh0[tid + off];
+      if (OUT == OUT_BRAS_CG) {
+        sh1[tid] += sh1[tid + off];
+        sh2[tid] += sh2[tid + off];
       }
     }
-    // per-column partials of this block (fixed tree order)
-    double* out0 = OUT == OUT_PLAIN ? partial : cg.part0;
-    if (out0 && (OUT != OUT_PLAIN || dotv)) {
-      sh0[tid] = d0;
-      if (OUT == OUT_BRAS_CG) {
-        sh1[tid] = d1;
-        sh2[tid] = d2;
-      }
-      __syncthreads();
-      for (int off = kBS / 2; off > 0; off >>= 1) {
-        if (tid < off) {
-          sh0[tid] += sh0[tid + off];
-          if (OUT == OUT_BRAS_CG) {
-            sh1[tid] += sh1[tid + off];
-            sh2[tid] += sh2[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out0[blockIdx.x] = sh0[0];
+    if (OUT == OUT_BRAS_CG) {
+      cg.part1[blockIdx.x] = sh1[0];
+      if (cg.flexible) cg.part2[blockIdx.x] = sh2[0];
+    }
+  }
+}
+
+// Several columns (R >= 2): thread t owns column t % R of rows t / R,
+// t / R + 256 / R, ... of each chunk, so consecutive threads read the
+// consecutive columns of one broken copy; a row's copies are summed in
+// transpose-map order as in the one-column pass.
+template <typename ZT, int OUT>
+__global__ void __launch_bounds__(kBS) k_reduce_mc(int R, int nchunk, const int32_t* __restrict__ chunk,
+                                                   const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ slot, const ZT* __restrict__ zb,
+                                                   const double* __restrict__ scale, double* __restrict__ y,
+                                                   const double* __restrict__ dotv, double* __restrict__ partial,
+                                                   CgArgs cg) {
+  __shared__ int32_t sl[kChunkCap];
+  __shared__ int32_t rp[kChunkRows + 1];
+  __shared__ double sh[kBS];
+  __shared__ double coef_s[256];
+  __shared__ int act_s[256];
+  const int tid = threadIdx.x;
+  for (int c = tid; c < R; c += kBS) {
+    act_s[c] = OUT == OUT_PLAIN ? 1 : cg.ic[I_ACTIVE * R + c];
+    coef_s[c] = OUT == OUT_MASS_CG ? cg.sc[S_BETA * R + c] : (OUT == OUT_BRAS_CG ? cg.sc[S_ALPHA * R + c] : 0.0);
+  }
+  __syncthreads();
+  {
+    bool any = false;
+    for (int c = 0; c < R; ++c) any = any || act_s[c];
+    if (!any) return;   // uniform across the grid
+  }
+  const int G = kBS / R;          // rows per pass (R <= 256)
+  const bool mine = tid < G * R;
+  const int col = mine ? tid % R : 0, g = tid / R;
+  const bool act = mine && act_s[col];
+  const double coef = coef_s[col];
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int32_t i0 = chunk[ch], i1 = chunk[ch + 1];
+    const int nr = i1 - i0;
+    const int32_t p0 = rowptr[i0];
+    const int cnt = rowptr[i1] - p0;
+    const bool big = cnt > kChunkCap;
+    if (!big)
+      for (int t = tid; t < cnt; t += kBS) sl[t] = slot[p0 + t];
+    for (int t = tid; t <= nr; t += kBS) rp[t] = rowptr[i0 + t] - p0;
+    __syncthreads();
+    if (act) {
+      for (int r = g; r < nr; r += G) {
+        const int a = rp[r], b = rp[r + 1];
+        double acc = 0.0;
+        int q = a;
+        for (; q + 4 <= b; q += 4) {
+          double v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t s = big ? slot[p0 + q + u] : sl[q + u];
+            v[u] = (double)zb[s * R + col];
           }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc += v[u];
         }
-        __syncthreads();
-      }
-      if (tid == 0) {
-        out0[(int64_t)blockIdx.x * R + col] = sh0[0];
-        if (OUT == OUT_BRAS_CG) {
-          cg.part1[(int64_t)blockIdx.x * R + col] = sh1[0];
-          if (cg.flexible) cg.part2[(int64_t)blockIdx.x * R + col] = sh2[0];
+        for (; q < b; ++q) {
+          const int64_t s = big ? slot[p0 + q] : sl[q];
+          acc += (double)zb[s * R + col];
         }
+        const int64_t i = i0 + r;
+        if (scale) acc *= scale[i];
+        reduce_epilogue<OUT>(i * R + col, acc, coef, cg, y, dotv, d0, d1, d2);
       }
+    }
+    __syncthreads();
+  }
+  // per-column partials: thread c adds the row groups' sums in order
+  double* out0 = OUT == OUT_PLAIN ? partial : cg.part0;
+  if (OUT == OUT_PLAIN && !(dotv && partial)) return;
+  double* outs[3] = {out0, cg.part1, cg.part2};
+  const double ds[3] = {d0, d1, d2};
+  const int nd = OUT == OUT_BRAS_CG ? (cg.flexible ? 3 : 2) : 1;
+  for (int k = 0; k < nd; ++k) {
+    sh[tid] = ds[k];
+    __syncthreads();
+    if (tid < R) {
+      double v = 0.0;
+      for (int gg = 0; gg < G; ++gg) v += sh[gg * R + tid];
+      outs[k][(int64_t)blockIdx.x * R + tid] = v;
     }
     __syncthreads();
   }
@@ -428,49 +497,25 @@ int vector_blocks(Ctx* c, int R) {
 
 #define NL_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(21) X(24) X(28) X(35) X(36) X(45) X(56) X(70) X(84)
 
-template <int NL, int FORM, typename T, typename ZT>
+template <int NL>
 static int elem_launch(Ctx* c, int R, const InArgs& in, const double* dscale, const double* A, const double* coefK,
-                       const T* ap, ZT* zb, hipStream_t s) {
+                       double* zb, hipStream_t s) {
   const unsigned nb = (unsigned)((c->E + kEPB - 1) / kEPB);
-  k_elem<NL, FORM, T, ZT><<<nb, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, ap, zb);
+  if (dscale)
+    k_elem<NL, true><<<nb, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, zb);
+  else
+    k_elem<NL, false><<<nb, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, zb);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
 
-template <int FORM, typename T, typename ZT>
-static int elem_dispatch(Ctx* c, int R, const InArgs& in, const double* dscale, const double* A,
-                         const double* coefK, const T* ap, ZT* zb, hipStream_t s) {
+static int scaled_dispatch(Ctx* c, int R, const InArgs& in, const double* dscale, const double* A,
+                           const double* coefK, double* zb, hipStream_t s) {
 #define CASE(N) \
-  case N: return elem_launch<N, FORM, T, ZT>(c, R, in, dscale, A, coefK, ap, zb, s);
+  case N: return elem_launch<N>(c, R, in, dscale, A, coefK, zb, s);
   switch (c->nl) {
     NL_CASES(CASE)
     default: return fail(BRAS_EINVAL, "n_loc %d has no element kernel", c->nl);
-  }
-#undef CASE
-}
-
-#define LANE_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(21) X(24) X(28) X(35) X(36)
-
-// work-group size of the per-lane element pass: one wavefront
-constexpr int lane_epb(int) { return 64; }
-
-template <int NL, int FORM, int NSYM, typename T, typename ZT>
-static int lane_launch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {
-  constexpr int EPB = lane_epb(FORM);
-  const unsigned nb = (unsigned)((c->E + EPB - 1) / EPB);
-  k_elem_lane<NL, FORM, NSYM, T, ZT, EPB><<<nb, EPB, 0, s>>>(c->E, R, c->l2g, in, c->symtab, c->coef, c->nsym, ap,
-                                                              zb);
-  BRAS_HIP(hipGetLastError());
-  return BRAS_OK;
-}
-
-template <int FORM, int NSYM, typename T, typename ZT>
-static int lane_dispatch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {
-#define CASE(N) \
-  case N: return lane_launch<N, FORM, NSYM, T, ZT>(c, R, in, ap, zb, s);
-  switch (c->nl) {
-    LANE_CASES(CASE)
-    default: return fail(BRAS_EINVAL, "n_loc %d has no per-lane element kernel", c->nl);
   }
 #undef CASE
 }
@@ -479,46 +524,50 @@ static int lane_dispatch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, h
 static int mass_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
   double* zb = (double*)c->zb;
   if (c->form == BRAS_ELEM_SCALED_REF)
-    return elem_dispatch<FORM_SCALED, double, double>(c, R, in, nullptr, c->ref, c->coef, nullptr, zb, s);
+    return scaled_dispatch(c, R, in, nullptr, c->ref, c->coef, zb, s);
   if (c->mpack) {
-    if (c->nl <= kLaneMaxNL) return lane_dispatch<FORM_PACKED, 0, double, double>(c, R, in, c->mpack, zb, s);
-    return elem_dispatch<FORM_PACKED, double, double>(c, R, in, nullptr, nullptr, nullptr, c->mpack, zb, s);
+    if (c->nl <= kLaneMaxNL) return lane_packed_f64(c, R, in, c->mpack, zb, s);
+    return mfma_elem_f64(c, R, in, c->mpack, zb, s);
   }
   // metric tables (setup keeps them only for n_loc <= kLaneMaxNL)
-  if (c->nsym <= 3) return lane_dispatch<FORM_METRIC, 3, double, double>(c, R, in, nullptr, zb, s);
-  return lane_dispatch<FORM_METRIC, 6, double, double>(c, R, in, nullptr, zb, s);
+  if (c->nsym <= 3) return lane_metric3(c, R, in, zb, s);
+  return lane_metric6(c, R, in, zb, s);
 }
 
 // element pass of the BRAS operator; reports whether the broken vector is float32
 static int bras_elem(Ctx* c, const InArgs& in, int R, hipStream_t s, bool* zb_float) {
   *zb_float = false;
   if (c->form == BRAS_ELEM_SCALED_REF)
-    return elem_dispatch<FORM_SCALED, double, double>(c, R, in, c->invd, c->refinv, c->icoef, nullptr,
-                                                       (double*)c->zb, s);
+    return scaled_dispatch(c, R, in, c->invd, c->refinv, c->icoef, (double*)c->zb, s);
   const bool lane = c->nl <= kLaneMaxNL;
   if (c->prec == BRAS_FP64) {
-    if (lane) return lane_dispatch<FORM_PACKED, 0, double, double>(c, R, in, (const double*)c->ainv, (double*)c->zb, s);
-    return elem_dispatch<FORM_PACKED, double, double>(c, R, in, nullptr, nullptr, nullptr, (const double*)c->ainv,
-                                                       (double*)c->zb, s);
+    if (lane) return lane_packed_f64(c, R, in, (const double*)c->ainv, (double*)c->zb, s);
+    return mfma_elem_f64(c, R, in, (const double*)c->ainv, (double*)c->zb, s);
   }
   *zb_float = true;
-  if (lane) return lane_dispatch<FORM_PACKED, 0, float, float>(c, R, in, (const float*)c->ainv, (float*)c->zb, s);
-  return elem_dispatch<FORM_PACKED, float, float>(c, R, in, nullptr, nullptr, nullptr, (const float*)c->ainv,
-                                                   (float*)c->zb, s);
+  if (lane) return lane_packed_f32(c, R, in, (const float*)c->ainv, (float*)c->zb, s);
+  return mfma_elem_f32(c, R, in, (const float*)c->ainv, (float*)c->zb, s);
 }
 
 template <typename ZT, int OUT>
 static int reduce_launch(Ctx* c, const ZT* zb, const double* scale, double* y, int R, hipStream_t s,
                          const double* dotv, double* partial, const CgArgs& cg) {
-  k_reduce<ZT, OUT><<<(unsigned)c->nchunk, kBS, 0, s>>>(R, c->chunk, c->rowptr, c->slot, zb, scale, y, dotv, partial,
-                                                        cg);
+  const unsigned nb = (unsigned)reduce_blocks(c, R);
+  if (R == 1)
+    k_reduce<ZT, OUT><<<nb, kBS, 0, s>>>((int)c->nchunk, c->chunk, c->rowptr, c->slot, zb, scale, y, dotv, partial,
+                                         cg);
+  else
+    k_reduce_mc<ZT, OUT><<<nb, kBS, 0, s>>>(R, (int)c->nchunk, c->chunk, c->rowptr, c->slot, zb, scale, y, dotv,
+                                            partial, cg);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
 
 int reduce_blocks(Ctx* c, int R) {
-  (void)R;
-  return c->nchunk;
+  // one column: one work-group per chunk up to a large cap (latency hiding);
+  // several columns: fewer, longer-lived work-groups and fewer partials
+  const int64_t cap = R == 1 ? kMaxReduceBlocks1 : kMaxReduceBlocks;
+  return (int)(c->nchunk < cap ? c->nchunk : cap);
 }
 
 int reduce_float_plain(Ctx* c, const float* zb, double* y, int R, hipStream_t s, const double* dotv,

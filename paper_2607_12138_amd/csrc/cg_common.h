@@ -68,45 +68,44 @@ __device__ inline double block_sum(const double* partial, int nb, int R, int col
   return v;
 }
 
-// Three fixed-order sums at once (c may be null): one pass over the partials.
-// sh must hold 3 * blockDim.x doubles.
-__device__ inline void block_sum3(const double* a, const double* b, const double* c, int nb, int R, int col,
-                                  double* sh, double* ra, double* rb, double* rc) {
-  double sa = 0.0, sb = 0.0, scv = 0.0;
-  for (int k0 = 0; k0 < nb; k0 += 4 * (int)blockDim.x) {
-    double va[4], vb[4], vc[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + (int)threadIdx.x + u * (int)blockDim.x;
-      const bool ok = k < nb;
-      va[u] = ok ? a[(int64_t)k * R + col] : 0.0;
-      vb[u] = ok ? b[(int64_t)k * R + col] : 0.0;
-      vc[u] = (ok && c) ? c[(int64_t)k * R + col] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      sa += va[u];
-      sb += vb[u];
-      scv += vc[u];
-    }
-  }
-  // three trees side by side in sh[0..3*blockDim)
+// Fixed-order sums of part[b*R + c], b < nb, for every column c, by one
+// block; out (shared memory, R entries) receives them.  sh holds blockDim.x
+// doubles.  With one column (or more columns than threads) each column is
+// summed by block_sum; otherwise thread t takes column t % R and every
+// (blockDim/R)-th partial, and thread c then adds the per-thread sums of
+// column c in thread order.
+__device__ inline void block_sums_all(const double* part, int nb, int R, double* out, double* sh) {
   const int bs = blockDim.x, t = threadIdx.x;
-  sh[t] = sa;
-  sh[bs + t] = sb;
-  sh[2 * bs + t] = scv;
-  __syncthreads();
-  for (int off = bs / 2; off > 0; off >>= 1) {
-    if (t < off) {
-      sh[t] += sh[t + off];
-      sh[bs + t] += sh[bs + t + off];
-      sh[2 * bs + t] += sh[2 * bs + t + off];
+  if (R == 1 || R > bs) {
+    for (int col = 0; col < R; ++col) {
+      const double v = block_sum(part, nb, R, col, sh);
+      if (t == 0) out[col] = v;
     }
     __syncthreads();
+    return;
   }
-  *ra = sh[0];
-  *rb = sh[bs];
-  *rc = c ? sh[2 * bs] : 0.0;
+  const int G = bs / R;
+  double s = 0.0;
+  if (t < G * R) {
+    const int col = t % R, g = t / R;
+    for (int b0 = g; b0 < nb; b0 += 8 * G) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + u * G;
+        v[u] = b < nb ? part[(int64_t)b * R + col] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+  }
+  sh[t] = s;
+  __syncthreads();
+  if (t < R) {
+    double v = 0.0;
+    for (int g = 0; g < G; ++g) v += sh[g * R + t];
+    out[t] = v;
+  }
   __syncthreads();
 }
 
@@ -115,66 +114,65 @@ __device__ inline void block_sum3(const double* a, const double* b, const double
 // derives the same values from the same partials.
 __device__ inline void alpha_prologue(const double* apart, int anb, int R, double* sc, int* ic, double* coef,
                                       int* act, double* sh) {
-  for (int col = 0; col < R; ++col) {
-    const int a0 = ic[I_ACTIVE * R + col];
-    double pq = 0.0;
-    if (a0) pq = block_sum(apart, anb, R, col, sh);
-    if (threadIdx.x == 0) {
-      if (!a0) {
-        coef[col] = 0.0;
-        act[col] = 0;
-      } else if (!(pq > 0.0) || !isfinite(pq)) {
-        coef[col] = 0.0;
-        act[col] = 0;
-        if (blockIdx.x == 0) {
-          ic[I_ACTIVE * R + col] = 0;
-          ic[I_STATUS * R + col] = ST_BREAK;
-        }
-      } else {
-        const double a = sc[S_RZ * R + col] / pq;
-        coef[col] = a;
-        act[col] = 1;
-        if (blockIdx.x == 0) sc[S_ALPHA * R + col] = a;
+  block_sums_all(apart, anb, R, coef, sh);   // coef[c] = p.q for now
+  for (int col = threadIdx.x; col < R; col += blockDim.x) {
+    const double pq = coef[col];
+    if (!ic[I_ACTIVE * R + col]) {
+      coef[col] = 0.0;
+      act[col] = 0;
+    } else if (!(pq > 0.0) || !isfinite(pq)) {
+      coef[col] = 0.0;
+      act[col] = 0;
+      if (blockIdx.x == 0) {
+        ic[I_ACTIVE * R + col] = 0;
+        ic[I_STATUS * R + col] = ST_BREAK;
       }
+    } else {
+      const double a = sc[S_RZ * R + col] / pq;
+      coef[col] = a;
+      act[col] = 1;
+      if (blockIdx.x == 0) sc[S_ALPHA * R + col] = a;
     }
   }
   __syncthreads();
 }
 
 // Convergence test on the updated recursive residual, then beta and rho
-// (one block, after the residual / preconditioner pass).
+// (one block, after the residual / preconditioner pass).  rr, rz, rzo: shared
+// memory of R entries each; sh: blockDim.x doubles.
 __device__ inline void finish_iteration(const double* part0, const double* part1, const double* part2, int nb,
-                                        int R, double* sc, int* ic, int flexible, int maxit, double* sh) {
-  for (int col = 0; col < R; ++col) {
+                                        int R, double* sc, int* ic, int flexible, int maxit, double* sh, double* rr,
+                                        double* rz, double* rzo) {
+  block_sums_all(part0, nb, R, rr, sh);
+  block_sums_all(part1, nb, R, rz, sh);
+  if (flexible) block_sums_all(part2, nb, R, rzo, sh);
+  for (int col = threadIdx.x; col < R; col += blockDim.x) {
     if (!ic[I_ACTIVE * R + col]) continue;
-    double rr, rz, rzo;
-    block_sum3(part0, part1, flexible ? part2 : nullptr, nb, R, col, sh, &rr, &rz, &rzo);
-    if (threadIdx.x == 0) {
-      const int it = ic[I_ITERS * R + col] + 1;
-      ic[I_ITERS * R + col] = it;
-      const double nrm = sqrt(rr);
-      sc[S_RR * R + col] = rr;
-      sc[S_RELRES * R + col] = nrm / sc[S_R0 * R + col];
-      const double old = sc[S_RZ * R + col];
-      if (!isfinite(nrm)) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_BREAK;
-      } else if (nrm <= sc[S_TARGET * R + col]) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_OK;
-      } else if (it >= maxit) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_NOCONV;
-      } else if (!(rz > 0.0) || !isfinite(rz)) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_BREAK;
-      } else {
-        sc[S_BETA * R + col] = flexible ? (rz - rzo) / old : rz / old;
-        sc[S_RZ * R + col] = rz;
-      }
+    const int it = ic[I_ITERS * R + col] + 1;
+    ic[I_ITERS * R + col] = it;
+    const double nrm = sqrt(rr[col]);
+    sc[S_RR * R + col] = rr[col];
+    sc[S_RELRES * R + col] = nrm / sc[S_R0 * R + col];
+    const double old = sc[S_RZ * R + col];
+    const double z = rz[col];
+    if (!isfinite(nrm)) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_BREAK;
+    } else if (nrm <= sc[S_TARGET * R + col]) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_OK;
+    } else if (it >= maxit) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_NOCONV;
+    } else if (!(z > 0.0) || !isfinite(z)) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_BREAK;
+    } else {
+      sc[S_BETA * R + col] = flexible ? (z - rzo[col]) / old : z / old;
+      sc[S_RZ * R + col] = z;
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 }  // namespace bras

@@ -5,6 +5,7 @@
 #include <utility>
 
 #include "cg_common.h"
+#include "internal.h"
 
 namespace bras {
 
@@ -227,5 +228,37 @@ __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32
     __syncthreads();
   }
 }
+
+#define LANE_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(21) X(24) X(28) X(35) X(36)
+
+template <int NL, int FORM, int NSYM, typename T, typename ZT>
+static int lane_launch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {
+  constexpr int EPB = 64;   // one wavefront per work-group
+  const unsigned nb = (unsigned)((c->E + EPB - 1) / EPB);
+  k_elem_lane<NL, FORM, NSYM, T, ZT, EPB><<<nb, EPB, 0, s>>>(c->E, R, c->l2g, in, c->symtab, c->coef, c->nsym, ap,
+                                                              zb);
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+template <int FORM, int NSYM, typename T, typename ZT>
+static int lane_dispatch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {
+#define CASE(N) \
+  case N: return lane_launch<N, FORM, NSYM, T, ZT>(c, R, in, ap, zb, s);
+  switch (c->nl) {
+    LANE_CASES(CASE)
+    default: return fail(BRAS_EINVAL, "n_loc %d has no per-lane element kernel", c->nl);
+  }
+#undef CASE
+}
+
+// One translation unit each (lane_*.hip), so they compile in parallel.
+int lane_packed_f64(Ctx* c, int R, const InArgs& in, const double* ap, double* zb, hipStream_t s);
+int lane_packed_f32(Ctx* c, int R, const InArgs& in, const float* ap, float* zb, hipStream_t s);
+int lane_metric3(Ctx* c, int R, const InArgs& in, double* zb, hipStream_t s);
+int lane_metric6(Ctx* c, int R, const InArgs& in, double* zb, hipStream_t s);
+// Per-element matrix-core pass for n_loc > kLaneMaxNL (elem_mfma.hip).
+int mfma_elem_f64(Ctx* c, int R, const InArgs& in, const double* mat, double* zb, hipStream_t s);
+int mfma_elem_f32(Ctx* c, int R, const InArgs& in, const float* mat, float* zb, hipStream_t s);
 
 }  // namespace bras

@@ -41,6 +41,7 @@ struct CgState;   // pcg.hip
 
 struct Ctx {
   int device = 0;
+  int ncu = 1;               // compute units of the device
   int64_t n = 0, E = 0, nbr = 0;
   int nl = 0;
   int form = 0, nsym = 0, prec = 0, max_rhs = 1;
@@ -66,8 +67,8 @@ struct Ctx {
   void* ainv = nullptr;      // METRIC/EXPLICIT: folded inverse, packed lower [npack][E] in prec,
                              // or (BF16) the Gram factor, packed lower, element-major [E][npack]
   size_t ainv_bytes = 0;
-  int agroup = 1;            // entry group of ainv (packed_group), 1 for the element-major BF16 factor
-  int mgroup = 1;            // entry group of mpack
+  int agroup = 0;            // layout of ainv (packed_group; 0 = element-major, also for the BF16 factor)
+  int mgroup = 0;            // layout of mpack
   double* symtab = nullptr;  // METRIC_REF, n_loc <= kLaneMaxNL: pair tables packed [npack][sym_stride(nsym)]
   double* mpack = nullptr;   // packed float64 M_K [npack][E] for the mass pass (EXPLICIT, or METRIC with
                              // n_loc > kLaneMaxNL)
@@ -86,12 +87,18 @@ inline int npack_of(int nl) { return nl * (nl + 1) / 2; }
 
 // Largest n_loc whose element passes keep a whole element in one lane's registers.
 constexpr int kLaneMaxNL = 36;
-// Packed per-element matrices are stored in groups of g consecutive entries q
-// (16 bytes when the per-lane pass reads them, else g = 1):
-// entry (q, K) at ((q / g) * E + K) * g + q % g, the entry count padded to a
-// multiple of g.
-inline int packed_group(int nl, size_t esz) { return nl <= kLaneMaxNL ? (int)(16 / esz) : 1; }
-inline size_t packed_slots(int nl, int g) { return (size_t)((npack_of(nl) + g - 1) / g) * g; }
+// Packed per-element matrices (q = i(i+1)/2 + j, i >= j) are stored either
+// in groups of g consecutive entries (g = 16 bytes / entry size, for the
+// per-lane pass, n_loc <= kLaneMaxNL): entry (q, K) at ((q / g) * E + K) * g
+// + q % g, the entry count padded to a multiple of g; or element-major (g = 0,
+// for the per-element passes): entry (q, K) at K * npack + q.
+inline int packed_group(int nl, size_t esz) { return nl <= kLaneMaxNL ? (int)(16 / esz) : 0; }
+inline size_t packed_slots(int nl, int g) {
+  return g == 0 ? (size_t)npack_of(nl) : (size_t)((npack_of(nl) + g - 1) / g) * g;
+}
+__host__ __device__ inline int64_t packed_at(int q, int64_t K, int64_t E, int g, int npk) {
+  return g == 0 ? K * npk + q : ((int64_t)(q / g) * E + K) * g + q % g;
+}
 // Row stride of the packed pair tables: 3 (up to 3 pairs, 2D) or 6 (3D), zero padded.
 inline int sym_stride(int nsym) { return nsym <= 3 ? 3 : 6; }
 

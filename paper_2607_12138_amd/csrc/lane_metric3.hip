@@ -1,0 +1,10 @@
+// Instantiations of the per-lane element pass (elem_lane.h).
+#include "elem_lane.h"
+
+namespace bras {
+
+int lane_metric3(Ctx* c, int R, const InArgs& in, double* zb, hipStream_t s) {
+  return lane_dispatch<FORM_METRIC, 3, double, double>(c, R, in, nullptr, zb, s);
+}
+
+}  // namespace bras

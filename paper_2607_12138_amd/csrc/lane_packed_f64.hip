@@ -1,0 +1,10 @@
+// Instantiations of the per-lane element pass (elem_lane.h).
+#include "elem_lane.h"
+
+namespace bras {
+
+int lane_packed_f64(Ctx* c, int R, const InArgs& in, const double* ap, double* zb, hipStream_t s) {
+  return lane_dispatch<FORM_PACKED, 0, double, double>(c, R, in, ap, zb, s);
+}
+
+}  // namespace bras

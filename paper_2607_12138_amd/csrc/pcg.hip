@@ -75,47 +75,48 @@ __global__ void __launch_bounds__(kBS) k_residual(int64_t n, int R, const double
 
 // Start (or restart) of CG.  restart == 0: r_0 norm and target are set from
 // this residual.  Columns already within target are stopped.
-__global__ void k_fin_init(int nb, int R, const double* __restrict__ part, double* __restrict__ sc,
-                           int* __restrict__ ic, double rtol, int restart) {
-  __shared__ double sh[kBS];
-  for (int col = 0; col < R; ++col) {
-    const double rr = block_sum(part, nb, R, col, sh);
-    if (threadIdx.x == 0) {
-      const double nrm = sqrt(rr);
-      if (!restart) {
-        sc[S_R0 * R + col] = nrm;
-        sc[S_TARGET * R + col] = rtol * nrm;
-        ic[I_ITERS * R + col] = 0;
-      }
-      sc[S_RR * R + col] = rr;
-      const double r0 = sc[S_R0 * R + col];
-      sc[S_RELRES * R + col] = r0 > 0.0 ? nrm / r0 : 0.0;
-      if (!isfinite(nrm)) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_BREAK;
-      } else if (nrm <= sc[S_TARGET * R + col] || nrm == 0.0) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_OK;
-      } else {
-        ic[I_ACTIVE * R + col] = 1;
-        ic[I_STATUS * R + col] = ST_RUN;
-      }
+__global__ void __launch_bounds__(kBS) k_fin_init(int nb, int R, const double* __restrict__ part,
+                                                  double* __restrict__ sc, int* __restrict__ ic, double rtol,
+                                                  int restart) {
+  __shared__ double sh[kBS], rr_s[256];
+  block_sums_all(part, nb, R, rr_s, sh);
+  for (int col = threadIdx.x; col < R; col += kBS) {
+    const double rr = rr_s[col];
+    const double nrm = sqrt(rr);
+    if (!restart) {
+      sc[S_R0 * R + col] = nrm;
+      sc[S_TARGET * R + col] = rtol * nrm;
+      ic[I_ITERS * R + col] = 0;
+    }
+    sc[S_RR * R + col] = rr;
+    const double r0 = sc[S_R0 * R + col];
+    sc[S_RELRES * R + col] = r0 > 0.0 ? nrm / r0 : 0.0;
+    if (!isfinite(nrm)) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_BREAK;
+    } else if (nrm <= sc[S_TARGET * R + col] || nrm == 0.0) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_OK;
+    } else {
+      ic[I_ACTIVE * R + col] = 1;
+      ic[I_STATUS * R + col] = ST_RUN;
     }
   }
 }
 
-// rho = r.z after the first preconditioner application; p = z happens in k_copy_active.
-__global__ void k_fin_rz(int nb, int R, const double* __restrict__ part, double* __restrict__ sc, int* __restrict__ ic) {
-  __shared__ double sh[kBS];
-  for (int col = 0; col < R; ++col) {
-    const double rz = block_sum(part, nb, R, col, sh);
-    if (threadIdx.x == 0 && ic[I_ACTIVE * R + col]) {
-      sc[S_RZ * R + col] = rz;
-      sc[S_BETA * R + col] = 0.0;
-      if (!(rz > 0.0) || !isfinite(rz)) {
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_BREAK;
-      }
+// rho = r.z after the first preconditioner application (p = 0, beta = 0).
+__global__ void __launch_bounds__(kBS) k_fin_rz(int nb, int R, const double* __restrict__ part,
+                                                double* __restrict__ sc, int* __restrict__ ic) {
+  __shared__ double sh[kBS], rz_s[256];
+  block_sums_all(part, nb, R, rz_s, sh);
+  for (int col = threadIdx.x; col < R; col += kBS) {
+    if (!ic[I_ACTIVE * R + col]) continue;
+    const double rz = rz_s[col];
+    sc[S_RZ * R + col] = rz;
+    sc[S_BETA * R + col] = 0.0;
+    if (!(rz > 0.0) || !isfinite(rz)) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_BREAK;
     }
   }
 }
@@ -129,22 +130,20 @@ __global__ void __launch_bounds__(kBS) k_zero(int64_t n, double* __restrict__ v)
 // alpha = rho / p.q for every running column (one block); used instead of the
 // consumers' prologue when every consumer work-group re-reading the partials
 // would cost more than this extra launch
-__global__ void k_fin_alpha(int nb, int R, const double* __restrict__ part, double* __restrict__ sc,
-                            int* __restrict__ ic) {
-  __shared__ double sh[kBS];
-  for (int col = 0; col < R; ++col) {
-    if (!ic[I_ACTIVE * R + col]) continue;   // uniform
-    const double pq = block_sum(part, nb, R, col, sh);
-    if (threadIdx.x == 0) {
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        sc[S_ALPHA * R + col] = 0.0;
-        ic[I_ACTIVE * R + col] = 0;
-        ic[I_STATUS * R + col] = ST_BREAK;
-      } else {
-        sc[S_ALPHA * R + col] = sc[S_RZ * R + col] / pq;
-      }
+__global__ void __launch_bounds__(kBS) k_fin_alpha(int nb, int R, const double* __restrict__ part,
+                                                   double* __restrict__ sc, int* __restrict__ ic) {
+  __shared__ double sh[kBS], pq_s[256];
+  block_sums_all(part, nb, R, pq_s, sh);
+  for (int col = threadIdx.x; col < R; col += kBS) {
+    if (!ic[I_ACTIVE * R + col]) continue;
+    const double pq = pq_s[col];
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      sc[S_ALPHA * R + col] = 0.0;
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_BREAK;
+    } else {
+      sc[S_ALPHA * R + col] = sc[S_RZ * R + col] / pq;
     }
-    __syncthreads();
   }
 }
 
@@ -153,22 +152,22 @@ __global__ void k_fin_alpha(int nb, int R, const double* __restrict__ part, doub
 constexpr double kPrologueReadsMax = 4.0e6;
 
 // convergence test, beta and rho after the preconditioner pass of an iteration
-__global__ void k_fin_iter(int nb, int R, const double* __restrict__ p0, const double* __restrict__ p1,
-                           const double* __restrict__ p2, double* __restrict__ sc, int* __restrict__ ic, int flexible,
-                           int maxit) {
-  __shared__ double sh[3 * kBS];
-  finish_iteration(p0, p1, p2, nb, R, sc, ic, flexible, maxit, sh);
+__global__ void __launch_bounds__(kBS) k_fin_iter(int nb, int R, const double* __restrict__ p0,
+                                                  const double* __restrict__ p1, const double* __restrict__ p2,
+                                                  double* __restrict__ sc, int* __restrict__ ic, int flexible,
+                                                  int maxit) {
+  __shared__ double sh[kBS], rr[256], rz[256], rzo[256];
+  finish_iteration(p0, p1, p2, nb, R, sc, ic, flexible, maxit, sh, rr, rz, rzo);
 }
 
 // true residual norm at exit: relres = ||b - M x|| / ||r_0||
-__global__ void k_fin_true(int nb, int R, const double* __restrict__ part, double* __restrict__ sc) {
-  __shared__ double sh[kBS];
-  for (int col = 0; col < R; ++col) {
-    const double rr = block_sum(part, nb, R, col, sh);
-    if (threadIdx.x == 0) {
-      const double r0 = sc[S_R0 * R + col];
-      sc[S_RELRES * R + col] = r0 > 0.0 ? sqrt(rr) / r0 : 0.0;
-    }
+__global__ void __launch_bounds__(kBS) k_fin_true(int nb, int R, const double* __restrict__ part,
+                                                  double* __restrict__ sc) {
+  __shared__ double sh[kBS], rr_s[256];
+  block_sums_all(part, nb, R, rr_s, sh);
+  for (int col = threadIdx.x; col < R; col += kBS) {
+    const double r0 = sc[S_R0 * R + col];
+    sc[S_RELRES * R + col] = r0 > 0.0 ? sqrt(rr_s[col]) / r0 : 0.0;
   }
 }
 

@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
   __shared__ int bad;
   const int64_t K = blockIdx.x;
   const int t = threadIdx.x, nt = blockDim.x;
-  const int npk = nl * (nl + 1) / 2;   // packed lower triangle, stored [q][E]
+  const int npk = nl * (nl + 1) / 2;   // packed lower triangle (layout: packed_at)
   if (t == 0) bad = 0;
   if (mode == 0 && t < nsym) g[t] = Gsoa[(int64_t)t * E + K];
   for (int l = t; l < nl; l += nt) dinv[l] = invd[l2g[K * nl + l]];
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
       v = Mexp[K * nn + i * nl + j];
     }
     A[i * nl + j] = v;
-    if (mpack) mpack[((int64_t)(q / mg) * E + K) * mg + q % mg] = v;
+    if (mpack) mpack[packed_at(q, K, E, mg, npk)] = v;
     if (i == j) diagb[(int64_t)i * E + K] = v;
   }
   __syncthreads();
@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
     unpack_lower(q, i, j);
     double s = 0.0;
     for (int k = i; k < nl; ++k) s += A[k * nl + i] * A[k * nl + j];
-    out[((int64_t)(q / og) * E + K) * og + q % og] = cast_out<T>(s * dinv[i] * dinv[j]);
+    out[packed_at(q, K, E, og, npk)] = cast_out<T>(s * dinv[i] * dinv[j]);
   }
 }
 
@@ -583,9 +583,10 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
   c->nsym = form == BRAS_ELEM_METRIC_REF ? nsym : 0;
   c->prec = apply_prec;
   c->max_rhs = max_rhs;
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
     delete c;
-    return fail(BRAS_EHIP, "hipGetDevice failed");
+    return fail(BRAS_EHIP, "device query failed");
   }
   if (hipStreamCreateWithFlags(&c->s_int, hipStreamNonBlocking) != hipSuccess) {
     delete c;
@@ -703,6 +704,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
         k_pack_sym<<<blocks_for(cnt, 256), 256, 0, s>>>(c->ref, n_loc, c->nsym, ss, c->symtab);
         if (hipGetLastError() != hipSuccess) { free_ctx(c); return fail(BRAS_EHIP, "pair table packing failed"); }
       } else {
+        c->mgroup = 0;   // element-major, read by the per-element pass
         TRY(dalloc(&c->mpack, (size_t)npack_of(n_loc) * E));
       }
     } else {
@@ -715,7 +717,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
       }
     }
     size_t esz = apply_prec == BRAS_FP64 ? 8 : (apply_prec == BRAS_FP32 ? 4 : 2);
-    c->agroup = apply_prec == BRAS_BF16 ? 1 : packed_group(n_loc, esz);
+    c->agroup = apply_prec == BRAS_BF16 ? 0 : packed_group(n_loc, esz);
     c->ainv_bytes = esz * packed_slots(n_loc, c->agroup) * E;
     TRY(dalloc((char**)&c->ainv, c->ainv_bytes));
     if (hipMemsetAsync(c->ainv, 0, c->ainv_bytes, s) != hipSuccess) {
