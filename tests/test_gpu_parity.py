@@ -23,6 +23,7 @@ CASES = [
     ("RT", 3, 1, 5, 0.2, False, "f64"),
     ("RT", 3, 4, 2, 0.2, False, "f64"),
     ("RT", 2, 3, 6, 0.2, False, "f32"),
+    ("RT", 3, 4, 2, 0.2, False, "f32"),     # n_loc 70: FP32 inverses on the FP64 matrix cores
 ]
 
 _cache = {}
@@ -123,6 +124,29 @@ def test_multi_rhs_columns(case, R):
     # one column at a time gives bitwise the same as the batched call
     y0 = gpu.bras(to_t(np.ascontiguousarray(X[:, 1]))).cpu().numpy()
     assert rel_inf(y0, Yb[:, 1]) <= 1e-15
+
+
+# Column counts past the 32-column blocks of the matrix-core passes, past
+# one wavefront (per-lane passes), and not dividing the reduce block.
+MANY = [(CASES[9], 40), (CASES[11], 33), (CASES[5], 70), (CASES[2], 67)]
+
+
+@pytest.mark.parametrize("case,R", MANY, ids=lambda v: ids(v) if isinstance(v, tuple) else "R%d" % v)
+def test_many_columns(case, R):
+    orc, gpu = build(case, max_rhs=R)
+    X = workloads.rhs(orc.n, R, 78)
+    say("many columns R=%d %s" % (R, case))
+    Yb = gpu.bras(to_t(X)).cpu().numpy()
+    Ym = gpu.mass(to_t(X)).cpu().numpy()
+    tb = 1e-13 if case[6] == "f64" else 2e-4
+    for r in range(R):
+        assert rel_inf(Ym[:, r], orc.M @ X[:, r]) <= 1e-13
+        assert rel_inf(Yb[:, r], orc.B @ X[:, r]) <= tb
+    say("  pcg R=%d" % R)
+    X2, st, its, rel = gpu.solve(to_t(X), "bras", rtol=1e-8)
+    X2 = X2.cpu().numpy()
+    for r in range(0, R, 9):
+        assert np.linalg.norm(X[:, r] - orc.M @ X2[:, r]) <= 1.5e-8 * np.linalg.norm(X[:, r])
 
 
 @pytest.mark.parametrize("case", [CASES[2], CASES[6]], ids=ids)
@@ -236,10 +260,10 @@ BF16_CASES = [("RT", 3, 4, 2, 0.2, False, "bf16"), ("RT", 3, 2, 3, 0.2, False, "
 
 
 @pytest.mark.parametrize("case", BF16_CASES, ids=ids)
-@pytest.mark.parametrize("R", [32, 5])
+@pytest.mark.parametrize("R", [32, 5, 41])
 def test_bf16_gram_apply(case, R):
     from oracle import reduced
-    orc, gpu = build(case, max_rhs=32)
+    orc, gpu = build(case, max_rhs=48)
     X = workloads.rhs(orc.n, R, 61)
     say("bf16 apply R=%d %s" % (R, case))
     Y = gpu.bras(to_t(X)).cpu().numpy()
@@ -263,7 +287,7 @@ def test_bf16_gram_apply(case, R):
 @pytest.mark.parametrize("case", BF16_CASES[:2], ids=ids)
 def test_bf16_flexible_pcg(case):
     from paper_2607_12138_amd import _lib as L
-    orc, gpu = build(case, max_rhs=32)
+    orc, gpu = build(case, max_rhs=48)
     B = workloads.rhs(orc.n, 32, 62)
     say("bf16 flexible pcg %s" % (case,))
     X, st, its, rel = gpu.solve(to_t(B), "bras", rtol=1e-8)
