@@ -180,6 +180,7 @@ def main():
     t0 = time.perf_counter()
     prob = MassProblem(w.family, w.dim, w.degree, w.N, jitter=w.jitter, seed=w.mesh_seed, rho=rho, prec=w.prec,
                        max_rhs=w.nrhs)
+    variant = prob.autotune(w.nrhs)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print("setup done: n=%d E=%d n_loc=%d (%.1f s)" % (prob.n, prob.E, prob.n_loc, setup_s), file=sys.stderr,
@@ -241,6 +242,7 @@ def main():
                      "bytes_per_launch": int(nbytes), "us_per_launch": round(bras_us, 3)},
         "source_digest": source_digest(),
         "setup_s": round(setup_s, 3),
+        "element_pass_variant": int(variant),
     }
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)

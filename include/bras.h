@@ -203,7 +203,7 @@ int bras_rho_grad(bras_handle h, const double* x_d, const double* lam_d,
 #define BRAS_INFO_FORM     5
 #define BRAS_INFO_MAXRHS   6
 #define BRAS_INFO_RESTARTS 7   /* refinement restarts in the last pcg_solve     */
-#define BRAS_INFO_VARIANT  8   /* apply-kernel variant chosen by the autotuner  */
+#define BRAS_INFO_VARIANT  8   /* element-pass scheduling variant (-1: built-in) */
 int bras_info(bras_handle h, int what, int64_t* value_h);
 
 /* Copy derived setup data to device buffers for inspection:
@@ -219,12 +219,18 @@ int bras_export(bras_handle h, int what, void* dst_d, void* stream);
 
 #define BRAS_OPT_GRAPH_ITERS 0  /* CG iterations per captured graph (>= 1)     */
 #define BRAS_OPT_MAX_RESTART 1  /* refinement restarts allowed (>= 0)         */
-#define BRAS_OPT_VARIANT     2  /* force an apply-kernel variant (-1 = auto)   */
+#define BRAS_OPT_VARIANT     2  /* force a scheduling variant (-1 = built-in)  */
 int bras_set_option(bras_handle h, int opt, double value);
 
-/* Time the apply-kernel variants for this handle at nrhs columns on stream
- * and keep the fastest (per element family, order and precision).  The
- * result can be read back with BRAS_INFO_VARIANT.  Synchronous. */
+/* Time the element-pass scheduling variants this handle offers (3D H(curl) /
+ * H(div) metric-form mass passes with n_loc <= 36: row order in batches of 2
+ * or 4 table entries, diagonal order in batches of 8; every other handle has
+ * one) on one mass + one BRAS apply at nrhs columns on stream, and keep the
+ * fastest.  All variants compute the same products (the summation order of
+ * each M_K entry's pair terms is the same; the order in which entries are
+ * accumulated differs).  Read the choice back with BRAS_INFO_VARIANT; setting
+ * BRAS_OPT_VARIANT overrides it.  Allocates two [n][nrhs] scratch vectors
+ * for the duration of the call.  Synchronous. */
 int bras_autotune(bras_handle h, int nrhs, void* stream);
 
 const char* bras_last_error(void);

@@ -23,7 +23,9 @@ SOURCES = [
     ("lane_packed_f64.hip", []),
     ("lane_packed_f32.hip", []),
     ("lane_metric3.hip", []),
-    ("lane_metric6.hip", []),
+    ("lane_metric6_v0.hip", []),
+    ("lane_metric6_v1.hip", []),
+    ("lane_metric6_v2.hip", []),
     ("elem_mfma.hip", []),
     ("pcg.hip", []),
     ("bf16.hip", []),

@@ -190,7 +190,9 @@ __device__ __forceinline__ void reduce_epilogue(int64_t t, double acc, double co
 }
 
 // One column: all threads load a chunk's broken values into LDS (independent
-// loads, so long rows do not serialise), then each thread sums its rows.
+// loads, so long rows do not serialise), then each thread sums its rows.  The
+// row bounds and the vectors the epilogue reads are loaded together with the
+// chunk's slots, so a chunk costs two dependent memory round trips.
 template <typename ZT, int OUT>
 __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __restrict__ chunk,
                                                 const int32_t* __restrict__ rowptr,
@@ -204,19 +206,46 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
   const double coef = OUT == OUT_MASS_CG ? cg.sc[S_BETA] : (OUT == OUT_BRAS_CG ? cg.sc[S_ALPHA] : 0.0);
   const int tid = threadIdx.x;
   constexpr int LPT = kChunkCap / kBS;   // copies per thread
+  constexpr int NV = OUT == OUT_PLAIN ? 2 : (OUT == OUT_MASS_CG ? 2 : 6);   // epilogue operands per row
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
   for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
     const int32_t i0 = chunk[ch], i1 = chunk[ch + 1];
     const int32_t p0 = rowptr[i0];
     const int cnt = rowptr[i1] - p0;
     const bool big = cnt > kChunkCap;   // a single row longer than the chunk capacity
+    int32_t sv[LPT];
     if (!big) {
-      int32_t sv[LPT];
 #pragma unroll
       for (int u = 0; u < LPT; ++u) {
         const int t = tid + u * kBS;
         sv[u] = t < cnt ? slot[p0 + t] : 0;
       }
+    }
+    int32_t ra[kRowsPerThread], rb[kRowsPerThread];
+    double pre[kRowsPerThread][NV];
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; ++k) {
+      const int32_t i = i0 + tid + k * kBS;
+      const bool own = i < i1;
+      const int32_t ic = own ? i : i0;
+      ra[k] = own ? rowptr[ic] - p0 : 0;
+      rb[k] = own ? rowptr[ic + 1] - p0 : 0;
+      if (OUT == OUT_PLAIN) {
+        pre[k][0] = scale ? scale[ic] : 1.0;
+        pre[k][1] = dotv ? dotv[ic] : 0.0;
+      } else if (OUT == OUT_MASS_CG) {
+        pre[k][0] = cg.z[ic];
+        pre[k][1] = cg.p[ic];
+      } else {
+        pre[k][0] = scale ? scale[ic] : 1.0;
+        pre[k][1] = cg.q[ic];
+        pre[k][2] = cg.r[ic];
+        pre[k][3] = cg.x[ic];
+        pre[k][4] = cg.p[ic];
+        pre[k][5] = cg.flexible ? cg.z[ic] : 0.0;
+      }
+    }
+    if (!big) {
       double vv[LPT];
 #pragma unroll
       for (int u = 0; u < LPT; ++u) {
@@ -229,14 +258,6 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
         if (t < cnt) vals[t] = vv[u];
       }
     }
-    int32_t ra[kRowsPerThread], rb[kRowsPerThread];
-#pragma unroll
-    for (int k = 0; k < kRowsPerThread; ++k) {
-      const int32_t i = i0 + tid + k * kBS;
-      const bool own = i < i1;
-      ra[k] = own ? rowptr[i] - p0 : 0;
-      rb[k] = own ? rowptr[i + 1] - p0 : 0;
-    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kRowsPerThread; ++k) {
@@ -247,8 +268,25 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
         for (int32_t q = ra[k]; q < rb[k]; ++q) acc += vals[q];
       else
         for (int32_t q = ra[k]; q < rb[k]; ++q) acc += (double)zb[slot[p0 + q]];
-      if (scale) acc *= scale[i];
-      reduce_epilogue<OUT>(i, acc, coef, cg, y, dotv, d0, d1, d2);
+      if (OUT == OUT_PLAIN) {
+        acc *= pre[k][0];
+        y[i] = acc;
+        d0 = fma(acc, pre[k][1], d0);
+      } else if (OUT == OUT_MASS_CG) {
+        const double pn = fma(coef, pre[k][1], pre[k][0]);
+        cg.p[i] = pn;
+        cg.q[i] = acc;
+        d0 = fma(pn, acc, d0);
+      } else {
+        acc *= pre[k][0];
+        const double rn = fma(-coef, pre[k][1], pre[k][2]);
+        cg.x[i] = fma(coef, pre[k][4], pre[k][3]);
+        d2 = fma(rn, pre[k][5], d2);
+        cg.z[i] = acc;
+        cg.r[i] = rn;
+        d0 = fma(rn, rn, d0);
+        d1 = fma(rn, acc, d1);
+      }
     }
     __syncthreads();
   }
@@ -520,6 +558,14 @@ static int scaled_dispatch(Ctx* c, int R, const InArgs& in, const double* dscale
 #undef CASE
 }
 
+// Scheduling variant of the 3D metric-form mass pass: the one set by the
+// autotuner or an option, else diagonal order for n_loc 20 (fastest when timed
+// on the 48^3 N1curl2 map) and row order otherwise.
+int metric_variant(const Ctx* c) {
+  if (c->variant >= 0 && c->variant < kMetricVariants) return c->variant;
+  return c->nl == 20 ? 2 : 0;
+}
+
 // element pass of the mass operator (float64)
 static int mass_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
   double* zb = (double*)c->zb;
@@ -531,7 +577,11 @@ static int mass_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
   }
   // metric tables (setup keeps them only for n_loc <= kLaneMaxNL)
   if (c->nsym <= 3) return lane_metric3(c, R, in, zb, s);
-  return lane_metric6(c, R, in, zb, s);
+  switch (metric_variant(c)) {
+    case 1: return lane_metric6_v1(c, R, in, zb, s);
+    case 2: return lane_metric6_v2(c, R, in, zb, s);
+    default: return lane_metric6_v0(c, R, in, zb, s);
+  }
 }
 
 // element pass of the BRAS operator; reports whether the broken vector is float32

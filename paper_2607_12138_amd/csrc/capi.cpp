@@ -59,8 +59,9 @@ extern "C" int bras_set_option(bras_handle h, int opt, double value) {
       c->max_restart = (int)value;
       break;
     case BRAS_OPT_VARIANT:
-      BRAS_CHECK(value >= -1 && value <= 1, "variant must be -1, 0 or 1");
+      BRAS_CHECK(value >= -1 && value < variant_count(c), "variant must be -1 or in 0..%d", variant_count(c) - 1);
       c->variant = (int)value;
+      cg_free(c);   // captured CG graphs hold the previous kernels
       break;
     default: return fail(BRAS_EINVAL, "unknown option %d", opt);
   }
@@ -101,29 +102,48 @@ extern "C" int bras_export(bras_handle h, int what, void* dst_d, void* stream) {
   return BRAS_OK;
 }
 
+int bras::variant_count(const Ctx* c) {
+  const bool metric6 = c->form == BRAS_ELEM_METRIC_REF && c->nsym > 3 && c->nl <= kLaneMaxNL;
+  return metric6 ? kMetricVariants : 1;
+}
+
+// Times mass apply + BRAS apply (one CG iteration's operator passes) for every
+// scheduling variant of this handle and keeps the fastest.
 extern "C" int bras_autotune(bras_handle h, int nrhs, void* stream) {
   clear_error();
   BRAS_CHECK(h, "null handle");
   Ctx* c = (Ctx*)h;
   BRAS_CHECK(nrhs >= 1 && nrhs <= c->max_rhs, "nrhs outside 1..max_rhs");
+  const int nv = variant_count(c);
+  if (nv == 1) {
+    c->variant = 0;
+    return BRAS_OK;
+  }
   hipStream_t s = (hipStream_t)stream;
   const size_t vec = sizeof(double) * (size_t)c->n * nrhs;
   double *x = nullptr, *y = nullptr;
   BRAS_HIP(hipMalloc((void**)&x, vec));
-  BRAS_HIP(hipMalloc((void**)&y, vec));
-  BRAS_HIP(hipMemsetAsync(x, 0, vec, s));
-  hipEvent_t e0, e1;
-  BRAS_HIP(hipEventCreate(&e0));
-  BRAS_HIP(hipEventCreate(&e1));
+  if (hipMalloc((void**)&y, vec) != hipSuccess) {
+    (void)hipFree(x);
+    return fail(BRAS_ENOMEM, "autotune workspace allocation failed");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = BRAS_OK;
+  if (hipMemsetAsync(x, 0, vec, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    st = fail(BRAS_EHIP, "autotune set-up failed");
   float best = 1e30f;
   int best_v = 0;
-  int st = BRAS_OK;
-  for (int v = 0; v <= 1 && st == BRAS_OK; ++v) {
+  for (int v = 0; v < nv && st == BRAS_OK; ++v) {
     c->variant = v;
-    for (int w = 0; w < 3 && st == BRAS_OK; ++w) st = launch_bras(c, x, y, nrhs, s, nullptr, nullptr, nullptr);
+    auto pass = [&]() {
+      int r = launch_mass(c, x, y, nrhs, s, nullptr, nullptr, nullptr);
+      return r ? r : launch_bras(c, x, y, nrhs, s, nullptr, nullptr, nullptr);
+    };
+    for (int w = 0; w < 2 && st == BRAS_OK; ++w) st = pass();
     if (st) break;
     (void)hipEventRecord(e0, s);
-    for (int rep = 0; rep < 10 && st == BRAS_OK; ++rep) st = launch_bras(c, x, y, nrhs, s, nullptr, nullptr, nullptr);
+    for (int rep = 0; rep < 10 && st == BRAS_OK; ++rep) st = pass();
     (void)hipEventRecord(e1, s);
     (void)hipEventSynchronize(e1);
     float ms = 0.f;
@@ -134,8 +154,9 @@ extern "C" int bras_autotune(bras_handle h, int nrhs, void* stream) {
     }
   }
   c->variant = best_v;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  cg_free(c);   // captured CG graphs hold the previous kernels
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(x);
   (void)hipFree(y);
   return st;

@@ -40,6 +40,18 @@ constexpr int tri_row(int q) {
   while ((i + 1) * (i + 2) / 2 <= q) ++i;
   return i;
 }
+// t-th entry in diagonal order (d = 0, 1, ..., entries (i, i - d)) as a
+// row-order packed index q = i(i+1)/2 + j
+template <int NL>
+constexpr int diag_q(int t) {
+  int d = 0;
+  while (t >= NL - d) {
+    t -= NL - d;
+    ++d;
+  }
+  const int i = d + t, j = t;
+  return i * (i + 1) / 2 + j;
+}
 // Return i unchanged, but only once dep has been computed: loads indexed by
 // the result cannot be issued before the arithmetic that produced dep, which
 // bounds how many loads of the unrolled product are in flight (otherwise the
@@ -63,7 +75,11 @@ __device__ __forceinline__ void touch_all(T (&z)[N]) {
   for (int i = 0; i < N; ++i) __asm__ volatile("" : "+v"(z[i]));
 }
 
-template <int NL, int FORM, int NSYM, typename T, typename ZT, int EPB>
+// VAR selects scheduling variants: metric form bit 0 diagonal order, bit 1
+// pinning on the entry values, bits 2-3 and 6-7 the batch size; packed form
+// bits 4-5 the batch size.  The metric variants the library offers to its
+// autotuner are kMetricVar[] below.
+template <int NL, int FORM, int NSYM, typename T, typename ZT, int EPB, int VAR = 0>
 __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32_t* __restrict__ l2g, InArgs in,
                                                    const double* __restrict__ symtab,
                                                    const double* __restrict__ coefK, int nsym,
@@ -167,36 +183,50 @@ __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32
     };
     if constexpr (FORM == FORM_METRIC) {
       // table entries are wave-uniform scalar loads (SGPR operands, no LDS
-      // traffic); batches of CQ entries, the next batch in flight
-      constexpr int CQ = 2;
+      // traffic), in batches of CQ entries, the next batch in flight.
+      // Visiting order: row by row, or diagonal by diagonal (entries (i, i-d)
+      // for i = d..NL-1), where consecutive entries update different
+      // accumulators.
+      constexpr int CQS = (VAR >> 2) & 3;
+      constexpr int CQ = (VAR & 64) ? ((VAR & 128) ? 16 : 12) : (CQS == 0 ? 2 : (CQS == 1 ? 4 : (CQS == 2 ? 1 : 8)));
+      constexpr bool DIAG = (VAR & 1) != 0;
+      constexpr bool PIN_M = (VAR & 2) != 0;
       constexpr int NBQ = (NPK + CQ - 1) / CQ;
       double tb[2][CQ * NSYM];
+      double mlast = wr[0];
       auto tload = [&](auto bc, int64_t o) {
         constexpr int b = decltype(bc)::value;
         const double* src = symtab + o;
+        static_for<CQ>([&](auto ec) {
+          constexpr int t = b * CQ + decltype(ec)::value;
+          if constexpr (t < NPK) {
+            constexpr int q = DIAG ? diag_q<NL>(t) : t;
 #pragma unroll
-        for (int t = 0; t < CQ * NSYM; ++t)
-          if (b * CQ * NSYM + t < NPK * NSYM) tb[b & 1][t] = src[b * CQ * NSYM + t];
+            for (int p = 0; p < NSYM; ++p) tb[b & 1][decltype(ec)::value * NSYM + p] = src[q * NSYM + p];
+          }
+        });
       };
       tload(std::integral_constant<int, 0>{}, pin_s((int64_t)0, wr[0]));
       static_for<NBQ>([&](auto bc) {
         constexpr int b = decltype(bc)::value;
-        if constexpr (b + 1 < NBQ) tload(std::integral_constant<int, b + 1>{}, pin_s((int64_t)0, wr[0]));
+        if constexpr (b + 1 < NBQ) tload(std::integral_constant<int, b + 1>{}, pin_s((int64_t)0, mlast));
         static_for<CQ>([&](auto ec) {
           constexpr int e = decltype(ec)::value;
-          constexpr int q = b * CQ + e;
-          if constexpr (q < NPK) {
+          constexpr int t = b * CQ + e;
+          if constexpr (t < NPK) {
+            constexpr int q = DIAG ? diag_q<NL>(t) : t;
             double acc = 0.0;
 #pragma unroll
             for (int p = 0; p < NSYM; ++p) acc = fma(g[p], tb[b & 1][e * NSYM + p], acc);
             use(std::integral_constant<int, q>{}, (T)acc);
+            if (PIN_M) mlast = acc;
           }
         });
-        touch_all(z);
+        if constexpr (!PIN_M) touch_all(z);
       });
     } else {
       constexpr int NQ = (NPK + V - 1) / V;   // 16-byte groups
-      constexpr int CV = 6;                   // groups per batch
+      constexpr int CV = ((VAR >> 4) & 3) == 0 ? 6 : (((VAR >> 4) & 3) == 1 ? 3 : (((VAR >> 4) & 3) == 2 ? 10 : 14));
       constexpr int NB = (NQ + CV - 1) / CV;
       // uniform base + per-lane offset (lanes past the last element read its data)
       const vec_t* sbase = reinterpret_cast<const vec_t*>(ap) + K0;
@@ -231,20 +261,20 @@ __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32
 
 #define LANE_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(21) X(24) X(28) X(35) X(36)
 
-template <int NL, int FORM, int NSYM, typename T, typename ZT>
+template <int NL, int FORM, int NSYM, typename T, typename ZT, int VAR>
 static int lane_launch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {
   constexpr int EPB = 64;   // one wavefront per work-group
   const unsigned nb = (unsigned)((c->E + EPB - 1) / EPB);
-  k_elem_lane<NL, FORM, NSYM, T, ZT, EPB><<<nb, EPB, 0, s>>>(c->E, R, c->l2g, in, c->symtab, c->coef, c->nsym, ap,
-                                                              zb);
+  k_elem_lane<NL, FORM, NSYM, T, ZT, EPB, VAR><<<nb, EPB, 0, s>>>(c->E, R, c->l2g, in, c->symtab, c->coef, c->nsym,
+                                                                   ap, zb);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
 
-template <int FORM, int NSYM, typename T, typename ZT>
+template <int FORM, int NSYM, typename T, typename ZT, int VAR = 0>
 static int lane_dispatch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {
 #define CASE(N) \
-  case N: return lane_launch<N, FORM, NSYM, T, ZT>(c, R, in, ap, zb, s);
+  case N: return lane_launch<N, FORM, NSYM, T, ZT, VAR>(c, R, in, ap, zb, s);
   switch (c->nl) {
     LANE_CASES(CASE)
     default: return fail(BRAS_EINVAL, "n_loc %d has no per-lane element kernel", c->nl);
@@ -256,7 +286,12 @@ static int lane_dispatch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, h
 int lane_packed_f64(Ctx* c, int R, const InArgs& in, const double* ap, double* zb, hipStream_t s);
 int lane_packed_f32(Ctx* c, int R, const InArgs& in, const float* ap, float* zb, hipStream_t s);
 int lane_metric3(Ctx* c, int R, const InArgs& in, double* zb, hipStream_t s);
-int lane_metric6(Ctx* c, int R, const InArgs& in, double* zb, hipStream_t s);
+// 3D metric form: kMetricVariants (internal.h) scheduling variants (row
+// order in batches of 2 and 4 entries, diagonal order in batches of 8), one
+// translation unit each.
+int lane_metric6_v0(Ctx* c, int R, const InArgs& in, double* zb, hipStream_t s);
+int lane_metric6_v1(Ctx* c, int R, const InArgs& in, double* zb, hipStream_t s);
+int lane_metric6_v2(Ctx* c, int R, const InArgs& in, double* zb, hipStream_t s);
 // Per-element matrix-core pass for n_loc > kLaneMaxNL (elem_mfma.hip).
 int mfma_elem_f64(Ctx* c, int R, const InArgs& in, const double* mat, double* zb, hipStream_t s);
 int mfma_elem_f32(Ctx* c, int R, const InArgs& in, const float* mat, float* zb, hipStream_t s);

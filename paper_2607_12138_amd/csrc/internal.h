@@ -45,7 +45,7 @@ struct Ctx {
   int64_t n = 0, E = 0, nbr = 0;
   int nl = 0;
   int form = 0, nsym = 0, prec = 0, max_rhs = 1;
-  int variant = -1;          // apply kernel variant (-1: default)
+  int variant = -1;          // element-pass scheduling variant (-1: built-in choice)
   int graph_iters = 8;
   int max_restart = 8;
   int64_t last_restarts = 0;
@@ -87,6 +87,8 @@ inline int npack_of(int nl) { return nl * (nl + 1) / 2; }
 
 // Largest n_loc whose element passes keep a whole element in one lane's registers.
 constexpr int kLaneMaxNL = 36;
+// Scheduling variants of the 3D metric-form mass pass offered to bras_autotune.
+constexpr int kMetricVariants = 3;
 // Packed per-element matrices (q = i(i+1)/2 + j, i >= j) are stored either
 // in groups of g consecutive entries (g = 16 bytes / entry size, for the
 // per-lane pass, n_loc <= kLaneMaxNL): entry (q, K) at ((q / g) * E + K) * g
@@ -125,6 +127,8 @@ int cg_bras_bf16_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
 struct InArgs;
 InArgs precond_input(const CgArgs& cg, int nrhs);
 int precond_consumer_blocks(Ctx* c, int pc, int nrhs);
+int metric_variant(const Ctx* c);   // apply.hip
+int variant_count(const Ctx* c);    // scheduling variants of this handle's element passes
 // reduce passes over a float32 broken vector (apply.hip)
 int reduce_float_plain(Ctx* c, const float* zb, double* y, int nrhs, hipStream_t s, const double* dotv,
                        double* dotpart);

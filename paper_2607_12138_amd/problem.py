@@ -96,6 +96,11 @@ class MassProblem:
     def info(self, what):
         return L.bras_info(self.h, what)
 
+    def autotune(self, nrhs=None):
+        """Pick the fastest element-pass scheduling variant for this mesh."""
+        L.bras_autotune(self.h, self.max_rhs if nrhs is None else nrhs)
+        return L.bras_info(self.h, "variant")
+
     def export(self, what):
         import torch
         if what == L.EXPORT_MULT:

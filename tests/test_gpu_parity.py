@@ -298,3 +298,25 @@ def test_bf16_flexible_pcg(case):
         assert true_rel <= 1.5e-8 and abs(true_rel - rel[r]) <= 1e-10
         xo, ito, ok, _ = opcg.pcg(orc.M, B[:, r], orc.B.dot, tol=1e-8)
         assert int(its[r]) <= ito + 3                   # BF16 preconditioner costs at most a few iterations
+
+
+def test_autotune_variants():
+    """Every scheduling variant of the metric-form mass pass gives the
+    oracle's products; the autotuner keeps one of them; invalid variants are
+    rejected."""
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(CASES[5])
+    x = workloads.vector(orc.n, 9)
+    say("autotune variants %s" % (CASES[5],))
+    for v in range(3):
+        L.bras_set_option(gpu.h, L.OPT_VARIANT, v)
+        assert rel_inf(gpu.mass(to_t(x)).cpu().numpy(), orc.M @ x) <= 1e-13
+        b = workloads.rhs(orc.n, 1, 41)
+        xs, st, its, rel = gpu.solve(to_t(b), "bras", rtol=1e-10)
+        assert st == L.BRAS_OK
+    L.bras_autotune(gpu.h, 1)
+    assert 0 <= gpu.info("variant") < 3
+    with pytest.raises(L.BrasError):
+        L.bras_set_option(gpu.h, L.OPT_VARIANT, 3)
+    L.bras_set_option(gpu.h, L.OPT_VARIANT, -1)
+    assert gpu.info("variant") == -1
