@@ -222,6 +222,38 @@ int bras_export(bras_handle h, int what, void* dst_d, void* stream);
 #define BRAS_OPT_VARIANT     2  /* force a scheduling variant (-1 = built-in)  */
 int bras_set_option(bras_handle h, int opt, double value);
 
+/* ======================================================================== *
+ * Stationary iterations with the same operators (Section 4).
+ * ======================================================================== */
+
+/* Power-iteration estimate of lambda_max(C M), C = BRAS (pc = BRAS_PC_BRAS)
+ * or diag(M)^-1 (BRAS_PC_JACOBI), used for the fixed-point weights of
+ * Section 4 (omega_diag = 1/lambda_max, omega_bras = 2/(1 + lambda_max)):
+ * v_0 = v0/||v0||; for k = 1..iters: q = M v, w = C q, lambda = q.w / q.v,
+ * v = w/||w||.  v0_d: [n] float64 (device, not modified).  The estimate is a
+ * Rayleigh quotient of the M-self-adjoint C M, so it never exceeds
+ * lambda_max.  EINVAL for a zero start vector, EBREAKDOWN on non-positive
+ * products.  Synchronous. */
+int bras_lambda_max(bras_handle h, int pc, const double* v0_d, int iters, double* lambda_h, void* stream);
+
+/* Damped fixed-point iteration u_{k+1} = u_k + omega C (f - M u_k)
+ * (Section 4) from u_0 = x_d, for every column independently; stops when
+ * ||f - M u_k||_2 <= rtol ||f - M u_0||_2 (iters_h = k, the number of
+ * updates) or after maxit updates (ENOCONV).  pc: BRAS_PC_JACOBI or
+ * BRAS_PC_BRAS.  Arguments and results as pcg_solve.  Synchronous. */
+int fixed_point_solve(bras_handle h, int pc, double omega, const double* b_d, double* x_d, int nrhs,
+                      double rtol, int maxit, int* iters_h, double* relres_h, void* stream);
+
+/* Chebyshev semi-iteration for C M on the interval [lmin, lmax] (Section 4
+ * recommends Chebyshev with the BRAS spectral interval, lmin = 1 by Cor.
+ * bras_lambda_min): d_0 = C r_0 / theta; rho_0 = 1/sigma; rho_k = 1/(2 sigma -
+ * rho_{k-1}); d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k/delta) C r_k;
+ * u_{k+1} = u_k + d_k, with theta = (lmax + lmin)/2, delta = (lmax - lmin)/2,
+ * sigma = theta/delta and r_k = f - M u_k.  No dot products besides the
+ * stopping test.  Stopping, arguments and results as fixed_point_solve. */
+int chebyshev_solve(bras_handle h, int pc, double lmin, double lmax, const double* b_d, double* x_d, int nrhs,
+                    double rtol, int maxit, int* iters_h, double* relres_h, void* stream);
+
 /* Time the element-pass scheduling variants this handle offers (3D H(curl) /
  * H(div) metric-form mass passes with n_loc <= 36: row order in batches of 2
  * or 4 table entries, diagonal order in batches of 8; every other handle has

@@ -21,6 +21,7 @@ H1, HCURL, HDIV = 0, 1, 2
 ELEM_EXPLICIT, ELEM_SCALED_REF, ELEM_METRIC_REF = 0, 1, 2
 FP64, FP32, BF16 = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_BRAS = 0, 1, 2
+PC = {"none": PC_NONE, "jacobi": PC_JACOBI, "bras": PC_BRAS}
 INFO = {"n": 0, "E": 1, "nloc": 2, "nbr": 3, "prec": 4, "form": 5, "maxrhs": 6, "restarts": 7, "variant": 8}
 EXPORT_MULT, EXPORT_ROWPTR, EXPORT_SLOT, EXPORT_DIAG = 0, 1, 2, 3
 OPT_GRAPH_ITERS, OPT_MAX_RESTART, OPT_VARIANT = 0, 1, 2
@@ -58,6 +59,9 @@ _SIGS = {
     "mass_apply": [vp, vp, vp, i32, vp],
     "jacobi_apply": [vp, vp, vp, i32, vp],
     "pcg_solve": [vp, i32, vp, vp, i32, dbl, i32, C.POINTER(C.c_int), P_dbl, vp],
+    "bras_lambda_max": [vp, i32, vp, i32, P_dbl, vp],
+    "fixed_point_solve": [vp, i32, dbl, vp, vp, i32, dbl, i32, C.POINTER(C.c_int), P_dbl, vp],
+    "chebyshev_solve": [vp, i32, dbl, dbl, vp, vp, i32, dbl, i32, C.POINTER(C.c_int), P_dbl, vp],
     "bras_rho_grad": [vp, vp, vp, vp, vp, i32, vp],
     "bras_info": [vp, i32, P_i64],
     "bras_export": [vp, i32, vp, vp],
@@ -211,6 +215,38 @@ def pcg_solve(h, pc, b_d, x_d, rtol, maxit, stream=None, raise_on=(BRAS_EINVAL, 
     its = (C.c_int * R)()
     rel = (C.c_double * R)()
     st = lib().pcg_solve(h, pc, _dev(b_d), _dev(x_d), R, float(rtol), int(maxit), its, rel, _stream(stream))
+    if st in raise_on:
+        check(st)
+    return st, np.array(its[:]), np.array(rel[:])
+
+
+def bras_lambda_max(h, pc, v0_d, iters=50, stream=None):
+    lam = C.c_double()
+    check(lib().bras_lambda_max(h, pc, _dev(v0_d), int(iters), C.byref(lam), _stream(stream)))
+    return lam.value
+
+
+def fixed_point_solve(h, pc, omega, b_d, x_d, rtol, maxit, stream=None,
+                      raise_on=(BRAS_EINVAL, BRAS_EHIP, BRAS_ENOMEM)):
+    """Returns (status, updates [nrhs], relative residuals [nrhs])."""
+    R = _nrhs(b_d)
+    its = (C.c_int * R)()
+    rel = (C.c_double * R)()
+    st = lib().fixed_point_solve(h, pc, float(omega), _dev(b_d), _dev(x_d), R, float(rtol), int(maxit), its, rel,
+                                 _stream(stream))
+    if st in raise_on:
+        check(st)
+    return st, np.array(its[:]), np.array(rel[:])
+
+
+def chebyshev_solve(h, pc, lmin, lmax, b_d, x_d, rtol, maxit, stream=None,
+                    raise_on=(BRAS_EINVAL, BRAS_EHIP, BRAS_ENOMEM)):
+    """Returns (status, updates [nrhs], relative residuals [nrhs])."""
+    R = _nrhs(b_d)
+    its = (C.c_int * R)()
+    rel = (C.c_double * R)()
+    st = lib().chebyshev_solve(h, pc, float(lmin), float(lmax), _dev(b_d), _dev(x_d), R, float(rtol), int(maxit),
+                               its, rel, _stream(stream))
     if st in raise_on:
         check(st)
     return st, np.array(its[:]), np.array(rel[:])

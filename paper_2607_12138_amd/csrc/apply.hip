@@ -30,7 +30,7 @@ constexpr int kBS = 256;                  // reduce / vector pass block size
 constexpr int kEB = 256;                  // element pass block size
 constexpr int kMaxVectorBlocks = 512;
 
-enum { OUT_PLAIN = 0, OUT_MASS_CG = 1, OUT_BRAS_CG = 2 };
+enum { OUT_PLAIN = 0, OUT_MASS_CG = 1, OUT_BRAS_CG = 2, OUT_RES = 3, OUT_STAT = 4 };
 
 // ---------------------------------------------------------------------------
 // element pass, affine H1 (a shared reference matrix times one coefficient per
@@ -160,6 +160,8 @@ __global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* _
 //                q = M p_new, partial p_new.q
 //   OUT_BRAS_CG  r_new = r - alpha q, x += alpha p, z = C r_new, partials
 //                r_new.r_new, r_new.z and (flexible) r_new.z_old
+//   OUT_RES      r = b - M x, partial r.r           (stationary iterations)
+//   OUT_STAT     d = a d + c C r, x += d            (a = sc[S_ALPHA], c = sc[S_BETA])
 constexpr int kChunkRows = 512;
 constexpr int kChunkCap = 2048;
 constexpr int kRowsPerThread = kChunkRows / kBS;
@@ -168,9 +170,18 @@ constexpr int kMaxReduceBlocks1 = 16384;  // one column
 
 // CG epilogue of one output entry t (column col, sum acc); accumulates dots
 template <int OUT>
-__device__ __forceinline__ void reduce_epilogue(int64_t t, double acc, double coef, const CgArgs& cg, double* y,
-                                                const double* dotv, double& d0, double& d1, double& d2) {
-  if (OUT == OUT_PLAIN) {
+__device__ __forceinline__ void reduce_epilogue(int64_t t, double acc, double coef, double coef2, const CgArgs& cg,
+                                                double* y, const double* dotv, double& d0, double& d1,
+                                                double& d2) {
+  if (OUT == OUT_RES) {
+    const double rv = cg.b[t] - acc;
+    cg.r[t] = rv;
+    d0 = fma(rv, rv, d0);
+  } else if (OUT == OUT_STAT) {
+    const double dn = fma(coef, cg.p[t], coef2 * acc);
+    cg.p[t] = dn;
+    cg.x[t] += dn;
+  } else if (OUT == OUT_PLAIN) {
     y[t] = acc;
     if (dotv) d0 = fma(acc, dotv[t], d0);
   } else if (OUT == OUT_MASS_CG) {
@@ -203,10 +214,12 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
   __shared__ double vals[kChunkCap];
   __shared__ double sh0[kBS], sh1[kBS], sh2[kBS];
   if (OUT != OUT_PLAIN && !cg.ic[I_ACTIVE]) return;   // uniform across the grid
-  const double coef = OUT == OUT_MASS_CG ? cg.sc[S_BETA] : (OUT == OUT_BRAS_CG ? cg.sc[S_ALPHA] : 0.0);
+  const double coef = OUT == OUT_MASS_CG ? cg.sc[S_BETA]
+                      : ((OUT == OUT_BRAS_CG || OUT == OUT_STAT) ? cg.sc[S_ALPHA] : 0.0);
+  const double coef2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   const int tid = threadIdx.x;
   constexpr int LPT = kChunkCap / kBS;   // copies per thread
-  constexpr int NV = OUT == OUT_PLAIN ? 2 : (OUT == OUT_MASS_CG ? 2 : 6);   // epilogue operands per row
+  constexpr int NV = (OUT == OUT_PLAIN || OUT == OUT_MASS_CG) ? 2 : (OUT == OUT_RES ? 1 : (OUT == OUT_STAT ? 3 : 6));
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
   for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
     const int32_t i0 = chunk[ch], i1 = chunk[ch + 1];
@@ -230,7 +243,13 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
       const int32_t ic = own ? i : i0;
       ra[k] = own ? rowptr[ic] - p0 : 0;
       rb[k] = own ? rowptr[ic + 1] - p0 : 0;
-      if (OUT == OUT_PLAIN) {
+      if (OUT == OUT_RES) {
+        pre[k][0] = cg.b[ic];
+      } else if (OUT == OUT_STAT) {
+        pre[k][0] = scale ? scale[ic] : 1.0;
+        pre[k][1] = cg.p[ic];
+        pre[k][2] = cg.x[ic];
+      } else if (OUT == OUT_PLAIN) {
         pre[k][0] = scale ? scale[ic] : 1.0;
         pre[k][1] = dotv ? dotv[ic] : 0.0;
       } else if (OUT == OUT_MASS_CG) {
@@ -268,7 +287,16 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
         for (int32_t q = ra[k]; q < rb[k]; ++q) acc += vals[q];
       else
         for (int32_t q = ra[k]; q < rb[k]; ++q) acc += (double)zb[slot[p0 + q]];
-      if (OUT == OUT_PLAIN) {
+      if (OUT == OUT_RES) {
+        const double rv = pre[k][0] - acc;
+        cg.r[i] = rv;
+        d0 = fma(rv, rv, d0);
+      } else if (OUT == OUT_STAT) {
+        acc *= pre[k][0];
+        const double dn = fma(coef, pre[k][1], coef2 * acc);
+        cg.p[i] = dn;
+        cg.x[i] = pre[k][2] + dn;
+      } else if (OUT == OUT_PLAIN) {
         acc *= pre[k][0];
         y[i] = acc;
         d0 = fma(acc, pre[k][1], d0);
@@ -292,6 +320,7 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
   }
   // partials of this block (fixed tree order)
   double* out0 = OUT == OUT_PLAIN ? partial : cg.part0;
+  if (OUT == OUT_STAT) return;
   if (OUT == OUT_PLAIN && !(dotv && partial)) return;
   sh0[tid] = d0;
   if (OUT == OUT_BRAS_CG) {
@@ -332,12 +361,14 @@ __global__ void __launch_bounds__(kBS) k_reduce_mc(int R, int nchunk, const int3
   __shared__ int32_t sl[kChunkCap];
   __shared__ int32_t rp[kChunkRows + 1];
   __shared__ double sh[kBS];
-  __shared__ double coef_s[256];
+  __shared__ double coef_s[256], coef2_s[256];
   __shared__ int act_s[256];
   const int tid = threadIdx.x;
   for (int c = tid; c < R; c += kBS) {
     act_s[c] = OUT == OUT_PLAIN ? 1 : cg.ic[I_ACTIVE * R + c];
-    coef_s[c] = OUT == OUT_MASS_CG ? cg.sc[S_BETA * R + c] : (OUT == OUT_BRAS_CG ? cg.sc[S_ALPHA * R + c] : 0.0);
+    coef_s[c] = OUT == OUT_MASS_CG ? cg.sc[S_BETA * R + c]
+                : ((OUT == OUT_BRAS_CG || OUT == OUT_STAT) ? cg.sc[S_ALPHA * R + c] : 0.0);
+    coef2_s[c] = OUT == OUT_STAT ? cg.sc[S_BETA * R + c] : 0.0;
   }
   __syncthreads();
   {
@@ -349,7 +380,7 @@ __global__ void __launch_bounds__(kBS) k_reduce_mc(int R, int nchunk, const int3
   const bool mine = tid < G * R;
   const int col = mine ? tid % R : 0, g = tid / R;
   const bool act = mine && act_s[col];
-  const double coef = coef_s[col];
+  const double coef = coef_s[col], coef2 = coef2_s[col];
   double d0 = 0.0, d1 = 0.0, d2 = 0.0;
   for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
     const int32_t i0 = chunk[ch], i1 = chunk[ch + 1];
@@ -382,13 +413,14 @@ __global__ void __launch_bounds__(kBS) k_reduce_mc(int R, int nchunk, const int3
         }
         const int64_t i = i0 + r;
         if (scale) acc *= scale[i];
-        reduce_epilogue<OUT>(i * R + col, acc, coef, cg, y, dotv, d0, d1, d2);
+        reduce_epilogue<OUT>(i * R + col, acc, coef, coef2, cg, y, dotv, d0, d1, d2);
       }
     }
     __syncthreads();
   }
   // per-column partials: thread c adds the row groups' sums in order
   double* out0 = OUT == OUT_PLAIN ? partial : cg.part0;
+  if (OUT == OUT_STAT) return;
   if (OUT == OUT_PLAIN && !(dotv && partial)) return;
   double* outs[3] = {out0, cg.part1, cg.part2};
   const double ds[3] = {d0, d1, d2};
@@ -451,6 +483,22 @@ __global__ void __launch_bounds__(kBS) k_diag_cg(int64_t n, int R, const double*
   if (cg.flexible) {
     sh2[threadIdx.x] = d2;
     block_partials(sh2, R, cg.part2);
+  }
+}
+
+// Stationary update with the diagonal preconditioner: d = a d + c (r ./ diag),
+// x += d, for running columns (a = sc[S_ALPHA], c = sc[S_BETA]).
+__global__ void __launch_bounds__(kBS) k_diag_st(int64_t n, int R, const double* __restrict__ s, CgArgs cg) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;   // a multiple of R
+  const int col = (int)(t0 % R);
+  if (!cg.ic[I_ACTIVE * R + col]) return;
+  const double a = cg.sc[S_ALPHA * R + col], c = cg.sc[S_BETA * R + col];
+  for (int64_t t = t0; t < n * R; t += stride) {
+    const int64_t i = R == 1 ? t : t / R;
+    const double dn = fma(a, cg.p[t], c * (cg.r[t] * s[i]));
+    cg.p[t] = dn;
+    cg.x[t] += dn;
   }
 }
 
@@ -716,6 +764,39 @@ int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
   k_diag_cg<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, pc == BRAS_PC_JACOBI ? c->invdiag : nullptr, cg);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
+}
+
+// Stationary iterations: r = b - M x with partial r.r
+int st_mass_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
+  InArgs in;
+  in.x = cg.x;
+  in.active = cg.ic + I_ACTIVE * R;
+  int st = mass_elem(c, in, R, s);
+  if (st) return st;
+  return reduce_launch<double, OUT_RES>(c, (const double*)c->zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
+}
+
+// Stationary iterations: d = a d + c C r, x += d (pc: BRAS_PC_BRAS or BRAS_PC_JACOBI)
+int st_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
+  if (pc == BRAS_PC_JACOBI) {
+    k_diag_st<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, c->invdiag, cg);
+    BRAS_HIP(hipGetLastError());
+    return BRAS_OK;
+  }
+  InArgs in;
+  in.x = cg.r;
+  in.active = cg.ic + I_ACTIVE * R;
+  if (c->prec == BRAS_BF16) {
+    int st = bf16_elem_pass(c, in, R, s);
+    if (st) return st;
+    return reduce_launch<float, OUT_STAT>(c, (const float*)c->zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
+  }
+  bool zf;
+  int st = bras_elem(c, in, R, s, &zf);
+  if (st) return st;
+  const double* scale = c->form == BRAS_ELEM_SCALED_REF ? c->invd : nullptr;
+  if (zf) return reduce_launch<float, OUT_STAT>(c, (const float*)c->zb, scale, nullptr, R, s, nullptr, nullptr, cg);
+  return reduce_launch<double, OUT_STAT>(c, (const double*)c->zb, scale, nullptr, R, s, nullptr, nullptr, cg);
 }
 
 }  // namespace bras

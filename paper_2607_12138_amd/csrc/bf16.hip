@@ -242,6 +242,8 @@ static int bf16_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
 #undef CASE
 }
 
+int bf16_elem_pass(Ctx* c, const InArgs& in, int R, hipStream_t s) { return bf16_elem(c, in, R, s); }
+
 int launch_bras_bf16(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
                      const int* active) {
   InArgs in;

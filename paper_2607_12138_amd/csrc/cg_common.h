@@ -34,6 +34,7 @@ struct InArgs {
 // Buffers and scalars of a fused CG pass.
 struct CgArgs {
   double *x = nullptr, *r = nullptr, *p = nullptr, *z = nullptr, *q = nullptr;
+  const double* b = nullptr;      // right-hand side (stationary iterations)
   double* sc = nullptr;
   int* ic = nullptr;
   double *part0 = nullptr, *part1 = nullptr, *part2 = nullptr;

@@ -124,8 +124,12 @@ struct CgArgs;
 int cg_mass_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
 int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int nrhs, hipStream_t s);
 int cg_bras_bf16_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
+// Stationary iterations (apply.hip): r = b - M x (partial r.r); d = a d + c C r, x += d
+int st_mass_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
+int st_precond_step(Ctx* c, int pc, const CgArgs& cg, int nrhs, hipStream_t s);
 struct InArgs;
 InArgs precond_input(const CgArgs& cg, int nrhs);
+int bf16_elem_pass(Ctx* c, const InArgs& in, int nrhs, hipStream_t s);   // bf16.hip
 int precond_consumer_blocks(Ctx* c, int pc, int nrhs);
 int metric_variant(const Ctx* c);   // apply.hip
 int variant_count(const Ctx* c);    // scheduling variants of this handle's element passes

@@ -45,9 +45,12 @@ struct CgState {
   double* part[4] = {nullptr, nullptr, nullptr, nullptr};   // partials [blocks][R]: r.r, r.z, r.z_old, p.q
   int* ic_host = nullptr;    // pinned copy of ic
   double* sc_host = nullptr;
+  double* stcoef = nullptr;  // stationary iterations: a_k [cap], then c_k [cap]
+  int stcoef_cap = 0;
   struct Key {
-    int pc, flexible, maxit;
+    int kind, pc, flexible, maxit;   // kind 0: CG, 1: stationary iteration
     bool operator<(const Key& o) const {
+      if (kind != o.kind) return kind < o.kind;
       if (pc != o.pc) return pc < o.pc;
       if (flexible != o.flexible) return flexible < o.flexible;
       return maxit < o.maxit;
@@ -121,6 +124,10 @@ __global__ void __launch_bounds__(kBS) k_fin_rz(int nb, int R, const double* __r
   }
 }
 
+__global__ void __launch_bounds__(kBS) k_set_int(int* __restrict__ v, int n, int value) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) v[t] = value;
+}
+
 __global__ void __launch_bounds__(kBS) k_zero(int64_t n, double* __restrict__ v) {
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -176,7 +183,8 @@ void cg_free(Ctx* c) {
   if (!g) return;
   for (auto& kv : g->graphs)
     for (auto ge : kv.second) (void)hipGraphExecDestroy(ge);
-  double* bufs[] = {g->b, g->x, g->r, g->z, g->p, g->q, g->sc, g->part[0], g->part[1], g->part[2], g->part[3]};
+  double* bufs[] = {g->b, g->x, g->r, g->z, g->p, g->q, g->sc, g->part[0], g->part[1], g->part[2], g->part[3],
+                    g->stcoef};
   for (double* p : bufs)
     if (p) (void)hipFree(p);
   if (g->ic) (void)hipFree(g->ic);
@@ -307,9 +315,11 @@ static int read_state(Ctx* c, hipStream_t s) {
   return BRAS_OK;
 }
 
-static int get_graphs(Ctx* c, int pc, int flexible, int maxit, std::vector<hipGraphExec_t>** out) {
+// Graphs of 1, 2, 4, ... iterations of one kind, captured on the idle
+// internal stream before any work is queued.
+template <typename F>
+static int capture_graphs(Ctx* c, CgState::Key key, F one_iteration, std::vector<hipGraphExec_t>** out) {
   CgState* g = c->cg;
-  CgState::Key key{pc, flexible, maxit};
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) {
     *out = &it->second;
@@ -321,7 +331,7 @@ static int get_graphs(Ctx* c, int pc, int flexible, int maxit, std::vector<hipGr
     const int iters = 1 << k;
     BRAS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     int st = BRAS_OK;
-    for (int i = 0; i < iters && st == BRAS_OK; ++i) st = iteration(c, pc, flexible, maxit, s);
+    for (int i = 0; i < iters && st == BRAS_OK; ++i) st = one_iteration(s);
     hipGraph_t graph;
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (st) return st;
@@ -335,6 +345,49 @@ static int get_graphs(Ctx* c, int pc, int flexible, int maxit, std::vector<hipGr
   g->graphs[key] = v;
   *out = &g->graphs[key];
   return BRAS_OK;
+}
+
+static int get_graphs(Ctx* c, int pc, int flexible, int maxit, std::vector<hipGraphExec_t>** out) {
+  return capture_graphs(c, CgState::Key{0, pc, flexible, maxit},
+                        [&](hipStream_t s) { return iteration(c, pc, flexible, maxit, s); }, out);
+}
+
+// Launch graphs for about `chunk` more iterations (binary decomposition).
+static int launch_chunk(std::vector<hipGraphExec_t>& graphs, int chunk, hipStream_t s) {
+  for (int k = kNumGraphs - 1; k >= 0; --k)
+    if (chunk & (1 << k)) {
+      hipError_t e = hipGraphLaunch(graphs[k], s);
+      if (e != hipSuccess) return fail(BRAS_EHIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
+    }
+  return BRAS_OK;
+}
+
+// Iterations to launch before the host looks at the flags again: enough to
+// reach the target at the slowest running column's observed rate (1..32).
+static int predict_chunk(CgState* g, int R, int maxit) {
+  int any = 0, max_it = 0;
+  double worst = 0.0;
+  for (int col = 0; col < R; ++col) {
+    if (!g->ic_host[I_ACTIVE * R + col]) continue;
+    any = 1;
+    const int it = g->ic_host[I_ITERS * R + col];
+    max_it = it > max_it ? it : max_it;
+    const double rel = g->sc_host[S_RELRES * R + col];
+    const double tgt = g->sc_host[S_TARGET * R + col] / g->sc_host[S_R0 * R + col];
+    if (it > 0 && rel > 0.0 && rel < 1.0) {
+      const double rate = std::log(rel) / it;   // per-iteration log reduction (< 0)
+      const double need = std::log(tgt / rel) / rate;
+      if (need > worst) worst = need;
+    } else if (4.0 > worst) {
+      worst = 4.0;
+    }
+  }
+  if (!any) return 0;
+  int chunk = (int)std::ceil(worst);
+  if (chunk < 1) chunk = 1;
+  if (chunk > 32) chunk = 32;
+  if (chunk > maxit - max_it + 1) chunk = maxit - max_it + 1;
+  return chunk < 1 ? 1 : chunk;
 }
 
 }  // namespace bras
@@ -375,36 +428,9 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
     if ((st = read_state(c, s))) break;
     // iterate: predict the remaining iterations from the observed rate
     while (true) {
-      int any = 0, max_it = 0;
-      double worst_log = 0.0, worst_rate = 0.0;
-      for (int col = 0; col < R; ++col) {
-        if (!g->ic_host[I_ACTIVE * R + col]) continue;
-        any = 1;
-        const int it = g->ic_host[I_ITERS * R + col];
-        max_it = it > max_it ? it : max_it;
-        const double rel = g->sc_host[S_RELRES * R + col];
-        const double tgt = g->sc_host[S_TARGET * R + col] / g->sc_host[S_R0 * R + col];
-        if (it > 0 && rel > 0.0 && rel < 1.0) {
-          const double rate = std::log(rel) / it;   // per-iteration log reduction (< 0)
-          const double need = std::log(tgt / rel) / rate;
-          if (need > worst_log) worst_log = need;
-          if (rate > worst_rate || worst_rate == 0.0) worst_rate = rate;
-        } else {
-          if (4.0 > worst_log) worst_log = 4.0;
-        }
-      }
-      if (!any) break;
-      int chunk = (int)std::ceil(worst_log);
-      if (chunk < 1) chunk = 1;
-      if (chunk > 32) chunk = 32;
-      if (chunk > maxit - max_it + 1) chunk = maxit - max_it + 1;
-      if (chunk < 1) chunk = 1;
-      for (int k = kNumGraphs - 1; k >= 0 && st == BRAS_OK; --k)
-        if (chunk & (1 << k)) {
-          hipError_t e = hipGraphLaunch((*graphs)[k], s);
-          if (e != hipSuccess) st = fail(BRAS_EHIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
-        }
-      if (st) break;
+      const int chunk = predict_chunk(g, R, maxit);
+      if (chunk == 0) break;
+      if ((st = launch_chunk(*graphs, chunk, s))) break;
       if ((st = read_state(c, s))) break;
     }
     if (st) break;
@@ -443,4 +469,298 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   if (result == BRAS_EBREAKDOWN) return fail(result, "PCG breakdown (p.q <= 0, r.z <= 0 or non-finite values)");
   if (result == BRAS_ENOCONV) return fail(result, "PCG did not reach rtol=%g within maxit=%d", rtol, maxit);
   return BRAS_OK;
+}
+
+// ===========================================================================
+// Stationary iterations with the same operators (Section 4): the damped
+// fixed point u_{k+1} = u_k + omega C (f - M u_k) and the Chebyshev
+// semi-iteration on a spectral interval [lmin, lmax] of C M, both written as
+//     r_k = f - M u_k;  stop if ||r_k|| <= rtol ||r_0||;
+//     d_k = a_k d_{k-1} + c_k C r_k;  u_{k+1} = u_k + d_k
+// with coefficient sequences computed on the host (fixed point: a_k = 0,
+// c_k = omega; Chebyshev: the three-term recurrence of the Chebyshev
+// polynomials on [lmin, lmax]).  No dot products other than ||r_k||.
+// ===========================================================================
+namespace bras {
+
+// start: r_0 norm and target; coefficients of update 0
+__global__ void __launch_bounds__(kBS) k_st_init(int nb, int R, const double* __restrict__ part,
+                                                 double* __restrict__ sc, int* __restrict__ ic, double rtol,
+                                                 const double* __restrict__ coef, int cap) {
+  __shared__ double sh[kBS], rr_s[256];
+  block_sums_all(part, nb, R, rr_s, sh);
+  for (int col = threadIdx.x; col < R; col += kBS) {
+    const double nrm = sqrt(rr_s[col]);
+    sc[S_R0 * R + col] = nrm;
+    sc[S_TARGET * R + col] = rtol * nrm;
+    sc[S_RELRES * R + col] = nrm > 0.0 ? 1.0 : 0.0;
+    ic[I_ITERS * R + col] = 0;
+    if (!isfinite(nrm)) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_BREAK;
+    } else if (nrm == 0.0) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_OK;
+    } else {
+      ic[I_ACTIVE * R + col] = 1;
+      ic[I_STATUS * R + col] = ST_RUN;
+      sc[S_ALPHA * R + col] = coef[0];
+      sc[S_BETA * R + col] = coef[cap];
+    }
+  }
+}
+
+// after update k (= iters so far + 1): residual test, next coefficients
+__global__ void __launch_bounds__(kBS) k_st_fin(int nb, int R, const double* __restrict__ part,
+                                                double* __restrict__ sc, int* __restrict__ ic,
+                                                const double* __restrict__ coef, int cap, int maxit) {
+  __shared__ double sh[kBS], rr_s[256];
+  block_sums_all(part, nb, R, rr_s, sh);
+  for (int col = threadIdx.x; col < R; col += kBS) {
+    if (!ic[I_ACTIVE * R + col]) continue;
+    const int it = ic[I_ITERS * R + col] + 1;
+    ic[I_ITERS * R + col] = it;
+    const double nrm = sqrt(rr_s[col]);
+    sc[S_RR * R + col] = rr_s[col];
+    sc[S_RELRES * R + col] = nrm / sc[S_R0 * R + col];
+    if (!isfinite(nrm)) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_BREAK;
+    } else if (nrm <= sc[S_TARGET * R + col]) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_OK;
+    } else if (it >= maxit) {
+      ic[I_ACTIVE * R + col] = 0;
+      ic[I_STATUS * R + col] = ST_NOCONV;
+    } else {
+      sc[S_ALPHA * R + col] = coef[it];
+      sc[S_BETA * R + col] = coef[cap + it];
+    }
+  }
+}
+
+static CgArgs st_args(Ctx* c) {
+  CgState* g = c->cg;
+  CgArgs a;
+  a.x = g->x;
+  a.r = g->r;
+  a.p = g->p;   // d
+  a.b = g->b;
+  a.sc = g->sc;
+  a.ic = g->ic;
+  a.part0 = g->part[0];
+  return a;
+}
+
+static int st_iteration(Ctx* c, int pc, int maxit, hipStream_t s) {
+  CgState* g = c->cg;
+  const int R = g->R;
+  CgArgs a = st_args(c);
+  int st = st_precond_step(c, pc, a, R, s);
+  if (st) return st;
+  if ((st = st_mass_step(c, a, R, s))) return st;
+  k_st_fin<<<1, kBS, 0, s>>>(reduce_blocks(c, R), R, g->part[0], g->sc, g->ic, g->stcoef, g->stcoef_cap, maxit);
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+// Common driver; ca, cc: host coefficient sequences of length maxit.
+static int stationary(Ctx* c, int pc, const std::vector<double>& ca, const std::vector<double>& cc,
+                      const double* b_d, double* x_d, int nrhs, double rtol, int maxit, int* iters_h,
+                      double* relres_h, void* stream) {
+  int st = cg_alloc(c, nrhs);
+  if (st) return st;
+  CgState* g = c->cg;
+  hipStream_t us = (hipStream_t)stream, s = c->s_int;
+  const int R = nrhs;
+  const size_t vec = sizeof(double) * (size_t)c->n * R;
+  if (g->stcoef_cap < maxit) {
+    // a larger table moves: drop the stationary graphs that point at the old one
+    for (auto it = g->graphs.begin(); it != g->graphs.end();) {
+      if (it->first.kind == 1) {
+        for (auto ge : it->second) (void)hipGraphExecDestroy(ge);
+        it = g->graphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    if (g->stcoef) (void)hipFree(g->stcoef);
+    g->stcoef = nullptr;
+    g->stcoef_cap = 0;
+    if (hipMalloc((void**)&g->stcoef, sizeof(double) * 2 * (size_t)maxit) != hipSuccess)
+      return fail(BRAS_ENOMEM, "coefficient table allocation failed");
+    g->stcoef_cap = maxit;
+  }
+  std::vector<double> tab(2 * (size_t)g->stcoef_cap, 0.0);
+  for (int k = 0; k < maxit; ++k) {
+    tab[k] = ca[k];
+    tab[g->stcoef_cap + k] = cc[k];
+  }
+  std::vector<hipGraphExec_t>* graphs = nullptr;
+  if ((st = capture_graphs(c, CgState::Key{1, pc, 0, maxit}, [&](hipStream_t ss) { return st_iteration(c, pc, maxit, ss); },
+                           &graphs)))
+    return st;
+  hipEvent_t ev;
+  BRAS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  BRAS_HIP(hipEventRecord(ev, us));
+  BRAS_HIP(hipStreamWaitEvent(s, ev, 0));
+  BRAS_HIP(hipMemcpyAsync(g->stcoef, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
+  BRAS_HIP(hipMemcpyAsync(g->b, b_d, vec, hipMemcpyDeviceToDevice, s));
+  BRAS_HIP(hipMemcpyAsync(g->x, x_d, vec, hipMemcpyDeviceToDevice, s));
+  const int nbv = vector_blocks(c, R);
+  k_zero<<<nbv, kBS, 0, s>>>(c->n * R, g->p);
+  k_set_int<<<1, kBS, 0, s>>>(g->ic + I_ACTIVE * R, R, 1);   // every column takes part in the first residual
+  BRAS_HIP(hipGetLastError());
+  CgArgs a = st_args(c);
+  if ((st = st_mass_step(c, a, R, s)) == BRAS_OK) {
+    k_st_init<<<1, kBS, 0, s>>>(reduce_blocks(c, R), R, g->part[0], g->sc, g->ic, rtol, g->stcoef, g->stcoef_cap);
+    st = read_state(c, s);
+  }
+  while (st == BRAS_OK) {
+    const int chunk = predict_chunk(g, R, maxit);
+    if (chunk == 0) break;
+    if ((st = launch_chunk(*graphs, chunk, s))) break;
+    st = read_state(c, s);
+  }
+  if (st == BRAS_OK) {
+    hipError_t e = hipMemcpyAsync(x_d, g->x, vec, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) st = fail(BRAS_EHIP, "copy of the solution failed");
+    (void)hipEventRecord(ev, s);
+    (void)hipStreamWaitEvent(us, ev, 0);
+    (void)hipStreamSynchronize(s);
+  }
+  (void)hipEventDestroy(ev);
+  if (st) return st;
+  int result = BRAS_OK;
+  for (int col = 0; col < R; ++col) {
+    if (iters_h) iters_h[col] = g->ic_host[I_ITERS * R + col];
+    if (relres_h) relres_h[col] = g->sc_host[S_RELRES * R + col];
+    const int cs = g->ic_host[I_STATUS * R + col];
+    if (cs == ST_BREAK) result = BRAS_EBREAKDOWN;
+    else if (cs == ST_NOCONV && result == BRAS_OK) result = BRAS_ENOCONV;
+  }
+  if (result == BRAS_EBREAKDOWN) return fail(result, "non-finite residual");
+  if (result == BRAS_ENOCONV) return fail(result, "did not reach rtol=%g within maxit=%d", rtol, maxit);
+  return BRAS_OK;
+}
+
+static int check_stationary(bras_handle h, int pc, const double* b_d, double* x_d, int nrhs, double rtol, int maxit) {
+  BRAS_CHECK(h && b_d && x_d, "null argument");
+  Ctx* c = (Ctx*)h;
+  BRAS_CHECK(pc == BRAS_PC_JACOBI || pc == BRAS_PC_BRAS, "preconditioner must be BRAS_PC_JACOBI or BRAS_PC_BRAS");
+  BRAS_CHECK(nrhs >= 1 && nrhs <= c->max_rhs, "nrhs %d outside 1..max_rhs=%d", nrhs, c->max_rhs);
+  BRAS_CHECK(rtol > 0.0 && rtol < 1.0, "rtol must be in (0, 1)");
+  BRAS_CHECK(maxit >= 1 && maxit <= 1000000, "maxit must be in 1..1e6");
+  return BRAS_OK;
+}
+
+// y = a x (grid-stride)
+__global__ void __launch_bounds__(kBS) k_scale(int64_t n, double a, const double* __restrict__ x,
+                                               double* __restrict__ y) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = t0; t < n; t += stride) y[t] = a * x[t];
+}
+
+// partial sums of x . y per block
+__global__ void __launch_bounds__(kBS) k_dot(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                             double* __restrict__ partial) {
+  __shared__ double sh[kBS];
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double d = 0.0;
+  for (int64_t t = t0; t < n; t += stride) d = fma(x[t], y[t], d);
+  sh[threadIdx.x] = d;
+  block_partials(sh, 1, partial);
+}
+
+static int host_sum(const double* part_d, int nb, hipStream_t s, double* out) {
+  std::vector<double> h(nb);
+  BRAS_HIP(hipMemcpyAsync(h.data(), part_d, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  double v = 0.0;
+  for (int b = 0; b < nb; ++b) v += h[b];   // fixed order
+  *out = v;
+  return BRAS_OK;
+}
+
+}  // namespace bras
+
+extern "C" int bras_lambda_max(bras_handle h, int pc, const double* v0_d, int iters, double* lambda_h,
+                               void* stream) {
+  clear_error();
+  BRAS_CHECK(h && v0_d && lambda_h, "null argument");
+  Ctx* c = (Ctx*)h;
+  BRAS_CHECK(pc == BRAS_PC_JACOBI || pc == BRAS_PC_BRAS, "preconditioner must be BRAS_PC_JACOBI or BRAS_PC_BRAS");
+  BRAS_CHECK(iters >= 1, "iters must be >= 1");
+  int st = cg_alloc(c, 1);
+  if (st) return st;
+  CgState* g = c->cg;
+  hipStream_t us = (hipStream_t)stream, s = c->s_int;
+  hipEvent_t ev;
+  BRAS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  BRAS_HIP(hipEventRecord(ev, us));
+  BRAS_HIP(hipStreamWaitEvent(s, ev, 0));
+  const int nbv = vector_blocks(c, 1);
+  const int nbq = reduce_blocks(c, 1);
+  const int nbw = pc == BRAS_PC_BRAS ? reduce_blocks(c, 1) : vector_blocks(c, 1);
+  double vv = 0.0, lam = 0.0;
+  // v = v0 / ||v0||   (v in g->x, q = M v in g->q, w = C q in g->z)
+  k_dot<<<nbv, kBS, 0, s>>>(c->n, v0_d, v0_d, g->part[0]);
+  st = host_sum(g->part[0], nbv, s, &vv);
+  if (st == BRAS_OK && !(vv > 0.0 && std::isfinite(vv))) st = fail(BRAS_EINVAL, "start vector must be nonzero and finite");
+  if (st == BRAS_OK) k_scale<<<nbv, kBS, 0, s>>>(c->n, 1.0 / std::sqrt(vv), v0_d, g->x);
+  for (int k = 0; k < iters && st == BRAS_OK; ++k) {
+    double qv = 0.0, wq = 0.0, ww = 0.0;
+    if ((st = launch_mass(c, g->x, g->q, 1, s, g->x, g->part[0], nullptr))) break;
+    st = pc == BRAS_PC_BRAS ? launch_bras(c, g->q, g->z, 1, s, g->q, g->part[1], nullptr)
+                            : launch_jacobi(c, g->q, g->z, 1, s, g->q, g->part[1], nullptr);
+    if (st) break;
+    k_dot<<<nbv, kBS, 0, s>>>(c->n, g->z, g->z, g->part[2]);
+    if ((st = host_sum(g->part[0], nbq, s, &qv)) || (st = host_sum(g->part[1], nbw, s, &wq)) ||
+        (st = host_sum(g->part[2], nbv, s, &ww)))
+      break;
+    if (!(qv > 0.0) || !(ww > 0.0) || !std::isfinite(wq)) {
+      st = fail(BRAS_EBREAKDOWN, "power iteration broke down (non-positive or non-finite products)");
+      break;
+    }
+    lam = wq / qv;
+    k_scale<<<nbv, kBS, 0, s>>>(c->n, 1.0 / std::sqrt(ww), g->z, g->x);
+  }
+  (void)hipEventRecord(ev, s);
+  (void)hipStreamWaitEvent(us, ev, 0);
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(ev);
+  if (st) return st;
+  *lambda_h = lam;
+  return BRAS_OK;
+}
+
+extern "C" int fixed_point_solve(bras_handle h, int pc, double omega, const double* b_d, double* x_d, int nrhs,
+                                 double rtol, int maxit, int* iters_h, double* relres_h, void* stream) {
+  clear_error();
+  int st = check_stationary(h, pc, b_d, x_d, nrhs, rtol, maxit);
+  if (st) return st;
+  BRAS_CHECK(omega > 0.0 && std::isfinite(omega), "omega must be positive");
+  std::vector<double> ca(maxit, 0.0), cc(maxit, omega);
+  return stationary((Ctx*)h, pc, ca, cc, b_d, x_d, nrhs, rtol, maxit, iters_h, relres_h, stream);
+}
+
+extern "C" int chebyshev_solve(bras_handle h, int pc, double lmin, double lmax, const double* b_d, double* x_d,
+                               int nrhs, double rtol, int maxit, int* iters_h, double* relres_h, void* stream) {
+  clear_error();
+  int st = check_stationary(h, pc, b_d, x_d, nrhs, rtol, maxit);
+  if (st) return st;
+  BRAS_CHECK(lmin > 0.0 && lmax > lmin && std::isfinite(lmax), "need 0 < lmin < lmax");
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  std::vector<double> ca(maxit, 0.0), cc(maxit, 0.0);
+  cc[0] = 1.0 / theta;
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < maxit; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    ca[k] = rn * rho;
+    cc[k] = 2.0 * rn / delta;
+    rho = rn;
+  }
+  return stationary((Ctx*)h, pc, ca, cc, b_d, x_d, nrhs, rtol, maxit, iters_h, relres_h, stream);
 }

@@ -81,6 +81,27 @@ class MassProblem:
         st, its, rel = L.pcg_solve(self.h, pcode, b, x, rtol, maxit)
         return x, st, its, rel
 
+    # -- stationary iterations (Section 4) ------------------------------------
+    def lambda_max(self, pc="bras", v0=None, iters=50):
+        """Power-iteration estimate of lambda_max(C M)."""
+        import torch
+        if v0 is None:
+            raise ValueError("a start vector is required (seeded, e.g. workloads.vector)")
+        v0 = torch.as_tensor(v0, dtype=torch.float64, device=self.device)
+        return L.bras_lambda_max(self.h, L.PC[pc], v0, iters)
+
+    def fixed_point(self, b, pc="bras", omega=None, rtol=1e-10, maxit=5000, x0=None):
+        """Damped fixed point; returns (x, status, updates, relres)."""
+        x = self.vec(1 if b.dim() == 1 else b.shape[1]) if x0 is None else x0.clone()
+        st, its, rel = L.fixed_point_solve(self.h, L.PC[pc], omega, b, x, rtol, maxit)
+        return x, st, its, rel
+
+    def chebyshev(self, b, pc="bras", lmin=1.0, lmax=None, rtol=1e-10, maxit=5000, x0=None):
+        """Chebyshev semi-iteration on [lmin, lmax]; returns (x, status, updates, relres)."""
+        x = self.vec(1 if b.dim() == 1 else b.shape[1]) if x0 is None else x0.clone()
+        st, its, rel = L.chebyshev_solve(self.h, L.PC[pc], lmin, lmax, b, x, rtol, maxit)
+        return x, st, its, rel
+
     def set_density(self, rho_d):
         """Recompute element coefficients rho_K |det J_K| and the inverses (H1)."""
         self.rho_d = rho_d

@@ -1,0 +1,142 @@
+"""GPU parity of the stationary iterations (Section 4): power-iteration
+estimates of lambda_max(C M), the damped fixed point and the Chebyshev
+semi-iteration, against the oracle on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fe, mesh, assembly, pcg as opcg, stationary as ost
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("P", 2, 1, 11, 0.0, "f64"),
+    ("P", 3, 3, 4, 0.2, "f64"),
+    ("N1curl", 3, 2, 3, 0.2, "f64"),
+    ("N1curl", 3, 2, 3, 0.2, "f32"),
+    ("RT", 3, 4, 2, 0.2, "f64"),
+]
+_cache = {}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def ids(c):
+    return "%s%d-%dd-N%d-%s" % (c[0], c[2], c[1], c[3], c[5])
+
+
+def build(case, max_rhs=4):
+    if case in _cache:
+        return _cache[case]
+    from paper_2607_12138_amd.problem import MassProblem
+    family, dim, deg, N, jit, prec = case
+    seed = 2000 + N
+    ref = fe.reference_element(family, dim, deg)
+    coords, cells = mesh.structured_mesh(dim, N, jitter=jit, seed=seed)
+    orc = assembly.Problem(ref, coords, cells)
+    say("setup %s" % (case,))
+    gpu = MassProblem(family, dim, deg, N, jitter=jit, seed=seed, prec=prec, max_rhs=max_rhs)
+    _cache[case] = (orc, gpu)
+    return orc, gpu
+
+
+def to_t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+@pytest.mark.parametrize("pc", ["bras", "jacobi"])
+def test_lambda_max_matches_oracle(case, pc):
+    orc, gpu = build(case)
+    v0 = workloads.vector(orc.n, 7)
+    C = orc.B.dot if pc == "bras" else opcg.jacobi(orc.diag)
+    lo = ost.power_lambda_max(orc.M, C, v0, iters=50)
+    say("lambda_max %s %s" % (pc, case))
+    lg = gpu.lambda_max(pc, v0, 50)
+    tol = 1e-10 if (case[5] == "f64" or pc == "jacobi") else 1e-5
+    assert abs(lg - lo) <= tol * lo
+    assert lg >= 1.0 - 1e-12 or pc == "jacobi"          # BRAS: lambda >= lambda_min >= 1
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+@pytest.mark.parametrize("pc", ["bras", "jacobi"])
+def test_fixed_point_matches_oracle(case, pc):
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(case)
+    tol = 1e-10 if case[5] == "f64" else 1e-8
+    v0 = workloads.vector(orc.n, 7)
+    C = orc.B.dot if pc == "bras" else opcg.jacobi(orc.diag)
+    lam = ost.power_lambda_max(orc.M, C, v0, iters=50)
+    om = 2.0 / (1.0 + lam) if pc == "bras" else 1.0 / lam
+    f = workloads.rhs(orc.n, 1, 43)
+    xo, ito, ok, _ = ost.fixed_point(orc.M, f, C, om, tol=tol)
+    assert ok
+    say("fixed point %s %s" % (pc, case))
+    x, st, its, rel = gpu.fixed_point(to_t(f), pc, om, rtol=tol)
+    assert st == L.BRAS_OK
+    x = x.cpu().numpy()
+    true_rel = np.linalg.norm(f - orc.M @ x) / np.linalg.norm(f)
+    assert true_rel <= tol and abs(rel[0] - true_rel) <= 1e-3 * tol + 1e-15   # residuals of different roundings of M x
+    if case[5] == "f64" or pc == "jacobi":
+        assert abs(int(its[0]) - ito) <= 1
+    else:
+        assert abs(int(its[0]) - ito) <= 3
+
+
+@pytest.mark.parametrize("case", CASES, ids=ids)
+def test_chebyshev_matches_oracle(case):
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(case)
+    tol = 1e-10 if case[5] == "f64" else 1e-8
+    lam = ost.power_lambda_max(orc.M, orc.B.dot, workloads.vector(orc.n, 7), iters=50)
+    lmax = 1.02 * lam                                   # a little room above the estimate
+    f = workloads.rhs(orc.n, 1, 44)
+    xo, ito, ok, _ = ost.chebyshev(orc.M, f, orc.B.dot, 1.0, lmax, tol=tol)
+    assert ok
+    say("chebyshev %s" % (case,))
+    x, st, its, rel = gpu.chebyshev(to_t(f), "bras", 1.0, lmax, rtol=tol)
+    assert st == L.BRAS_OK
+    x = x.cpu().numpy()
+    assert np.linalg.norm(f - orc.M @ x) <= tol * np.linalg.norm(f)
+    assert abs(int(its[0]) - ito) <= (1 if case[5] == "f64" else 3)
+    assert np.linalg.norm(x - xo) <= 1e3 * tol * np.linalg.norm(xo)
+
+
+def test_multi_column_and_edge_cases():
+    from paper_2607_12138_amd import _lib as L
+    case = CASES[2]
+    orc, gpu = build(case)
+    F = workloads.rhs(orc.n, 3, 45)
+    F[:, 1] *= 1e-3
+    F[:, 2] = 0.0                                        # converged before any update
+    lam = ost.power_lambda_max(orc.M, orc.B.dot, workloads.vector(orc.n, 7))
+    om = 2.0 / (1.0 + lam)
+    say("fixed point, 3 columns")
+    X, st, its, rel = gpu.fixed_point(to_t(F), "bras", om, rtol=1e-10)
+    assert st == L.BRAS_OK and its[2] == 0
+    X = X.cpu().numpy()
+    for r in range(2):
+        xo, ito, ok, _ = ost.fixed_point(orc.M, F[:, r], orc.B.dot, om, tol=1e-10)
+        assert abs(int(its[r]) - ito) <= 1
+        x1, _, i1, _ = gpu.fixed_point(to_t(np.ascontiguousarray(F[:, r])), "bras", om, rtol=1e-10)
+        assert int(i1[0]) == int(its[r])
+        assert np.max(np.abs(x1.cpu().numpy() - X[:, r])) <= 1e-12 * np.max(np.abs(X[:, r]))
+    assert float(np.abs(X[:, 2]).max()) == 0.0
+    say("stationary error paths")
+    b = to_t(F[:, 0].copy())
+    with pytest.raises(L.BrasError):
+        gpu.fixed_point(b, "bras", -1.0)
+    with pytest.raises(L.BrasError):
+        gpu.chebyshev(b, "bras", 2.0, 1.5)
+    with pytest.raises(L.BrasError):
+        L.fixed_point_solve(gpu.h, L.PC_NONE, 0.5, b, gpu.vec(), 1e-10, 10)
+    st, its, rel = L.fixed_point_solve(gpu.h, L.PC_BRAS, om, b, gpu.vec(), 1e-10, 1)
+    assert st == L.BRAS_ENOCONV and its[0] == 1
+    with pytest.raises(L.BrasError):
+        gpu.lambda_max("bras", np.zeros(orc.n))
