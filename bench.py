@@ -103,6 +103,34 @@ def time_apply(fn, x, y, reps):
     return e0.elapsed_time(e1) / reps * 1e3   # microseconds
 
 
+def stationary_section(prob, b, w, steps):
+    """Section 4's other solvers on the same system: damped fixed point with
+    omega_bras = 2/(1 + lambda_max) and omega_diag = 1/lambda_max, and the
+    Chebyshev semi-iteration on [1, 1.02 lambda_max] with BRAS (lambda_min >= 1,
+    Cor. bras_lambda_min).  lambda_max by 50 power iterations from a seeded
+    vector; as in the paper, its estimation is not part of the solve time."""
+    import torch
+    v0 = workloads.vector(prob.n, w.seed(4))
+    lam_b = prob.lambda_max("bras", v0, 50)
+    lam_d = prob.lambda_max("jacobi", v0, 50)
+    runs = {
+        "fixed_point_bras": lambda: prob.fixed_point(b, "bras", 2.0 / (1.0 + lam_b), rtol=w.tol),
+        "fixed_point_jacobi": lambda: prob.fixed_point(b, "jacobi", 1.0 / lam_d, rtol=w.tol),
+        "chebyshev_bras": lambda: prob.chebyshev(b, "bras", 1.0, 1.02 * lam_b, rtol=w.tol),
+    }
+    out = {"lambda_max_bras": round(lam_b, 6), "lambda_max_jacobi": round(lam_d, 6)}
+    for name, fn in runs.items():
+        fn()                                             # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st, its, rel = fn()
+        torch.cuda.synchronize()
+        out[name] = {"ms": round((time.perf_counter() - t0) / steps * 1e3, 4), "iterations": int(max(its)),
+                     "status": int(st), "relres": float(np.max(rel))}
+    return out
+
+
 def cpu_baseline(w, its_gpu, budget_s=20.0):
     """The oracle's BRAS-PCG on the same workload, matrix-free (its element
     route), one thread.  Setup (mesh, numbering, element matrices and
@@ -153,6 +181,8 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(workloads.BY_NAME))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--stationary-steps", type=int, default=2,
+                    help="timed fixed-point / Chebyshev solves of each kind (0: skip)")
     ap.add_argument("--mode", choices=["full", "apply", "copy"], default="full",
                     help="apply: only back-to-back BRAS applies (for counter runs); "
                          "copy: a device copy of known size (counter calibration)")
@@ -180,7 +210,7 @@ def main():
     t0 = time.perf_counter()
     prob = MassProblem(w.family, w.dim, w.degree, w.N, jitter=w.jitter, seed=w.mesh_seed, rho=rho, prec=w.prec,
                        max_rhs=w.nrhs)
-    variant = prob.autotune(w.nrhs)
+    variant = prob.autotune(w.nrhs) if a.mode == "full" else -1
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print("setup done: n=%d E=%d n_loc=%d (%.1f s)" % (prob.n, prob.E, prob.n_loc, setup_s), file=sys.stderr,
@@ -203,6 +233,10 @@ def main():
     jac_ms, st_j, its_j, rel_j, xj = time_solves(prob, b, "jacobi", w.tol, a.steps)
     print("solves done: bras %.3f ms (%s its), jacobi %.3f ms (%s its)" % (bras_ms, its_b, jac_ms, its_j),
           file=sys.stderr, flush=True)
+    stat = None
+    if a.stationary_steps > 0:
+        stat = stationary_section(prob, b, w, a.stationary_steps)
+        print("stationary done: %s" % json.dumps(stat), file=sys.stderr, flush=True)
     x = prob.vec(w.nrhs)
     x.copy_(b)
     y = prob.vec(w.nrhs)
@@ -243,6 +277,7 @@ def main():
         "source_digest": source_digest(),
         "setup_s": round(setup_s, 3),
         "element_pass_variant": int(variant),
+        "stationary": stat,
     }
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
