@@ -24,7 +24,7 @@ def metric(kind, coords, cells, rho=None):
     det = np.linalg.det(J)
     adet = np.abs(det)
     r = np.ones(len(cells)) if rho is None else np.asarray(rho, dtype=float)
-    if kind == "P":
+    if kind in ("P", "B"):          # H1 (Lagrange or Bernstein basis)
         return r * adet
     if kind == "N1curl":
         Jinv = np.linalg.inv(J)
@@ -37,7 +37,7 @@ def metric(kind, coords, cells, rho=None):
 def element_matrices(ref, coords, cells, rho=None):
     """M_K for every element, [E, n_loc, n_loc]."""
     G = metric(ref.family, coords, cells, rho)
-    if ref.family == "P":
+    if ref.family in ("P", "B"):
         return G[:, None, None] * ref.mass[None]
     return np.einsum("kab,abij->kij", G, ref.mass)
 

@@ -14,6 +14,13 @@ Families (Section 3 names them after Firedrake; the readings used here):
            degree-k homogeneous fields u with x . u = 0 (3D) or (-y, x) P~_{k-1}
            (2D).  Degrees of freedom are integral moments.
 * "RT"     Raviart-Thomas RT_k = [P_{k-1}]^d + x P~_{k-1}, integral moments.
+* "B"      H1 P_p in the Bernstein basis (Section 4, Table h1_mass_solve):
+           B_alpha = p!/(alpha_0! ... alpha_d!) lambda_0^alpha_0 ... lambda_d^alpha_d
+           over barycentric multi-indices |alpha| = p, lambda_0 = 1 - sum x_i,
+           lambda_i = x_i.  A function whose multi-index vanishes off a
+           sub-simplex is supported on it there, so with cells listing sorted
+           vertices neighbouring cells agree on shared functions; local order
+           as for Lagrange nodes (same multi-indices).
 
 Moment degrees of freedom (the variant is not stated in the paper; this is
 the integral-moment reading).  Entities are taken with sorted vertices
@@ -366,13 +373,63 @@ def _functionals(family, d, k, mons):
     return rows, tuple(counts), None
 
 
+def _bernstein(d, k, mons):
+    """Bernstein basis (exact rationals) in the local order of the Lagrange
+    nodes: vertices, then edges, faces, interior, each entity's multi-indices
+    in descending lexicographic order.  Returns (polynomials, counts)."""
+    lam = [poly.add(poly.const(d, Fraction(1)), sum_vars(d), -1)] + [poly.var(d, i) for i in range(d)]
+    out = []
+    counts = [0] * (d + 1)
+    for edim in range(d + 1):
+        for verts in local_entities(d, edim):
+            idxs = [(k,)] if edim == 0 else interior_multi_indices(len(verts), k)
+            counts[edim] = len(idxs)
+            for beta in idxs:
+                alpha = [0] * (d + 1)
+                for v, b in zip(verts, beta):
+                    alpha[v] = b
+                coef = Fraction(math.factorial(k), math.prod(math.factorial(a) for a in alpha))
+                p = poly.const(d, coef)
+                for i, a in enumerate(alpha):
+                    p = poly.mul(p, poly.power(lam[i], a, d))
+                out.append(p)
+    return out, tuple(counts)
+
+
+def sum_vars(d):
+    p = {}
+    for i in range(d):
+        p = poly.add(p, poly.var(d, i))
+    return p
+
+
+def _bernstein_element(dim, degree):
+    mons = poly.monomials(dim, degree)
+    index = {m: i for i, m in enumerate(mons)}
+    polys, counts = _bernstein(dim, degree, mons)
+    nb = len(polys)
+    coef = [[Fraction(0)] * len(mons) for _ in range(nb)]
+    for j, p in enumerate(polys):
+        for e, c in p.items():
+            coef[j][index[e]] += c
+    mass = np.empty((nb, nb))
+    for i in range(nb):
+        for j in range(i, nb):
+            v = poly.integrate(poly.mul(polys[i], polys[j]), dim)   # exact rational
+            mass[i, j] = mass[j, i] = float(v)
+    basis = np.array([[[float(c) for c in coef[j]]] for j in range(nb)])
+    return RefElement("B", dim, degree, 1, nb, counts, mons, basis, mass, None)
+
+
 @lru_cache(maxsize=None)
 def reference_element(family, dim, degree):
     """Construct the reference element (basis coefficients and mass tables)."""
-    if family not in ("P", "N1curl", "RT"):
+    if family not in ("P", "N1curl", "RT", "B"):
         raise ValueError(family)
     if dim not in (2, 3) or degree < 1:
         raise ValueError("unsupported element")
+    if family == "B":
+        return _bernstein_element(dim, degree)
     with mp.workdps(DPS):
         mons = poly.monomials(dim, degree)
         m = len(mons)
@@ -422,7 +479,7 @@ def reference_element(family, dim, degree):
 
 
 def element_dim(family, d, k):
-    if family == "P":
+    if family in ("P", "B"):
         return math.comb(k + d, d)
     if family == "RT":
         return d * math.comb(k - 1 + d, d) + math.comb(k - 1 + d - 1, d - 1)

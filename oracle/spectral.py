@@ -90,7 +90,7 @@ def projector_lambda_max(pi, mats, n):
 
 def metric_contrast(kind, G):
     """beta/alpha bound of Cor. bras_piola_metric_contrast from per-element G."""
-    if kind == "P":
+    if kind in ("P", "B"):
         return float(np.max(G) / np.min(G))
     ev = np.linalg.eigvalsh(G)
     return float(ev[:, -1].max() / ev[:, 0].min())

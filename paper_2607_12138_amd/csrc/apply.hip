@@ -3,19 +3,21 @@
 // M = P^T M_br P (eq. M_PMbrP), diag(M)^-1, and the density gradient.
 //
 // Every operator is two passes over device memory:
-//   element pass  a 256-thread work-group owns floor(256/n_loc) whole
-//                 elements, one thread per element row: the thread gathers
-//                 one entry of the input (optionally an axpy of two vectors,
-//                 times D^-1) into LDS, then forms its row of M_K w_K (or
-//                 M_K^-1 w_K) from the element's gathered vector and writes
-//                 it to the broken vector in element-major order K*n_loc + l,
-//                 so loads of the map and stores of the result are contiguous;
-//   reduce pass   one thread per (conforming DOF, column): sum the DOF's
-//                 broken copies in the fixed order of the transpose map, scale
-//                 by D^-1 (BRAS), and either store the result, or run the CG
-//                 update that consumes it, with dot products accumulated into
-//                 per-block partials that the last work-group sums in block
-//                 order (no floating-point atomics anywhere).
+//   element pass  gathers each element's inputs (optionally an axpy of two
+//                 vectors, times D^-1 for the H1 scaled form), multiplies by
+//                 M_K or the folded inverse and writes the products to the
+//                 broken vector zb[l][K][column] (local-index-major, so the 64
+//                 lanes of a wavefront, one element each, store contiguously).
+//                 Kernels: k_elem below (H1 scaled form), k_elem_lane
+//                 (elem_lane.h: per-element matrices, n_loc <= 36),
+//                 k_elem_mfma (elem_mfma.hip: n_loc > 36, FP64 matrix cores),
+//                 k_bras_bf16 (bf16.hip: BF16 Gram factors on matrix cores);
+//   reduce pass   sums each conforming DOF's broken copies in the fixed order
+//                 of the transpose map (scaled by D^-1 for the H1 form) and
+//                 either stores the result or runs the CG / stationary update
+//                 that consumes it, writing per-block dot-product partials
+//                 that a later kernel sums in block order (no floating-point
+//                 atomics anywhere).
 // Vectors with several columns are [n][R] (column fastest).
 #include <cmath>
 

@@ -7,13 +7,16 @@
 //           (or after maxit products M p); z = C r; rho' = r.z;
 //           beta = rho'/rho; rho = rho'
 //
-// Each iteration is two fused operator passes (apply.hip):
+// Each iteration is two fused operator passes (apply.hip) and one or two
+// one-block kernels:
 //   mass pass    element pass on z + beta p, reduce pass writes q and the new
-//                p and finishes alpha = rho / p.q in its last work-group;
-//   precond pass element pass on r - alpha q (BRAS), reduce pass updates
-//                x and r, writes z and finishes ||r||, the stopping test,
-//                beta and rho in its last work-group (Jacobi / none: one
-//                vector pass).
+//                p and the p.q partials;
+//   alpha        alpha = rho / p.q, in a one-block kernel on large meshes or
+//                in the prologue of the next pass's work-groups on small ones;
+//   precond pass element pass on r - alpha q (BRAS), reduce pass updates x and
+//                r, writes z and the r.r, r.z partials (Jacobi / none: one
+//                vector pass);
+//   finish       one block: ||r||, the stopping test, beta and rho.
 // Scalars and convergence flags stay in device memory; every dot product is
 // a fixed-order two-stage reduction, so results are bitwise reproducible.
 // Iterations are captured into hipGraphs of 1, 2, 4, 8, 16 and 32
@@ -21,7 +24,8 @@
 // host reads the flags only between graph launches.  When the stored BRAS
 // inverses are FP32/BF16 the flexible beta = r_new.(z_new - z_old)/rho_old
 // is used and, at exit, CG restarts from x while the true residual is above
-// the tolerance.
+// the tolerance.  The fixed-point and Chebyshev iterations at the end of this
+// file share the passes and the graph machinery.
 #include <cmath>
 #include <cstring>
 #include <map>

@@ -10,7 +10,7 @@ from tests.quadrature import simplex_rule, gauss01, orthonormal_numeric
 ELEMENTS = [("P", 2, 1), ("P", 2, 2), ("P", 2, 3), ("P", 2, 4), ("P", 3, 1), ("P", 3, 2),
             ("P", 3, 3), ("P", 3, 4), ("RT", 2, 1), ("RT", 2, 3), ("N1curl", 2, 2),
             ("RT", 3, 1), ("RT", 3, 2), ("RT", 3, 4), ("N1curl", 3, 1), ("N1curl", 3, 2),
-            ("N1curl", 3, 3)]
+            ("N1curl", 3, 3), ("B", 2, 2), ("B", 2, 4), ("B", 3, 3), ("B", 3, 4)]
 
 
 def ref_volume(d):
@@ -258,3 +258,61 @@ def test_piola_element_matrix_against_physical_quadrature(family):
             phys = np.einsum("ab,pjb->pja", J / det, Phi)
         Mq = abs(det) * np.einsum("p,pia,pja->ij", wts, phys, phys)
         assert np.max(np.abs(Mq - mats[K])) < 1e-13 * np.max(np.abs(mats[K]))
+
+
+@pytest.mark.parametrize("d,k", [(2, 1), (2, 3), (2, 4), (3, 2), (3, 4)])
+def test_bernstein_closed_form_mass(d, k):
+    """int_T B_a B_b = (k!)^2 (a+b)! / (a! b! (2k+d)!) on the unit simplex
+    (multi-index factorials are products over the d+1 entries)."""
+    from math import factorial, prod
+    e = fe.reference_element("B", d, k)
+    alphas = []
+    for edim in range(d + 1):
+        for verts in fe.local_entities(d, edim):
+            idxs = [(k,)] if edim == 0 else fe.interior_multi_indices(len(verts), k)
+            for beta in idxs:
+                a = [0] * (d + 1)
+                for v, b in zip(verts, beta):
+                    a[v] = b
+                alphas.append(a)
+    fac = lambda a: prod(factorial(x) for x in a)            # noqa: E731
+    M = np.array([[factorial(k) ** 2 * fac([x + y for x, y in zip(a, b)]) / (fac(a) * fac(b) * factorial(2 * k + d))
+                   for b in alphas] for a in alphas])
+    assert np.max(np.abs(M - e.mass)) <= 1e-15 * np.max(M)
+
+
+@pytest.mark.parametrize("d,k", [(2, 3), (3, 4)])
+def test_bernstein_partition_of_unity_and_positivity(d, k):
+    e = fe.reference_element("B", d, k)
+    pts, _ = simplex_rule(d, 6)
+    v = e.eval(pts)[:, :, 0]
+    assert np.allclose(v.sum(axis=1), 1.0, atol=1e-14)
+    assert v.min() >= -1e-15
+    # vertex functions are 1 at their vertex and every other function vanishes there
+    V = e.eval(np.array(fe.ref_vertices(d), dtype=float))[:, :, 0]
+    assert np.allclose(V[:, :d + 1], np.eye(d + 1), atol=1e-15) and np.allclose(V[:, d + 1:], 0.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("d,k", [(2, 3), (3, 2), (3, 3)])
+def test_bernstein_global_conformity_and_l2_norm(d, k):
+    """The local Bernstein coefficients of one global polynomial agree on
+    every shared entity (so P is 0/1 with the sorted-vertex numbering), and
+    u' M u equals its L2 norm squared."""
+    ref = fe.reference_element("B", d, k)
+    coords, cells = mesh.structured_mesh(d, 2, jitter=0.2, seed=6)
+    pr = assembly.Problem(ref, coords, cells, need_bras=False)
+    c = np.array([0.4, -1.3, 0.8])[:d]
+    f = lambda x: 1.0 + (x @ c) ** k - 0.5 * x[:, 0] * x[:, -1]      # noqa: E731
+    Js = mesh.jacobians(coords, cells)
+    pts, wts = simplex_rule(d, 2 * k + 2)
+    B = ref.eval(pts)[:, :, 0]
+    w = np.empty((len(cells), ref.n_loc))
+    for K in range(len(cells)):
+        x = coords[cells[K, 0]] + pts @ Js[K].T
+        w[K] = np.linalg.lstsq(B, f(x), rcond=None)[0]               # exact: f is in the local space
+    u = np.zeros(pr.n)
+    u[pr.pi.ravel()] = w.ravel()
+    assert np.max(np.abs(w - u[pr.pi])) < 1e-11
+    tot = sum(abs(np.linalg.det(Js[K])) * np.sum(wts * f(coords[cells[K, 0]] + pts @ Js[K].T) ** 2)
+              for K in range(len(cells)))
+    assert abs(u @ (pr.M @ u) - tot) < 1e-11 * tot
