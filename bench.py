@@ -41,7 +41,7 @@ def algorithmic_bytes(w, n, E, n_loc, R, prec):
     not counted."""
     nbr = E * n_loc
     vec = 8.0 * n * R
-    if w.family == "P":
+    if w.family in ("P", "B"):
         elem = 8.0 * E          # one coefficient per element (shared reference inverse)
         dinv = 8.0 * n
     else:
@@ -259,7 +259,7 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32 apply / f64 CG", "bf16": "bf16 apply / f64 CG"}[w.prec],
         "data": "synthetic: seeded Kuhn mesh and U[-1,1] right-hand side",
         "config": {
-            "workload": w.name, "family": {"P": "H1 Lagrange", "N1curl": "N1curl", "RT": "RT"}[w.family],
+            "workload": w.name, "family": {"P": "H1 Lagrange", "B": "H1 Bernstein", "N1curl": "N1curl", "RT": "RT"}[w.family],
             "degree": w.degree, "dim": w.dim, "mesh": "%d^%d Kuhn simplices, jitter %.1fh" % (w.N, w.dim, w.jitter),
             "n": prob.n, "E": prob.E, "n_loc": prob.n_loc, "nrhs": w.nrhs, "rtol": w.tol, "apply_precision": w.prec,
         },

@@ -43,10 +43,12 @@ extern "C" {
 #define BRAS_EBREAKDOWN -5   /* PCG breakdown: p.q <= 0, r.z <= 0, NaN / Inf  */
 #define BRAS_ENOMEM     -6   /* device allocation failed                      */
 
-/* ---- element families (Section 3: Lagrange, N1curl, RT) ----------------- */
+/* ---- element families (Section 4: Lagrange, Bernstein, N1curl, RT) ------ */
 #define BRAS_H1    0         /* H1 Lagrange P_p, GLL-based nodes             */
 #define BRAS_HCURL 1         /* first-kind Nedelec N1curl_k, covariant Piola */
 #define BRAS_HDIV  2         /* Raviart-Thomas RT_k, contravariant Piola     */
+#define BRAS_H1_BERNSTEIN 3  /* H1 P_p in the Bernstein basis p!/alpha! lambda^alpha,
+                                local order as the Lagrange nodes (same multi-indices) */
 
 /* ---- element-data forms accepted by bras_setup -------------------------- */
 #define BRAS_ELEM_EXPLICIT   0  /* elem_d: E x n_loc x n_loc float64 M_K, row-major */

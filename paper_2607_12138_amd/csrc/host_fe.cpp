@@ -444,12 +444,53 @@ int lu_solve(int n, std::vector<ld>& A, int m, std::vector<ld>& B) {
 
 }  // namespace
 
+// Bernstein reference mass in closed form: on the unit simplex
+//   int B_a B_b = (k!)^2 (a+b)! / (a! b! (2k+d)!)
+// (multi-index factorials are products over the d+1 barycentric entries),
+// in the local order of the Lagrange nodes (vertices, edges, faces, interior;
+// an entity's multi-indices in descending lexicographic order).
+static void bernstein_mass(int d, int k, double* out) {
+  std::vector<std::vector<int>> alphas;
+  for (int edim = 0; edim <= d; ++edim)
+    for (auto& verts : combos(d + 1, edim + 1)) {
+      std::vector<std::vector<int>> idxs;
+      if (edim == 0)
+        idxs = {{k}};
+      else
+        interior_multi(edim + 1, k, idxs);
+      for (auto& beta : idxs) {
+        std::vector<int> a(d + 1, 0);
+        for (size_t v = 0; v < verts.size(); ++v) a[verts[v]] = beta[v];
+        alphas.push_back(a);
+      }
+    }
+  auto fact = [](int m) {
+    ld f = 1;
+    for (int i = 2; i <= m; ++i) f *= i;
+    return f;
+  };
+  const int nl = (int)alphas.size();
+  for (int i = 0; i < nl; ++i)
+    for (int j = 0; j < nl; ++j) {
+      ld num = fact(k) * fact(k), den = fact(2 * k + d);
+      for (int c = 0; c <= d; ++c) {
+        num *= fact(alphas[i][c] + alphas[j][c]);
+        den *= fact(alphas[i][c]) * fact(alphas[j][c]);
+      }
+      out[i * nl + j] = (double)(num / den);
+    }
+}
+
 extern "C" int bras_reference_mass(int family, int dim, int degree, double* ref_h) {
   bras::clear_error();
   if (!ref_h) return fail(BRAS_EINVAL, "null output pointer");
   int nl, counts[4];
   int st = bras::element_counts(family, dim, degree, &nl, counts);
   if (st) return st;
+  if (family == BRAS_H1_BERNSTEIN) {
+    bernstein_mass(dim, degree, ref_h);
+    return BRAS_OK;
+  }
   const int d = dim, k = degree;
   const int ncomp = family == BRAS_H1 ? 1 : d;
 

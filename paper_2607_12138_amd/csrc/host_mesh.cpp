@@ -36,7 +36,7 @@ int element_counts(int family, int dim, int degree, int* n_loc, int counts[4]) {
   for (int i = 0; i < 4; ++i) counts[i] = 0;
   if (dim != 2 && dim != 3) return fail(BRAS_EINVAL, "dim must be 2 or 3 (got %d)", dim);
   int p = degree;
-  if (family == BRAS_H1) {
+  if (family == BRAS_H1 || family == BRAS_H1_BERNSTEIN) {
     if (p < 1 || p > 6) return fail(BRAS_EINVAL, "H1 degree must be 1..6 (got %d)", p);
     counts[0] = 1;
     counts[1] = p - 1;

@@ -27,7 +27,7 @@ __global__ void k_geometry(int family, int dim, const double* __restrict__ X, co
   for (int i = 0; i < nv; ++i)
     if (c[i] < 0 || c[i] >= nvert) {
       // invalid vertex id: a NaN coefficient makes setup fail with ENOTSPD
-      const int cnt = family == BRAS_H1 ? 1 : nsym;
+      const int cnt = (family == BRAS_H1 || family == BRAS_H1_BERNSTEIN) ? 1 : nsym;
       for (int p = 0; p < cnt; ++p) out[K * cnt + p] = __longlong_as_double(0x7ff8000000000000LL);
       return;
     }
@@ -41,7 +41,7 @@ __global__ void k_geometry(int family, int dim, const double* __restrict__ X, co
           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
   const double adet = fabs(det);
   const double r = rho ? rho[K] : 1.0;
-  if (family == BRAS_H1) {
+  if (family == BRAS_H1 || family == BRAS_H1_BERNSTEIN) {
     out[K] = r * adet;
     return;
   }
@@ -533,7 +533,8 @@ extern "C" int bras_geometry(int family, int dim, int64_t nvert, const double* c
                              const int32_t* cells_d, const double* rho_d, double* elem_d, void* stream) {
   clear_error();
   BRAS_CHECK(dim == 2 || dim == 3, "dim must be 2 or 3");
-  BRAS_CHECK(family == BRAS_H1 || family == BRAS_HCURL || family == BRAS_HDIV, "unknown family %d", family);
+  BRAS_CHECK(family == BRAS_H1 || family == BRAS_HCURL || family == BRAS_HDIV || family == BRAS_H1_BERNSTEIN,
+             "unknown family %d", family);
   BRAS_CHECK(coords_d && cells_d && elem_d, "null pointer argument");
   BRAS_CHECK(nvert > 0 && ncell > 0, "empty mesh");
   hipStream_t s = (hipStream_t)stream;

@@ -27,7 +27,7 @@ class MassProblem:
         self.cells_d = torch.from_numpy(self.cells).to(dev)
         self.l2g_d = torch.from_numpy(self.l2g).to(dev)
         self.ref_d = torch.from_numpy(np.ascontiguousarray(self.ref)).to(dev)
-        if self.family == L.H1:
+        if L.is_h1(self.family):
             self.form, self.nsym = L.ELEM_SCALED_REF, 0
             self.elem_d = torch.empty(self.E, dtype=torch.float64, device=dev)
             self.dcoef_d = torch.empty(self.E, dtype=torch.float64, device=dev)

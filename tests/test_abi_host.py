@@ -29,7 +29,8 @@ def test_mesh_bit_exact(dim, N, jit, seed):
 
 
 CASES = [("P", 2, 1), ("P", 2, 3), ("P", 3, 1), ("P", 3, 3), ("P", 3, 4), ("N1curl", 3, 1), ("N1curl", 3, 2),
-         ("RT", 3, 1), ("RT", 3, 4), ("RT", 2, 2), ("N1curl", 2, 3), ("P", 2, 5)]
+         ("RT", 3, 1), ("RT", 3, 4), ("RT", 2, 2), ("N1curl", 2, 3), ("P", 2, 5), ("B", 2, 3), ("B", 3, 2),
+         ("B", 3, 4)]
 
 
 @pytest.mark.parametrize("family,dim,deg", CASES)
@@ -54,7 +55,7 @@ def test_dofmap_bit_exact(family, dim, deg):
 def test_reference_mass_matches_oracle(family, dim, deg):
     lib_tab = L.bras_reference_mass(L.FAMILY[family], dim, deg)
     ref = ofe.reference_element(family, dim, deg)
-    if family == "P":
+    if family in ("P", "B"):
         expect = ref.mass[None]
         got = lib_tab[None]
     else:

@@ -24,6 +24,8 @@ CASES = [
     ("RT", 3, 4, 2, 0.2, False, "f64"),
     ("RT", 2, 3, 6, 0.2, False, "f32"),
     ("RT", 3, 4, 2, 0.2, False, "f32"),     # n_loc 70: FP32 inverses on the FP64 matrix cores
+    ("B", 3, 4, 3, 0.2, False, "f64"),      # Bernstein basis (Table h1_mass_solve)
+    ("B", 2, 3, 6, 0.0, True, "f64"),
 ]
 
 _cache = {}

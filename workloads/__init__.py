@@ -20,7 +20,7 @@ SEED_BASE = 0x260712138
 @dataclass(frozen=True)
 class Workload:
     name: str
-    family: str          # "P" (H1 Lagrange), "N1curl", "RT"
+    family: str          # "P" (H1 Lagrange), "B" (H1 Bernstein), "N1curl", "RT"
     dim: int
     degree: int
     N: int               # squares / cubes per side
@@ -50,6 +50,8 @@ WORKLOADS = [
     Workload("n1curl2_3d_48_jit", "N1curl", 3, 2, 48, 0.2, 1, "f32", 1e-8, 3),
     Workload("rt4_3d_32_jit_r32", "RT", 3, 4, 32, 0.2, 32, "bf16", 1e-8, 4),
     Workload("h1p4_3d_32_rho", "P", 3, 4, 32, 0.0, 1, "f64", 1e-10, 5, density=True),
+    # the paper's largest H1 gap: Bernstein p = 4 in 3D at about 1e6 DOFs (Table h1_mass_solve)
+    Workload("h1b4_3d_25", "B", 3, 4, 25, 0.0, 1, "f64", 1e-10, 6),
 ]
 
 BY_NAME = {w.name: w for w in WORKLOADS}
