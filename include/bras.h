@@ -43,12 +43,14 @@ extern "C" {
 #define BRAS_EBREAKDOWN -5   /* PCG breakdown: p.q <= 0, r.z <= 0, NaN / Inf  */
 #define BRAS_ENOMEM     -6   /* device allocation failed                      */
 
-/* ---- element families (Section 4: Lagrange, Bernstein, N1curl, RT) ------ */
+/* ---- element families (Section 4: Lagrange, Bernstein, N1curl, N2curl, RT, BDM) */
 #define BRAS_H1    0         /* H1 Lagrange P_p, GLL-based nodes             */
 #define BRAS_HCURL 1         /* first-kind Nedelec N1curl_k, covariant Piola */
 #define BRAS_HDIV  2         /* Raviart-Thomas RT_k, contravariant Piola     */
 #define BRAS_H1_BERNSTEIN 3  /* H1 P_p in the Bernstein basis p!/alpha! lambda^alpha,
                                 local order as the Lagrange nodes (same multi-indices) */
+#define BRAS_HCURL2 4        /* second-kind Nedelec N2curl_k = [P_k]^d, covariant Piola */
+#define BRAS_HDIV2  5        /* Brezzi-Douglas-Marini BDM_k = [P_k]^d, contravariant Piola */
 
 /* ---- element-data forms accepted by bras_setup -------------------------- */
 #define BRAS_ELEM_EXPLICIT   0  /* elem_d: E x n_loc x n_loc float64 M_K, row-major */
@@ -97,7 +99,8 @@ int bras_mesh_structured(int dim, int N, double jitter, uint64_t seed,
 
 /* Element description: n_loc and the DOFs per vertex, edge, face and cell
  * (dofs_per_entity_h[4]; 2D uses entries 0..2, entry 2 = cell).
- * Supported: H1 degree 1..6 (2D/3D), HCURL and HDIV degree 1..4 (2D/3D). */
+ * Supported: H1 degree 1..6 (2D/3D), HCURL, HDIV, HCURL2 and HDIV2 degree
+ * 1..4 (2D/3D). */
 int bras_element_info(int family, int dim, int degree, int* n_loc_h, int* dofs_per_entity_h);
 
 /* Reference mass tables on conv{0, e_1, .., e_d} (eq. piola_mass_pullbacks).
@@ -108,7 +111,11 @@ int bras_element_info(int family, int dim, int degree, int* n_loc_h, int* dofs_p
  * Mhat^{ab}_ij = int phi_i^a phi_j^b, so M_K = sum_p G_p S_p.
  * Degrees of freedom: point values at recursive GLL nodes (H1); integral
  * moments against orthonormal polynomials of each sorted-vertex entity
- * (HCURL / HDIV).  Computed by quadrature in extended precision. */
+ * (HCURL / HDIV); for HCURL2 / HDIV2 the classical second-kind moments
+ * (edges / facets against P_k, N2curl faces against RT_{k-1}, interiors
+ * against RT_{k-1} (2D) / RT_{k-2} (3D) for N2curl and N1curl_{k-1} for BDM),
+ * the RT / N1curl test fields being monomial spanning fields orthonormalised
+ * in a fixed order.  Computed by quadrature in extended precision. */
 int bras_reference_mass(int family, int dim, int degree, double* ref_h);
 
 /* Canonical local-to-global map.  Edges / faces are the sorted vertex pairs /
@@ -123,8 +130,8 @@ int bras_dofmap(int family, int dim, int degree, int64_t nvert, int64_t ncell,
 
 /* Per-element pullback coefficients on the device (eq. piola_mass_pullbacks):
  * H1    elem_d[K]         = rho_K |det J_K|
- * HCURL elem_d[K][nsym]   = rho_K |det J_K| J_K^-1 J_K^-T   (symmetric pairs)
- * HDIV  elem_d[K][nsym]   = rho_K J_K^T J_K / |det J_K|
+ * HCURL, HCURL2 elem_d[K][nsym] = rho_K |det J_K| J_K^-1 J_K^-T (symmetric pairs)
+ * HDIV, HDIV2   elem_d[K][nsym] = rho_K J_K^T J_K / |det J_K|
  * J_K has columns v_i - v_0.  rho_d may be NULL (rho = 1).  Asynchronous. */
 int bras_geometry(int family, int dim, int64_t nvert, const double* coords_d,
                   int64_t ncell, const int32_t* cells_d, const double* rho_d,

@@ -26,10 +26,10 @@ def metric(kind, coords, cells, rho=None):
     r = np.ones(len(cells)) if rho is None else np.asarray(rho, dtype=float)
     if kind in ("P", "B"):          # H1 (Lagrange or Bernstein basis)
         return r * adet
-    if kind == "N1curl":
+    if kind in ("N1curl", "N2curl"):          # covariant Piola
         Jinv = np.linalg.inv(J)
         return (r * adet)[:, None, None] * (Jinv @ np.transpose(Jinv, (0, 2, 1)))
-    if kind == "RT":
+    if kind in ("RT", "BDM"):                 # contravariant Piola
         return (r / adet)[:, None, None] * (np.transpose(J, (0, 2, 1)) @ J)
     raise ValueError(kind)
 

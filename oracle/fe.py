@@ -14,6 +14,8 @@ Families (Section 3 names them after Firedrake; the readings used here):
            degree-k homogeneous fields u with x . u = 0 (3D) or (-y, x) P~_{k-1}
            (2D).  Degrees of freedom are integral moments.
 * "RT"     Raviart-Thomas RT_k = [P_{k-1}]^d + x P~_{k-1}, integral moments.
+* "N2curl" second-kind Nedelec, the full space [P_k]^d (covariant Piola).
+* "BDM"    Brezzi-Douglas-Marini, the full space [P_k]^d (contravariant Piola).
 * "B"      H1 P_p in the Bernstein basis (Section 4, Table h1_mass_solve):
            B_alpha = p!/(alpha_0! ... alpha_d!) lambda_0^alpha_0 ... lambda_d^alpha_d
            over barycentric multi-indices |alpha| = p, lambda_0 = 1 - sum x_i,
@@ -33,7 +35,21 @@ the integral-moment reading).  Entities are taken with sorted vertices
   interior      int_K u_c q, component-major,   q in P_{k-2} (RT, 2D N1curl)
                                                 or P_{k-3} (3D N1curl)
 with q running over the orthonormal polynomials of the entity in parameter
-coordinates (oracle.poly).  With these functionals a field's degrees of
+coordinates (oracle.poly).  Second-kind families (classical moments; the
+test spaces are listed in the design notes):
+  N2curl edge   int_0^1 (u . t) q ds,                       q in P_k
+  N2curl face   int_f (u . t_1) q_1 + (u . t_2) q_2,        (q_1, q_2) in RT_{k-1}
+                                                            (face parameters)
+  N2curl int.   int_K u . q,  q in RT_{k-1} (2D) or RT_{k-2} (3D)
+  BDM facet     int (u . n) q,  n as for RT,                q in P_k
+  BDM interior  int_K u . q,  q in N1curl_{k-1}
+where the RT_j / N1curl_j test fields are the monomial spanning fields
+[P_{j-1}]^m (component-major), then x q (RT), (-y, x) q (2D N1curl) or
+x cross (e_c q) (3D N1curl; q outer, c inner, each kept only if independent
+of the fields kept before it), q over the homogeneous monomials of degree
+j - 1, and then orthonormalised in that order (Gram-Schmidt under the L2
+inner product of the entity's parameter domain, i.e. f L^-T with L the
+Cholesky factor of their Gram matrix).  With these functionals a field's degrees of
 freedom are unchanged by the covariant / contravariant Piola maps, so shared
 degrees of freedom agree between neighbouring cells and P stays 0/1.
 
@@ -269,6 +285,8 @@ def _space_basis(family, d, k, mons):
     index = {a: i for i, a in enumerate(mons)}
     if family == "P":
         return [{(0, i): Fraction(1)} for i in range(len(mons))]
+    if family in ("N2curl", "BDM"):
+        return [{(c, i): Fraction(1)} for c in range(d) for i in range(len(mons))]
     vecs = []
     for c in range(d):
         for mu in poly.monomials(d, k - 1):
@@ -337,6 +355,9 @@ def _functionals(family, d, k, mons):
                     rows.append([row])
         return rows, tuple(counts), np.array([[float(c) for c in x] for x in nodes])
 
+    if family in ("N2curl", "BDM"):
+        return _second_kind_functionals(family, d, k, mons)
+
     if family == "N1curl" or (family == "RT" and d == 2):
         qs = poly.orthogonal_rational(1, k - 1)
         for verts in local_entities(d, 1):
@@ -370,6 +391,143 @@ def _functionals(family, d, k, mons):
                 rows.append(_interior_row(d, mons, c, q, n2))
         nint = d * len(qs)
     counts[d] = nint
+    return rows, tuple(counts), None
+
+
+def _is_independent(kept, v):
+    """Whether the rational vector v is independent of the rows in kept."""
+    rows = [list(r) for r in kept] + [list(v)]
+    return len(rational_null_space(list(map(list, zip(*rows))))) == 0
+
+
+def test_fields(kind, m, j):
+    """Monomial spanning fields of RT_j or N1curl_j on the m-simplex, in the
+    fixed order stated in the module docstring.  A field is a list of m
+    polynomials (dicts exponent -> Fraction)."""
+    if j < 1:
+        return []
+    out = []
+    for c in range(m):
+        for mu in poly.monomials(m, j - 1):
+            f = [{} for _ in range(m)]
+            f[c] = {mu: Fraction(1)}
+            out.append(f)
+    hom = poly.homogeneous(m, j - 1)
+    if kind == "RT":
+        for mu in hom:
+            f = []
+            for c in range(m):
+                e = list(mu)
+                e[c] += 1
+                f.append({tuple(e): Fraction(1)})
+            out.append(f)
+    elif m == 2:
+        for mu in hom:
+            e0 = list(mu); e0[1] += 1
+            e1 = list(mu); e1[0] += 1
+            out.append([{tuple(e0): Fraction(-1)}, {tuple(e1): Fraction(1)}])
+    else:
+        # x cross (e_c q): component c+1 gets x_{c+2} q, component c+2 gets -x_{c+1} q
+        homj = poly.homogeneous(3, j)
+        col = {a: i for i, a in enumerate(homj)}
+        kept = []
+        for mu in hom:
+            for c in range(3):
+                i1, i2 = (c + 1) % 3, (c + 2) % 3
+                ea = list(mu); ea[i2] += 1
+                eb = list(mu); eb[i1] += 1
+                f = [{} for _ in range(3)]
+                f[i1] = {tuple(ea): Fraction(1)}
+                f[i2] = {tuple(eb): Fraction(-1)}
+                v = [Fraction(0)] * (3 * len(homj))
+                v[i1 * len(homj) + col[tuple(ea)]] = Fraction(1)
+                v[i2 * len(homj) + col[tuple(eb)]] = Fraction(-1)
+                if _is_independent(kept, v):
+                    kept.append(v)
+                    out.append(f)
+    return out
+
+
+def _field_moment_row(d, mons, verts, dirs, field):
+    """ell[c][mu] = int_entity sum_i (e_c x^mu . dirs_i) field_i  over the
+    entity's parameter domain (dirs_i: the i-th parameter tangent, or a unit
+    direction)."""
+    v0, A = _entity_param(d, verts)
+    k = len(verts) - 1
+    ell = [[mp.mpf(0)] * len(mons) for _ in range(d)]
+    for mi, mu in enumerate(mons):
+        restricted = poly.compose_affine({mu: Fraction(1)}, v0, A)
+        for dv, q in zip(dirs, field):
+            if not q:
+                continue
+            val = poly.integrate(poly.mul(restricted, q), k)
+            for c in range(d):
+                if dv[c] != 0:
+                    ell[c][mi] += _mpf(val * dv[c])
+    return ell
+
+
+def _orthonormal_rows(raw, fields, m):
+    """Rows of the Gram-Schmidt-orthonormalised test fields: sum_j Linv[i, j] raw_j,
+    G = L L^T the Gram matrix of the fields on the m-simplex."""
+    nf = len(fields)
+    if nf == 0:
+        return []
+    G = mp.matrix(nf, nf)
+    for i in range(nf):
+        for j in range(nf):
+            tot = Fraction(0)
+            for a, b in zip(fields[i], fields[j]):
+                if a and b:
+                    tot += poly.integrate(poly.mul(a, b), m)
+            G[i, j] = _mpf(tot)
+    Linv = mp.inverse(mp.cholesky(G))
+    out = []
+    for i in range(nf):
+        row = [[mp.mpf(0)] * len(raw[0][0]) for _ in range(len(raw[0]))]
+        for j in range(i + 1):
+            for c in range(len(row)):
+                for mu in range(len(row[c])):
+                    row[c][mu] += Linv[i, j] * raw[j][c][mu]
+        out.append(row)
+    return out
+
+
+def _second_kind_functionals(family, d, k, mons):
+    rows = []
+    counts = [0] * (d + 1)
+    rv = ref_vertices(d)
+    if d == 2 or family == "N2curl":
+        qs = poly.orthogonal_rational(1, k)
+        for verts in local_entities(d, 1):
+            t = tuple(rv[verts[1]][i] - rv[verts[0]][i] for i in range(d))
+            direction = t if family == "N2curl" else (t[1], -t[0])
+            for q, n2 in qs:
+                rows.append(_moment_row(d, mons, verts, direction, q, n2))
+        counts[1] = len(qs)
+    if d == 3:
+        for verts in local_entities(3, 2):
+            t1 = tuple(rv[verts[1]][i] - rv[verts[0]][i] for i in range(3))
+            t2 = tuple(rv[verts[2]][i] - rv[verts[0]][i] for i in range(3))
+            if family == "BDM":
+                qs = poly.orthogonal_rational(2, k)
+                nrm = _cross(t1, t2)
+                for q, n2 in qs:
+                    rows.append(_moment_row(3, mons, verts, nrm, q, n2))
+                counts[2] = len(qs)
+            else:
+                fs = test_fields("RT", 2, k - 1)
+                raw = [_field_moment_row(3, mons, verts, (t1, t2), f) for f in fs]
+                rows.extend(_orthonormal_rows(raw, fs, 2))
+                counts[2] = len(fs)
+    if family == "BDM":
+        fs = test_fields("N1curl", d, k - 1)
+    else:
+        fs = test_fields("RT", d, k - 1 if d == 2 else k - 2)
+    unit = [tuple(1 if i == c else 0 for i in range(d)) for c in range(d)]
+    raw = [_field_moment_row(d, mons, tuple(range(d + 1)), unit, f) for f in fs]
+    rows.extend(_orthonormal_rows(raw, fs, d))
+    counts[d] = len(fs)
     return rows, tuple(counts), None
 
 
@@ -424,7 +582,7 @@ def _bernstein_element(dim, degree):
 @lru_cache(maxsize=None)
 def reference_element(family, dim, degree):
     """Construct the reference element (basis coefficients and mass tables)."""
-    if family not in ("P", "N1curl", "RT", "B"):
+    if family not in ("P", "N1curl", "RT", "B", "N2curl", "BDM"):
         raise ValueError(family)
     if dim not in (2, 3) or degree < 1:
         raise ValueError("unsupported element")
@@ -485,4 +643,6 @@ def element_dim(family, d, k):
         return d * math.comb(k - 1 + d, d) + math.comb(k - 1 + d - 1, d - 1)
     if family == "N1curl":
         return k * (k + 2) * (k + 3) // 2 if d == 3 else k * (k + 2)
+    if family in ("N2curl", "BDM"):
+        return d * math.comb(k + d, d)
     raise ValueError(family)

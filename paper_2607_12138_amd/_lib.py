@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libbras.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "bras.h")
 
 BRAS_OK, BRAS_EINVAL, BRAS_ENOTSPD, BRAS_EHIP, BRAS_ENOCONV, BRAS_EBREAKDOWN, BRAS_ENOMEM = 0, -1, -2, -3, -4, -5, -6
-H1, HCURL, HDIV, H1_BERNSTEIN = 0, 1, 2, 3
+H1, HCURL, HDIV, H1_BERNSTEIN, HCURL2, HDIV2 = 0, 1, 2, 3, 4, 5
 ELEM_EXPLICIT, ELEM_SCALED_REF, ELEM_METRIC_REF = 0, 1, 2
 FP64, FP32, BF16 = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_BRAS = 0, 1, 2
@@ -25,7 +25,7 @@ PC = {"none": PC_NONE, "jacobi": PC_JACOBI, "bras": PC_BRAS}
 INFO = {"n": 0, "E": 1, "nloc": 2, "nbr": 3, "prec": 4, "form": 5, "maxrhs": 6, "restarts": 7, "variant": 8}
 EXPORT_MULT, EXPORT_ROWPTR, EXPORT_SLOT, EXPORT_DIAG = 0, 1, 2, 3
 OPT_GRAPH_ITERS, OPT_MAX_RESTART, OPT_VARIANT = 0, 1, 2
-FAMILY = {"P": H1, "N1curl": HCURL, "RT": HDIV, "B": H1_BERNSTEIN}
+FAMILY = {"P": H1, "N1curl": HCURL, "RT": HDIV, "B": H1_BERNSTEIN, "N2curl": HCURL2, "BDM": HDIV2}
 
 
 def is_h1(family):

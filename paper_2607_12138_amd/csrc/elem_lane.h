@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32
   }
 }
 
-#define LANE_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(21) X(24) X(28) X(35) X(36)
+#define LANE_CASES(X) X(3) X(4) X(6) X(8) X(10) X(12) X(15) X(20) X(21) X(24) X(28) X(30) X(35) X(36)
 
 template <int NL, int FORM, int NSYM, typename T, typename ZT, int VAR>
 static int lane_launch(Ctx* c, int R, const InArgs& in, const T* ap, ZT* zb, hipStream_t s) {

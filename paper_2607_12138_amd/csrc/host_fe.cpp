@@ -21,6 +21,13 @@
 //    components (component-major), each against the orthonormal polynomials
 //    of the entity's parameter domain, Gram-Schmidt of monomials ordered by
 //    total degree and then by descending exponent tuple.
+//  N2curl_k = BDM_k = [P_k]^d with the classical second-kind moments: edge
+//    tangents (N2curl) / facet normals (BDM) against P_k as above; N2curl
+//    faces (u . t_1) q_1 + (u . t_2) q_2 for (q_1, q_2) in RT_{k-1} of the
+//    face parameters; interiors u . q for q in RT_{k-1} (2D N2curl),
+//    RT_{k-2} (3D N2curl) or N1curl_{k-1} (BDM).  Those RT / N1curl test
+//    fields are monomial spanning fields in a fixed order (see test_fields),
+//    orthonormalised in that order on the entity's parameter simplex.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -282,6 +289,11 @@ std::vector<Field> spanning_set(int family, int d, int k) {
     for (auto& a : monomials(d, k)) S.push_back(Field{{{0, a}}, {1}});
     return S;
   }
+  if (family == BRAS_HCURL2 || family == BRAS_HDIV2) {
+    for (int c = 0; c < d; ++c)
+      for (auto& a : monomials(d, k)) S.push_back(Field{{{c, a}}, {1}});
+    return S;
+  }
   for (int c = 0; c < d; ++c)
     for (auto& a : monomials(d, k - 1)) S.push_back(Field{{{c, a}}, {1}});
   auto hom = monomials(d, k - 1, true);
@@ -319,6 +331,73 @@ std::vector<Field> spanning_set(int family, int d, int k) {
         f.terms.push_back({i2, eb});
         f.coef.push_back(-1);
         S.push_back(f);
+      }
+  }
+  return S;
+}
+
+// Spanning fields of RT_j (rt) or N1curl_j on the m-simplex, the test fields
+// of the second-kind moments: [P_{j-1}]^m component-major, then x q (RT),
+// (-y q, x q) (2D N1curl) or x cross (e_c q) (3D N1curl: q outer, c inner;
+// a field in the span of those kept before it is skipped), q over the
+// homogeneous monomials of degree j - 1 in the order of monomials().
+std::vector<Field> test_fields(bool rt, int m, int j) {
+  std::vector<Field> S;
+  if (j < 1) return S;
+  for (int c = 0; c < m; ++c)
+    for (auto& a : monomials(m, j - 1)) S.push_back(Field{{{c, a}}, {1}});
+  auto hom = monomials(m, j - 1, true);
+  if (rt) {
+    for (auto& a : hom) {
+      Field f;
+      for (int c = 0; c < m; ++c) {
+        Exp e = a;
+        e[c] += 1;
+        f.terms.push_back({c, e});
+        f.coef.push_back(1);
+      }
+      S.push_back(f);
+    }
+  } else if (m == 2) {
+    for (auto& a : hom) {
+      Exp e0 = a, e1 = a;
+      e0[1] += 1;
+      e1[0] += 1;
+      S.push_back(Field{{{0, e0}, {1, e1}}, {-1, 1}});
+    }
+  } else {
+    // coefficient vectors over (component, degree-j homogeneous monomial);
+    // independence by Gram-Schmidt against the kept ones (entries 0, +-1)
+    auto homj = monomials(3, j, true);
+    const int nh = (int)homj.size();
+    auto col = [&](const Exp& e) {
+      for (int i = 0; i < nh; ++i)
+        if (homj[i] == e) return i;
+      return -1;
+    };
+    std::vector<std::vector<ld>> basis;
+    for (auto& a : hom)
+      for (int c = 0; c < 3; ++c) {
+        const int i1 = (c + 1) % 3, i2 = (c + 2) % 3;
+        Exp ea = a, eb = a;
+        ea[i2] += 1;
+        eb[i1] += 1;
+        std::vector<ld> v(3 * nh, 0);
+        v[i1 * nh + col(ea)] = 1;
+        v[i2 * nh + col(eb)] = -1;
+        std::vector<ld> w = v;
+        for (auto& b : basis) {
+          ld dot = 0;
+          for (int t = 0; t < 3 * nh; ++t) dot += b[t] * w[t];
+          for (int t = 0; t < 3 * nh; ++t) w[t] -= dot * b[t];
+        }
+        ld nn = 0;
+        for (ld x : w) nn += x * x;
+        nn = std::sqrt(nn);
+        if (nn < 1e-9L) continue;
+        for (auto& x : w) x /= nn;
+        basis.push_back(w);
+        S.push_back(Field{{{i1, ea}, {i2, eb}}, {1, -1}});
       }
   }
   return S;
@@ -379,7 +458,92 @@ int build_functionals(int family, int d, int k, std::vector<Functional>& F) {
         F.push_back(f);
       }
   };
+  // moments int_entity sum_i (u . dirs_i) f_i of test fields f given in the
+  // entity's parameter coordinates, orthonormalised in their order: with
+  // G = L L^T their Gram matrix, functional a uses sum_{b<=a} (L^-1)_ab f_b
+  auto add_field_moments = [&](const std::vector<int>& verts, const std::vector<Field>& fields,
+                               const std::vector<std::array<ld, 3>>& dirs) {
+    const int ek = (int)verts.size() - 1;
+    const int nf = (int)fields.size();
+    if (nf == 0) return;
+    std::vector<Pt> pts;
+    std::vector<ld> wts;
+    simplex_rule(ek, k + 2, pts, wts);
+    const int np = (int)pts.size();
+    std::vector<ld> fv((size_t)nf * np * ek);
+    for (int a = 0; a < nf; ++a)
+      for (int p = 0; p < np; ++p) eval_field(fields[a], pts[p].x, ek, &fv[((size_t)a * np + p) * ek], ek);
+    std::vector<ld> L((size_t)nf * nf, 0);
+    for (int a = 0; a < nf; ++a)
+      for (int b = 0; b <= a; ++b) {
+        ld g = 0;
+        for (int p = 0; p < np; ++p)
+          for (int i = 0; i < ek; ++i) g += wts[p] * fv[((size_t)a * np + p) * ek + i] * fv[((size_t)b * np + p) * ek + i];
+        L[(size_t)a * nf + b] = g;
+      }
+    for (int a = 0; a < nf; ++a) {          // Cholesky in place (lower)
+      for (int b = 0; b <= a; ++b) {
+        ld t = L[(size_t)a * nf + b];
+        for (int c = 0; c < b; ++c) t -= L[(size_t)a * nf + c] * L[(size_t)b * nf + c];
+        L[(size_t)a * nf + b] = (a == b) ? std::sqrt(t) : t / L[(size_t)b * nf + b];
+      }
+    }
+    std::vector<ld> Li((size_t)nf * nf, 0);  // L^-1 (lower), forward substitution per column
+    for (int c = 0; c < nf; ++c)
+      for (int a = c; a < nf; ++a) {
+        ld t = (a == c) ? 1 : 0;
+        for (int b = c; b < a; ++b) t -= L[(size_t)a * nf + b] * Li[(size_t)b * nf + c];
+        Li[(size_t)a * nf + c] = t / L[(size_t)a * nf + a];
+      }
+    for (int a = 0; a < nf; ++a) {
+      Functional f;
+      for (int p = 0; p < np; ++p) {
+        Pt x{{0, 0, 0}};
+        for (int i = 0; i < d; ++i) {
+          x.x[i] = rv[verts[0]][i];
+          for (int j = 0; j < ek; ++j) x.x[i] += pts[p].x[j] * (rv[verts[j + 1]][i] - rv[verts[0]][i]);
+        }
+        std::array<ld, 3> dir = {0, 0, 0};
+        for (int b = 0; b <= a; ++b) {
+          const ld cb = Li[(size_t)a * nf + b] * wts[p];
+          for (int i = 0; i < ek; ++i) {
+            const ld q = cb * fv[((size_t)b * np + p) * ek + i];
+            for (int c = 0; c < 3; ++c) dir[c] += q * dirs[i][c];
+          }
+        }
+        f.x.push_back(x);
+        f.dir.push_back(dir);
+      }
+      F.push_back(f);
+    }
+  };
   auto sub = [&](int a, int b, int i) { return rv[b][i] - rv[a][i]; };
+  if (family == BRAS_HCURL2 || family == BRAS_HDIV2) {
+    const bool curl = family == BRAS_HCURL2;
+    if (d == 2 || curl)
+      for (auto& e : combos(d + 1, 2)) {
+        std::array<ld, 3> t = {sub(e[0], e[1], 0), sub(e[0], e[1], 1), d == 3 ? sub(e[0], e[1], 2) : 0};
+        add_moments(e, k, {curl ? t : std::array<ld, 3>{t[1], -t[0], 0}});
+      }
+    if (d == 3)
+      for (auto& f : combos(4, 3)) {
+        std::array<ld, 3> t1 = {sub(f[0], f[1], 0), sub(f[0], f[1], 1), sub(f[0], f[1], 2)};
+        std::array<ld, 3> t2 = {sub(f[0], f[2], 0), sub(f[0], f[2], 1), sub(f[0], f[2], 2)};
+        if (curl) {
+          add_field_moments(f, test_fields(true, 2, k - 1), {t1, t2});
+        } else {
+          std::array<ld, 3> nrm = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2],
+                                   t1[0] * t2[1] - t1[1] * t2[0]};
+          add_moments(f, k, {nrm});
+        }
+      }
+    std::vector<int> all;
+    for (int i = 0; i <= d; ++i) all.push_back(i);
+    std::vector<std::array<ld, 3>> unit = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    unit.resize(d);
+    add_field_moments(all, curl ? test_fields(true, d, d == 2 ? k - 1 : k - 2) : test_fields(false, d, k - 1), unit);
+    return BRAS_OK;
+  }
   if (family == BRAS_HCURL || (family == BRAS_HDIV && d == 2)) {
     for (auto& e : combos(d + 1, 2)) {
       std::array<ld, 3> t = {sub(e[0], e[1], 0), sub(e[0], e[1], 1), d == 3 ? sub(e[0], e[1], 2) : 0};

@@ -69,6 +69,23 @@ int element_counts(int family, int dim, int degree, int* n_loc, int counts[4]) {
       counts[3] = 3 * (int)binom(p - 3 + 3, 3);        // [P_{k-3}]^3
       *n_loc = 6 * counts[1] + 4 * counts[2] + counts[3];
     }
+  } else if (family == BRAS_HCURL2 || family == BRAS_HDIV2) {
+    if (p < 1 || p > 4) return fail(BRAS_EINVAL, "second-kind degree must be 1..4 (got %d)", p);
+    const int rt2 = (p - 1) * (p + 1);                 // dim RT_{k-1} (2D)
+    if (dim == 2) {
+      counts[1] = p + 1;                               // tangential / normal moments against P_k
+      counts[2] = rt2;                                 // RT_{k-1} (N2curl) or N1curl_{k-1} (BDM), same dim
+      *n_loc = 3 * counts[1] + counts[2];
+    } else if (family == BRAS_HCURL2) {
+      counts[1] = p + 1;                               // tangential moments against P_k
+      counts[2] = rt2;                                 // against RT_{k-1} on the face
+      counts[3] = (p - 2) * (p - 1) * (p + 1) / 2;     // against RT_{k-2}
+      *n_loc = 6 * counts[1] + 4 * counts[2] + counts[3];
+    } else {
+      counts[2] = (p + 1) * (p + 2) / 2;               // normal moments against P_k on the face
+      counts[3] = (p - 1) * (p + 1) * (p + 2) / 2;     // against N1curl_{k-1}
+      *n_loc = 4 * counts[2] + counts[3];
+    }
   } else {
     return fail(BRAS_EINVAL, "unknown family %d", family);
   }

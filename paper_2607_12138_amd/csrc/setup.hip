@@ -46,7 +46,7 @@ __global__ void k_geometry(int family, int dim, const double* __restrict__ X, co
     return;
   }
   double G[3][3];
-  if (family == BRAS_HDIV) {
+  if (family == BRAS_HDIV || family == BRAS_HDIV2) {
     // J^T J / |det J|
     for (int a = 0; a < dim; ++a)
       for (int b = 0; b < dim; ++b) {
@@ -533,8 +533,7 @@ extern "C" int bras_geometry(int family, int dim, int64_t nvert, const double* c
                              const int32_t* cells_d, const double* rho_d, double* elem_d, void* stream) {
   clear_error();
   BRAS_CHECK(dim == 2 || dim == 3, "dim must be 2 or 3");
-  BRAS_CHECK(family == BRAS_H1 || family == BRAS_HCURL || family == BRAS_HDIV || family == BRAS_H1_BERNSTEIN,
-             "unknown family %d", family);
+  BRAS_CHECK(family >= BRAS_H1 && family <= BRAS_HDIV2, "unknown family %d", family);
   BRAS_CHECK(coords_d && cells_d && elem_d, "null pointer argument");
   BRAS_CHECK(nvert > 0 && ncell > 0, "empty mesh");
   hipStream_t s = (hipStream_t)stream;

@@ -1,5 +1,6 @@
 """The paper's mass-solve experiments (Section 4; Tables h1_mass_solve,
-hcurl_mass_solve, hdiv_mass_solve) run through libbras on one GPU.
+hcurl_mass_solve, hdiv_mass_solve; all six element families) run through
+libbras on one GPU.
 
 For each element family, dimension and degree the conforming system has
 about 1e6 DOFs on an unjittered Kuhn mesh of the unit square / cube; the
@@ -24,7 +25,7 @@ TOL = 1e-10
 MAXIT = 5000
 TARGET_DOFS = 1_000_000
 SEED = 0x260712138 + 0x7AB1E
-FAMILIES = ("P", "B", "N1curl", "RT")
+FAMILIES = ("P", "B", "N1curl", "RT", "N2curl", "BDM")
 
 
 def entity_counts(dim, N):

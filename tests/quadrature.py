@@ -60,3 +60,61 @@ def orthonormal_numeric(d, q, n=12):
         Vx = np.stack([np.prod(x ** np.array(a), axis=1) for a in exps], axis=1)
         return Vx @ Rinv
     return ev
+
+
+def _exps(d, q, homogeneous=False):
+    from itertools import product
+    out = []
+    for deg in range(q if homogeneous else 0, q + 1):
+        blk = [a for a in product(range(deg + 1), repeat=d) if sum(a) == deg]
+        blk.sort(reverse=True)
+        out.extend(blk)
+    return out
+
+
+def test_fields_numeric(kind, m, j, n=12):
+    """RT_j (kind "RT") or N1curl_j test fields on the m-simplex, in the fixed
+    spanning order of the second-kind moments ([P_{j-1}]^m component-major,
+    then x q, (-y q, x q) or x cross (e_c q) with dependent ones skipped),
+    orthonormalised in that order under this quadrature.  Returns a function
+    mapping points [npts, m] to values [npts, nfields, m]."""
+    if j < 1:
+        return None
+    mono = lambda x, a: np.prod(x ** np.array(a), axis=1)       # noqa: E731
+    fields = []                                                 # callables x -> [npts, m]
+    for c in range(m):
+        for a in _exps(m, j - 1):
+            fields.append(lambda x, c=c, a=a: np.eye(m)[c][None, :] * mono(x, a)[:, None])
+    for a in _exps(m, j - 1, homogeneous=True):
+        if kind == "RT":
+            fields.append(lambda x, a=a: x * mono(x, a)[:, None])
+        elif m == 2:
+            fields.append(lambda x, a=a: np.stack([-x[:, 1], x[:, 0]], axis=1) * mono(x, a)[:, None])
+        else:
+            for c in range(3):
+                fields.append(lambda x, a=a, c=c: np.cross(x, np.eye(3)[c][None, :]) * mono(x, a)[:, None])
+    pts, wts = simplex_rule(m, n)
+    vals = [f(pts) for f in fields]
+    # skip dependent fields (greedy, in order), then Gram-Schmidt in order
+    kept, Q, R_rows = [], [], []
+    for i, v in enumerate(vals):
+        w = v.copy()
+        coef = np.zeros(len(vals))
+        coef[i] = 1.0
+        for qv, qc in zip(Q, R_rows):
+            c = np.sum(wts[:, None] * qv * w)
+            w = w - c * qv
+            coef = coef - c * qc
+        nrm = np.sqrt(np.sum(wts[:, None] * w * w))
+        if nrm < 1e-9 * np.sqrt(np.sum(wts[:, None] * v * v)):
+            continue
+        kept.append(i)
+        Q.append(w / nrm)
+        R_rows.append(coef / nrm)
+    C = np.array(R_rows)                                        # orthonormal = C @ fields
+
+    def ev(x):
+        x = np.atleast_2d(x)
+        F = np.stack([f(x) for f in fields], axis=1)            # [npts, nall, m]
+        return np.einsum("qa,pam->pqm", C, F)
+    return ev

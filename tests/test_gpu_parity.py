@@ -26,6 +26,15 @@ CASES = [
     ("RT", 3, 4, 2, 0.2, False, "f32"),     # n_loc 70: FP32 inverses on the FP64 matrix cores
     ("B", 3, 4, 3, 0.2, False, "f64"),      # Bernstein basis (Table h1_mass_solve)
     ("B", 2, 3, 6, 0.0, True, "f64"),
+    # second-kind families: per-lane metric form (n_loc 12, 30), packed FP32 and matrix cores (60, 105)
+    ("N2curl", 2, 2, 6, 0.2, False, "f64"),
+    ("BDM", 3, 1, 5, 0.2, False, "f64"),
+    ("N2curl", 3, 2, 3, 0.2, False, "f32"),
+    ("BDM", 3, 2, 3, 0.2, False, "f64"),
+    ("N2curl", 2, 4, 5, 0.0, True, "f64"),
+    ("N2curl", 3, 3, 2, 0.2, False, "f64"),
+    ("BDM", 3, 4, 2, 0.2, False, "f64"),
+    ("BDM", 3, 4, 2, 0.2, False, "f32"),
 ]
 
 _cache = {}

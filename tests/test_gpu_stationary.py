@@ -17,6 +17,7 @@ CASES = [
     ("N1curl", 3, 2, 3, 0.2, "f64"),
     ("N1curl", 3, 2, 3, 0.2, "f32"),
     ("RT", 3, 4, 2, 0.2, "f64"),
+    ("BDM", 3, 2, 3, 0.2, "f64"),
 ]
 _cache = {}
 

@@ -5,12 +5,15 @@ import numpy as np
 import pytest
 
 from oracle import fe, mesh, dofmap, assembly
-from tests.quadrature import simplex_rule, gauss01, orthonormal_numeric
+from tests.quadrature import simplex_rule, gauss01, orthonormal_numeric, test_fields_numeric
 
 ELEMENTS = [("P", 2, 1), ("P", 2, 2), ("P", 2, 3), ("P", 2, 4), ("P", 3, 1), ("P", 3, 2),
             ("P", 3, 3), ("P", 3, 4), ("RT", 2, 1), ("RT", 2, 3), ("N1curl", 2, 2),
             ("RT", 3, 1), ("RT", 3, 2), ("RT", 3, 4), ("N1curl", 3, 1), ("N1curl", 3, 2),
-            ("N1curl", 3, 3), ("B", 2, 2), ("B", 2, 4), ("B", 3, 3), ("B", 3, 4)]
+            ("N1curl", 3, 3), ("B", 2, 2), ("B", 2, 4), ("B", 3, 3), ("B", 3, 4),
+            ("N2curl", 2, 1), ("N2curl", 2, 3), ("BDM", 2, 2), ("N2curl", 3, 1), ("N2curl", 3, 2),
+            ("N2curl", 3, 3), ("BDM", 3, 1), ("BDM", 3, 2), ("BDM", 3, 3)]
+SECOND_KIND = ("N2curl", "BDM")
 
 
 def ref_volume(d):
@@ -96,9 +99,49 @@ def test_lagrange_polynomial_exactness(d, p):
     assert abs(fv @ e.mass @ gv - exact) < 1e-13 * max(1.0, abs(exact))
 
 
+def _second_kind_functionals_numeric(family, d, k):
+    rv = np.array(fe.ref_vertices(d), dtype=float)
+    funcs = []
+    if d == 2 or family == "N2curl":
+        s, w = gauss01(k + 3)
+        q = orthonormal_numeric(1, k)(s[:, None])
+        for a, b in itertools.combinations(range(d + 1), 2):
+            t = rv[b] - rv[a]
+            dirv = t if family == "N2curl" else np.array([t[1], -t[0]])
+            x = rv[a] + s[:, None] * t
+            for m in range(q.shape[1]):
+                funcs.append(lambda u, x=x, dirv=dirv, qm=q[:, m], w=w: np.sum(w * (u(x) @ dirv) * qm))
+    if d == 3:
+        st, w = simplex_rule(2, k + 3)
+        for a, b, c in itertools.combinations(range(4), 3):
+            t1, t2 = rv[b] - rv[a], rv[c] - rv[a]
+            x = rv[a] + st[:, :1] * t1 + st[:, 1:] * t2
+            if family == "BDM":
+                q = orthonormal_numeric(2, k)(st)
+                nrm = np.cross(t1, t2)
+                for m in range(q.shape[1]):
+                    funcs.append(lambda u, x=x, nv=nrm, qm=q[:, m], w=w: np.sum(w * (u(x) @ nv) * qm))
+            elif k >= 2:
+                F = test_fields_numeric("RT", 2, k - 1)(st)              # [npts, nf, 2]
+                T = np.stack([t1, t2])                                   # [2, 3]
+                for m in range(F.shape[1]):
+                    funcs.append(lambda u, x=x, T=T, Fm=F[:, m, :], w=w:
+                                 np.sum(w * np.sum((u(x) @ T.T) * Fm, axis=1)))
+    j = k - 1 if (family == "BDM" or d == 2) else k - 2
+    ev = test_fields_numeric("RT" if family == "N2curl" else "N1curl", d, j)
+    if ev is not None:
+        pts, w = simplex_rule(d, k + 3)
+        F = ev(pts)
+        for m in range(F.shape[1]):
+            funcs.append(lambda u, pts=pts, Fm=F[:, m, :], w=w: np.sum(w * np.sum(u(pts) * Fm, axis=1)))
+    return funcs
+
+
 def _entity_functionals_numeric(family, d, k):
     """The moment functionals, evaluated by quadrature, as callables on a field
     function u(x) -> [npts, d] (independent of the oracle's exact route)."""
+    if family in SECOND_KIND:
+        return _second_kind_functionals_numeric(family, d, k)
     rv = np.array(fe.ref_vertices(d), dtype=float)
     funcs = []
     if family == "N1curl" or (family == "RT" and d == 2):
@@ -135,7 +178,7 @@ def _entity_functionals_numeric(family, d, k):
     return funcs
 
 
-@pytest.mark.parametrize("family,d,k", [el for el in ELEMENTS if el[0] != "P"])
+@pytest.mark.parametrize("family,d,k", [el for el in ELEMENTS if el[0] not in ("P", "B")])
 def test_vector_duality_numeric(family, d, k):
     e = fe.reference_element(family, d, k)
     funcs = _entity_functionals_numeric(family, d, k)
@@ -144,7 +187,7 @@ def test_vector_duality_numeric(family, d, k):
     assert np.allclose(A, np.eye(e.n_loc), atol=1e-12)
 
 
-@pytest.mark.parametrize("family,d,k", [el for el in ELEMENTS if el[0] != "P"])
+@pytest.mark.parametrize("family,d,k", [el for el in ELEMENTS if el[0] not in ("P", "B")])
 def test_vector_traces_and_field_reproduction(family, d, k):
     e = fe.reference_element(family, d, k)
     rng = np.random.default_rng(11)
@@ -153,7 +196,10 @@ def test_vector_traces_and_field_reproduction(family, d, k):
     # a constant and a linear field of the space are reproduced exactly
     v = rng.standard_normal(d)
     fields = [lambda x: np.tile(v, (len(x), 1))]
-    if family == "RT":
+    if family in SECOND_KIND:
+        A = rng.standard_normal((d, d))
+        fields.append(lambda x: x @ A.T)                        # any linear field is in [P_1]^d
+    elif family == "RT":
         fields.append(lambda x: x.copy())                       # x in RT_1
     elif d == 3:
         fields.append(lambda x: np.cross(v, x))                 # v x x in N1curl_1
@@ -165,21 +211,24 @@ def test_vector_traces_and_field_reproduction(family, d, k):
         c, *_ = np.linalg.lstsq(Phi.transpose(0, 2, 1).reshape(-1, e.n_loc), F.ravel(), rcond=None)
         assert np.allclose(np.einsum("pjc,j->pc", Phi, c), F, atol=1e-11)
         assert abs(c @ Mid @ c - np.sum(wts * np.sum(F * F, axis=1))) < 1e-12
-    # normal (RT) / tangential (N1curl) traces on an entity are in P_{k-1}
+    # normal (RT, BDM) / tangential (N1curl, N2curl) traces on an entity are in
+    # P_{k-1} (first kind) or P_k (second kind)
+    tdeg = k if family in SECOND_KIND else k - 1
+    curl = family in ("N1curl", "N2curl")
     s = np.linspace(0.05, 0.95, 3 * k + 4)
-    if family == "N1curl" or d == 2:
+    if curl or d == 2:
         t = np.zeros(d); t[0] = 1.0
         x = s[:, None] * t[None, :]
-        dirv = t if family == "N1curl" else np.array([t[1], -t[0]])
+        dirv = t if curl else np.array([t[1], -t[0]])
         tr = e.eval(x) @ dirv
-        Vd = np.vander(s, k, increasing=True)
+        Vd = np.vander(s, tdeg + 1, increasing=True)
         res = tr - Vd @ np.linalg.lstsq(Vd, tr, rcond=None)[0]
         assert np.max(np.abs(res)) < 1e-10
-    if family == "RT" and d == 3:
+    if not curl and d == 3:
         st = rng.uniform(0, 0.5, size=(40, 2))
         x = np.column_stack([st, np.zeros(40)])               # face (0,1,2)
         tr = e.eval(x)[:, :, 2]
-        ex = [a for a in itertools.product(range(k), repeat=2) if sum(a) <= k - 1]
+        ex = [a for a in itertools.product(range(tdeg + 1), repeat=2) if sum(a) <= tdeg]
         Vd = np.stack([st[:, 0] ** a * st[:, 1] ** b for a, b in ex], axis=1)
         res = tr - Vd @ np.linalg.lstsq(Vd, tr, rcond=None)[0]
         assert np.max(np.abs(res)) < 1e-9
@@ -191,14 +240,16 @@ def _pullback_dofs(family, ref, J, x0, f, d):
     funcs = _entity_functionals_numeric(family, d, ref.degree)
     det = np.linalg.det(J)
     Jinv = np.linalg.inv(J)
-    if family == "N1curl":
+    if family in ("N1curl", "N2curl"):
         fh = lambda xh: f(x0 + xh @ J.T) @ J
     else:
         fh = lambda xh: det * (f(x0 + xh @ J.T) @ Jinv.T)
     return np.array([fn(fh) for fn in funcs])
 
 
-@pytest.mark.parametrize("family,d,k", [("RT", 3, 2), ("N1curl", 3, 2), ("RT", 2, 2), ("N1curl", 2, 2), ("RT", 3, 1)])
+@pytest.mark.parametrize("family,d,k", [("RT", 3, 2), ("N1curl", 3, 2), ("RT", 2, 2), ("N1curl", 2, 2), ("RT", 3, 1),
+                                        ("BDM", 3, 1), ("BDM", 3, 2), ("N2curl", 3, 1), ("N2curl", 3, 2),
+                                        ("N2curl", 2, 1), ("BDM", 2, 2)])
 def test_global_conformity_and_l2_norm(family, d, k):
     ref = fe.reference_element(family, d, k)
     coords, cells = mesh.structured_mesh(d, 2, jitter=0.2, seed=5)
@@ -206,7 +257,7 @@ def test_global_conformity_and_l2_norm(family, d, k):
     A = np.array([[0.3, -1.1, 0.4], [0.7, 0.2, -0.5], [0.1, 0.9, 0.6]])[:d, :d]
     c = np.array([0.5, -0.25, 1.0])[:d]
     f = lambda x: x @ A.T + c                                   # linear field: in both spaces for k >= 2
-    if k == 1:
+    if k == 1 and family not in SECOND_KIND:
         if family == "RT":
             f = lambda x: 0.7 * x + c
         else:
@@ -241,7 +292,7 @@ def test_h1_global_interpolant_l2_norm():
     assert abs(u @ (pr.M @ u) - tot) < 1e-13 * tot
 
 
-@pytest.mark.parametrize("family", ["N1curl", "RT"])
+@pytest.mark.parametrize("family", ["N1curl", "RT", "N2curl", "BDM"])
 def test_piola_element_matrix_against_physical_quadrature(family):
     ref = fe.reference_element(family, 3, 2)
     coords, cells = mesh.structured_mesh(3, 2, jitter=0.2, seed=8)
@@ -252,7 +303,7 @@ def test_piola_element_matrix_against_physical_quadrature(family):
         J = Js[K]
         det = np.linalg.det(J)
         Phi = ref.eval(pts)
-        if family == "N1curl":
+        if family in ("N1curl", "N2curl"):
             phys = np.einsum("ab,pjb->pja", np.linalg.inv(J).T, Phi)
         else:
             phys = np.einsum("ab,pjb->pja", J / det, Phi)
