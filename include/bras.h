@@ -99,8 +99,8 @@ int bras_mesh_structured(int dim, int N, double jitter, uint64_t seed,
 
 /* Element description: n_loc and the DOFs per vertex, edge, face and cell
  * (dofs_per_entity_h[4]; 2D uses entries 0..2, entry 2 = cell).
- * Supported: H1 degree 1..6 (2D/3D), HCURL, HDIV, HCURL2 and HDIV2 degree
- * 1..4 (2D/3D). */
+ * Supported: H1 degree 1..6 (2D/3D), HCURL and HDIV degree 1..4 (2D/3D),
+ * HCURL2 and HDIV2 degree 1..7 (2D) and 1..4 (3D). */
 int bras_element_info(int family, int dim, int degree, int* n_loc_h, int* dofs_per_entity_h);
 
 /* Reference mass tables on conv{0, e_1, .., e_d} (eq. piola_mass_pullbacks).

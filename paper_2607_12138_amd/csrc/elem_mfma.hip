@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(kMB) k_elem_mfma(int64_t E, int R, const int32
   }
 }
 
-#define MFMA_CASES(X) X(45) X(56) X(60) X(70) X(84) X(105)
+#define MFMA_CASES(X) X(42) X(45) X(56) X(60) X(70) X(72) X(84) X(105)
 
 template <int NL, typename T, typename ZT>
 static int mfma_launch(Ctx* c, int R, const InArgs& in, const T* mat, ZT* zb, hipStream_t s) {

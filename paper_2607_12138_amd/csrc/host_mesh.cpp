@@ -70,7 +70,8 @@ int element_counts(int family, int dim, int degree, int* n_loc, int counts[4]) {
       *n_loc = 6 * counts[1] + 4 * counts[2] + counts[3];
     }
   } else if (family == BRAS_HCURL2 || family == BRAS_HDIV2) {
-    if (p < 1 || p > 4) return fail(BRAS_EINVAL, "second-kind degree must be 1..4 (got %d)", p);
+    if (p < 1 || p > (dim == 2 ? 7 : 4))
+      return fail(BRAS_EINVAL, "second-kind degree must be 1..%d in %dD (got %d)", dim == 2 ? 7 : 4, dim, p);
     const int rt2 = (p - 1) * (p + 1);                 // dim RT_{k-1} (2D)
     if (dim == 2) {
       counts[1] = p + 1;                               // tangential / normal moments against P_k

@@ -275,8 +275,8 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
                                                     double* __restrict__ mpack, int mg, T* __restrict__ out, int og,
                                                     int gram, int* __restrict__ flag) {
   extern __shared__ double lds[];
-  double* A = lds;               // nl*nl (lower triangle used)
-  double* g = A + nl * nl;       // nsym (<= 6)
+  double* A = lds;               // lower triangle, packed: entry (i, j), i >= j, at i(i+1)/2 + j
+  double* g = A + nl * (nl + 1) / 2;   // nsym (<= 6)
   double* dinv = g + 8;          // nl
   __shared__ int bad;
   const int64_t K = blockIdx.x;
@@ -287,6 +287,7 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
   for (int l = t; l < nl; l += nt) dinv[l] = invd[l2g[K * nl + l]];
   __syncthreads();
   const int nn = nl * nl;
+  auto P = [](int i, int j) { return i * (i + 1) / 2 + j; };
   for (int q = t; q < npk; q += nt) {
     int i, j;
     unpack_lower(q, i, j);
@@ -297,28 +298,28 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
     } else {
       v = Mexp[K * nn + i * nl + j];
     }
-    A[i * nl + j] = v;
+    A[P(i, j)] = v;
     if (mpack) mpack[packed_at(q, K, E, mg, npk)] = v;
     if (i == j) diagb[(int64_t)i * E + K] = v;
   }
   __syncthreads();
   // right-looking Cholesky
   for (int j = 0; j < nl; ++j) {
-    const double piv = A[j * nl + j];
+    const double piv = A[P(j, j)];
     if (!(piv > 0.0) || !isfinite(piv)) {
       if (t == 0) bad = 1;
       break;
     }
     const double ljj = sqrt(piv);
-    for (int i = j + 1 + t; i < nl; i += nt) A[i * nl + j] /= ljj;
+    for (int i = j + 1 + t; i < nl; i += nt) A[P(i, j)] /= ljj;
     __syncthreads();
-    if (t == 0) A[j * nl + j] = ljj;
+    if (t == 0) A[P(j, j)] = ljj;
     const int m = nl - j - 1;
     for (int q = t; q < m * (m + 1) / 2; q += nt) {
       int ii, kk;
       unpack_lower(q, ii, kk);
       const int i = j + 1 + ii, k = j + 1 + kk;
-      A[i * nl + k] -= A[i * nl + j] * A[k * nl + j];
+      A[P(i, k)] -= A[P(i, j)] * A[P(k, j)];
     }
     __syncthreads();
   }
@@ -329,18 +330,18 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
   }
   // X = L^-1 in place, columns from the last: X_ij = -(sum_{k=j+1..i} X_ik L_kj) / L_jj
   for (int j = nl - 1; j >= 0; --j) {
-    const double ljj = A[j * nl + j];
+    const double ljj = A[P(j, j)];
     double v[2] = {0.0, 0.0};
     int c = 0;
     for (int i = j + 1 + t; i < nl; i += nt, ++c) {
       double s = 0.0;
-      for (int k = j + 1; k <= i; ++k) s += A[i * nl + k] * A[k * nl + j];
+      for (int k = j + 1; k <= i; ++k) s += A[P(i, k)] * A[P(k, j)];
       v[c] = -s / ljj;
     }
     __syncthreads();
     c = 0;
-    for (int i = j + 1 + t; i < nl; i += nt, ++c) A[i * nl + j] = v[c];
-    if (t == 0) A[j * nl + j] = 1.0 / ljj;
+    for (int i = j + 1 + t; i < nl; i += nt, ++c) A[P(i, j)] = v[c];
+    if (t == 0) A[P(j, j)] = 1.0 / ljj;
     __syncthreads();
   }
   if (gram) {
@@ -348,7 +349,7 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
     for (int q = t; q < npk; q += nt) {
       int i, j;
       unpack_lower(q, i, j);
-      out[K * npk + q] = cast_out<T>(A[i * nl + j] * dinv[j]);
+      out[K * npk + q] = cast_out<T>(A[P(i, j)] * dinv[j]);
     }
     return;
   }
@@ -357,7 +358,7 @@ __global__ void __launch_bounds__(64) k_elem_factor(int mode, int64_t E, int nl,
     int i, j;
     unpack_lower(q, i, j);
     double s = 0.0;
-    for (int k = i; k < nl; ++k) s += A[k * nl + i] * A[k * nl + j];
+    for (int k = i; k < nl; ++k) s += A[P(k, i)] * A[P(k, j)];
     out[packed_at(q, K, E, og, npk)] = cast_out<T>(s * dinv[i] * dinv[j]);
   }
 }
@@ -482,7 +483,7 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
   double* mpack = c->mpack;   // non-null when the mass pass reads packed M_K
   double* diagb = nullptr;
   BRAS_HIP(hipMalloc((void**)&diagb, sizeof(double) * c->nbr));
-  size_t lds = sizeof(double) * (nl * nl + 8 + nl);
+  size_t lds = sizeof(double) * (npack_of(nl) + 8 + nl);
   const int gram = c->prec == BRAS_BF16 ? 1 : 0;
   if (lds > 64 * 1024) return fail(BRAS_EINVAL, "n_loc %d too large for the element factorisation", nl);
   if (c->prec == BRAS_FP64)

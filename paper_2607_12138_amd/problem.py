@@ -10,7 +10,7 @@ from . import _lib as L
 
 class MassProblem:
     def __init__(self, family, dim, degree, N, jitter=0.0, seed=0, rho=None, prec="f64", max_rhs=1,
-                 device="cuda"):
+                 device="cuda", coord_map=None):
         import torch
         self.family = L.FAMILY[family] if isinstance(family, str) else family
         self.dim, self.degree, self.N = dim, degree, N
@@ -18,6 +18,8 @@ class MassProblem:
         self.max_rhs = max_rhs
         self.device = torch.device(device)
         self.coords, self.cells = L.bras_mesh_structured(dim, N, jitter, seed)
+        if coord_map is not None:          # e.g. an affine map of the whole mesh
+            self.coords = np.ascontiguousarray(coord_map(self.coords), dtype=np.float64)
         self.n, self.l2g = L.bras_dofmap(self.family, dim, degree, len(self.coords), self.cells)
         self.n_loc, self.dofs_per_entity = L.bras_element_info(self.family, dim, degree)
         self.E = len(self.cells)

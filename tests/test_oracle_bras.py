@@ -270,3 +270,27 @@ def test_gram_factor_identity_and_bf16_emulation_error():
         assert x[:, r] @ yb[:, r] > 0
     assert reduced.round_bf16(np.array([1.0 + 2.0 ** -9]))[0] == 1.0          # tie to even
     assert reduced.round_bf16(np.array([1.0 + 3 * 2.0 ** -9]))[0] == 1.0 + 2.0 ** -7
+
+
+@pytest.mark.parametrize("deg,N", [(1, 6), (3, 3)])
+def test_rotated_stretch_bound(deg, N):
+    """Eq. rot_stretch_map on a 2D BDM mesh: the map has det 1 and singular
+    values r, 1/r, so relative to the unstretched mesh the H(div) metric has
+    contrast r^4; lambda_min(Mbras^-1 M) stays 1 and Cor.
+    bras_piola_metric_contrast bounds lambda_max by r^4 times the unstretched
+    value.  BRAS stays below the diagonal preconditioner."""
+    ref = fe.reference_element("BDM", 2, deg)
+    coords, cells = mesh.structured_mesh(2, N, jitter=0.0, seed=0)
+    base = assembly.Problem(ref, coords, cells)
+    kb1, lo1, hi1 = spectral.kappa_hat(base.M, base.B)
+    assert abs(lo1 - 1.0) < 1e-10
+    for r in (3.0, 5.0):
+        st = assembly.Problem(ref, workloads.rotated_stretch(coords, r), cells)
+        J = mesh.jacobians(st.coords, cells)
+        assert np.allclose(np.linalg.det(J), np.linalg.det(mesh.jacobians(coords, cells)), rtol=1e-12)
+        kb, lo, hi = spectral.kappa_hat(st.M, st.B)
+        kd = spectral.kappa_hat(st.M, sp.diags(1.0 / st.diag))[0]
+        assert abs(lo - 1.0) < 1e-10
+        assert hi <= r ** 4 * hi1 * (1 + 1e-12)
+        assert hi > hi1                                  # the stretch does cost something
+        assert kb < kd

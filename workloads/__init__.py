@@ -87,3 +87,15 @@ def sample(count, k, seed):
 
 def vector(n, seed, lo=-1.0, hi=1.0):
     return np.random.default_rng(seed).uniform(lo, hi, size=n)
+
+
+def rotated_stretch(coords, r):
+    """Coordinates under the affine map x -> c + R S R^T (x - c), c = (1/2, 1/2),
+    R the rotation by pi/4, S = diag(r, 1/r) (the rotated-stretch meshes of
+    eq. rot_stretch_map; 2D, det = 1)."""
+    coords = np.asarray(coords, dtype=np.float64)
+    c = np.array([0.5, 0.5])
+    q = np.sqrt(0.5)
+    R = np.array([[q, -q], [q, q]])
+    A = R @ np.diag([r, 1.0 / r]) @ R.T
+    return c + (coords - c) @ A.T
