@@ -131,6 +131,27 @@ def stationary_section(prob, b, w, steps):
     return out
 
 
+def assembled_section(prob, x, y, bras_us, reps):
+    """The assembled M_bras^-1 (CSR, float64 values, int32 columns) applied as a
+    sparse product, against the matrix-free apply on the same input: the
+    sparse form moves 12 bytes per stored entry, the element form the packed
+    inverses once per element."""
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    csr = prob.assemble(L.OP_BRAS)
+    torch.cuda.synchronize()
+    asm_s = time.perf_counter() - t0
+    nnz = int(csr[1].numel())
+    us = time_apply(lambda u, v: L.bras_csr_apply(prob.n, csr[0], csr[1], csr[2], u, v), x, y, reps)
+    nbytes = 12 * nnz + 8 * (prob.n + 1) + 16 * prob.n
+    del csr
+    torch.cuda.empty_cache()
+    return {"nnz": nnz, "assemble_s": round(asm_s, 3), "us_per_apply": round(us, 3), "bytes_per_apply": nbytes,
+            "gbs": round(nbytes / (us * 1e-6) / 1e9, 1), "time_vs_matrix_free": round(us / bras_us, 3)}
+
+
 def cpu_baseline(w, its_gpu, budget_s=20.0):
     """The oracle's BRAS-PCG on the same workload, matrix-free (its element
     route), one thread.  Setup (mesh, numbering, element matrices and
@@ -181,6 +202,7 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(workloads.BY_NAME))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-assembled", action="store_true", help="skip the assembled (CSR) BRAS comparison")
     ap.add_argument("--stationary-steps", type=int, default=2,
                     help="timed fixed-point / Chebyshev solves of each kind (0: skip)")
     ap.add_argument("--mode", choices=["full", "apply", "copy"], default="full",
@@ -244,6 +266,10 @@ def main():
     mass_us = time_apply(lambda u, v: L.mass_apply(prob.h, u, v), x, y, a.apply_reps)
     nbytes = algorithmic_bytes(w, prob.n, prob.E, prob.n_loc, w.nrhs, w.prec)
     achieved = nbytes / (bras_us * 1e-6) / 1e9
+    assembled = None
+    if w.nrhs == 1 and w.prec != "bf16" and not a.no_assembled:
+        assembled = assembled_section(prob, x, y, bras_us, a.apply_reps)
+        print("assembled done: %s" % json.dumps(assembled), file=sys.stderr, flush=True)
     traffic = stored_traffic(w.name)
     out = {
         "metric": METRIC,
@@ -259,7 +285,8 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32 apply / f64 CG", "bf16": "bf16 apply / f64 CG"}[w.prec],
         "data": "synthetic: seeded Kuhn mesh and U[-1,1] right-hand side",
         "config": {
-            "workload": w.name, "family": {"P": "H1 Lagrange", "B": "H1 Bernstein", "N1curl": "N1curl", "RT": "RT"}[w.family],
+            "workload": w.name, "family": {"P": "H1 Lagrange", "B": "H1 Bernstein", "N1curl": "N1curl", "RT": "RT",
+                                           "N2curl": "N2curl", "BDM": "BDM"}[w.family],
             "degree": w.degree, "dim": w.dim, "mesh": "%d^%d Kuhn simplices, jitter %.1fh" % (w.N, w.dim, w.jitter),
             "n": prob.n, "E": prob.E, "n_loc": prob.n_loc, "nrhs": w.nrhs, "rtol": w.tol, "apply_precision": w.prec,
         },
@@ -278,6 +305,7 @@ def main():
         "setup_s": round(setup_s, 3),
         "element_pass_variant": int(variant),
         "stationary": stat,
+        "assembled_bras": assembled,
     }
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)

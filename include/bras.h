@@ -226,6 +226,29 @@ int bras_info(bras_handle h, int what, int64_t* value_h);
 #define BRAS_EXPORT_DIAG   3
 int bras_export(bras_handle h, int what, void* dst_d, void* stream);
 
+/* ---- assembled operators (eq. mass_and_bras_element_sums: M_bras^-1 has the
+ * sparsity of M) ------------------------------------------------------------
+ * CSR on the device: rowptr int64 [n+1], col int32 [nnz] ascending within each
+ * row, val float64 [nnz].  Row i holds every DOF of every element containing
+ * DOF i; entry (i, j) sums over the copies (K, l) of i in transpose-map order
+ * (K*n_loc + l ascending) the element entries M_K[l][m] (BRAS_OP_MASS) or
+ * d_i^-1 (M_K^-1)[l][m] d_j^-1 (BRAS_OP_BRAS, from the stored FP64 / FP32
+ * inverses) with pi(K, m) = j.  Buffers are caller allocated. */
+#define BRAS_OP_MASS 0
+#define BRAS_OP_BRAS 1
+/* Row pointers and nnz of the pattern (the same for both operators).  EINVAL
+ * when a row has more than 1024 candidate columns (max d_i * n_loc) or nnz
+ * reaches 2^31.  Synchronises the stream. */
+int bras_csr_rowptr(bras_handle h, int64_t* rowptr_d, int64_t* nnz_h, void* stream);
+/* Columns and values for rowptr_d from bras_csr_rowptr.  EINVAL for a handle
+ * storing BF16 Gram factors.  Asynchronous on the stream. */
+int bras_csr_assemble(bras_handle h, int op, const int64_t* rowptr_d, int32_t* col_d, double* val_d, void* stream);
+/* y = A x for a CSR matrix on the device (one column, float64): each row's
+ * sum is taken in a fixed order (16 strided partial sums, then a butterfly).
+ * x and y must not overlap. */
+int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t* col_d, const double* val_d,
+                   const double* x_d, double* y_d, void* stream);
+
 #define BRAS_OPT_GRAPH_ITERS 0  /* CG iterations per captured graph (>= 1)     */
 #define BRAS_OPT_MAX_RESTART 1  /* refinement restarts allowed (>= 0)         */
 #define BRAS_OPT_VARIANT     2  /* force a scheduling variant (-1 = built-in)  */

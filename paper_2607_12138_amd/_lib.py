@@ -71,6 +71,9 @@ _SIGS = {
     "bras_export": [vp, i32, vp, vp],
     "bras_set_option": [vp, i32, dbl],
     "bras_autotune": [vp, i32, vp],
+    "bras_csr_rowptr": [vp, vp, P_i64, vp],
+    "bras_csr_assemble": [vp, i32, vp, vp, vp, vp],
+    "bras_csr_apply": [i64, vp, vp, vp, vp, vp, vp],
 }
 
 
@@ -268,6 +271,23 @@ def bras_info(h, what):
 
 def bras_export(h, what, dst_d, stream=None):
     check(lib().bras_export(h, what, _dev(dst_d), _stream(stream)))
+
+
+OP_MASS, OP_BRAS = 0, 1
+
+
+def bras_csr_rowptr(h, rowptr_d, stream=None):
+    nnz = C.c_int64()
+    check(lib().bras_csr_rowptr(h, _dev(rowptr_d), C.byref(nnz), _stream(stream)))
+    return nnz.value
+
+
+def bras_csr_assemble(h, op, rowptr_d, col_d, val_d, stream=None):
+    check(lib().bras_csr_assemble(h, op, _dev(rowptr_d), _dev(col_d), _dev(val_d), _stream(stream)))
+
+
+def bras_csr_apply(n, rowptr_d, col_d, val_d, x_d, y_d, stream=None):
+    check(lib().bras_csr_apply(n, _dev(rowptr_d), _dev(col_d), _dev(val_d), _dev(x_d), _dev(y_d), _stream(stream)))
 
 
 def bras_set_option(h, opt, value):

@@ -20,6 +20,7 @@ SOURCES = [
     ("capi.cpp", []),
     ("setup.hip", []),
     ("apply.hip", []),
+    ("csr.hip", []),
     ("lane_packed_f64.hip", []),
     ("lane_packed_f32.hip", []),
     ("lane_metric3.hip", []),

@@ -124,6 +124,22 @@ class MassProblem:
         L.bras_autotune(self.h, self.max_rhs if nrhs is None else nrhs)
         return L.bras_info(self.h, "variant")
 
+    def assemble(self, op):
+        """The assembled operator (L.OP_MASS or L.OP_BRAS) as CSR device tensors
+        (rowptr int64, col int32, val float64)."""
+        import torch
+        rowptr = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        nnz = L.bras_csr_rowptr(self.h, rowptr)
+        col = torch.empty(nnz, dtype=torch.int32, device=self.device)
+        val = torch.empty(nnz, dtype=torch.float64, device=self.device)
+        L.bras_csr_assemble(self.h, op, rowptr, col, val)
+        return rowptr, col, val
+
+    def csr_apply(self, csr, x, y=None):
+        y = self.vec() if y is None else y
+        L.bras_csr_apply(self.n, csr[0], csr[1], csr[2], x, y)
+        return y
+
     def export(self, what):
         import torch
         if what == L.EXPORT_MULT:
