@@ -143,7 +143,10 @@ int bras_geometry(int family, int dim, int64_t nvert, const double* coords_d,
 
 /* Build a handle for the conforming space with n DOFs, E elements of n_loc
  * local DOFs, map l2g_d [E][n_loc] (device, int32), and element data in one
- * of the BRAS_ELEM_* forms (nsym is used by METRIC_REF only).
+ * of the BRAS_ELEM_* forms (nsym is used by METRIC_REF only).  n_loc <= 120;
+ * the element passes exist for the n_loc of the supported families (3..36
+ * per lane, 42..105 per element on the matrix cores), EINVAL at the first
+ * apply otherwise.
  * Validates the map: entries in [0, n), distinct within an element, and every
  * DOF has d_i >= 1 (P has full column rank, Section 2.2) - else EINVAL.
  * Computes d, the transpose map, diag(M), and every element's exact inverse

@@ -276,22 +276,44 @@ std::vector<std::vector<int>> combos(int nv, int K) {
 struct Field {           // spanning field: ncomp components, each a single monomial times a coefficient
   std::vector<std::pair<int, Exp>> terms;   // (component, exponent)
   std::vector<ld> coef;
+  bool legendre = false;  // exponent a stands for prod_i P_{a_i}(2 x_i - 1) instead of x^a
 };
+
+// prod_i P_{a_i}(2 x_i - 1), Legendre polynomials by their three-term recurrence
+ld legendre_product(const Exp& a, const ld* x, int d) {
+  ld v = 1;
+  for (int i = 0; i < d; ++i) {
+    const ld t = 2 * x[i] - 1;
+    ld p0 = 1, p1 = t;
+    if (a[i] == 0) continue;
+    for (int n = 2; n <= a[i]; ++n) {
+      const ld p2 = ((2 * n - 1) * t * p1 - (n - 1) * p0) / n;
+      p0 = p1;
+      p1 = p2;
+    }
+    v *= p1;
+  }
+  return v;
+}
 
 void eval_field(const Field& f, const ld* x, int d, ld* out, int ncomp) {
   for (int c = 0; c < ncomp; ++c) out[c] = 0;
-  for (size_t t = 0; t < f.terms.size(); ++t) out[f.terms[t].first] += f.coef[t] * mono(f.terms[t].second, x, d);
+  for (size_t t = 0; t < f.terms.size(); ++t)
+    out[f.terms[t].first] += f.coef[t] * (f.legendre ? legendre_product(f.terms[t].second, x, d)
+                                                     : mono(f.terms[t].second, x, d));
 }
 
 std::vector<Field> spanning_set(int family, int d, int k) {
   std::vector<Field> S;
+  // full P_k spaces: products of shifted Legendre polynomials span the same
+  // space as the monomials and keep the Gram-Schmidt well conditioned
   if (family == BRAS_H1) {
-    for (auto& a : monomials(d, k)) S.push_back(Field{{{0, a}}, {1}});
+    for (auto& a : monomials(d, k)) S.push_back(Field{{{0, a}}, {1}, true});
     return S;
   }
   if (family == BRAS_HCURL2 || family == BRAS_HDIV2) {
     for (int c = 0; c < d; ++c)
-      for (auto& a : monomials(d, k)) S.push_back(Field{{{c, a}}, {1}});
+      for (auto& a : monomials(d, k)) S.push_back(Field{{{c, a}}, {1}, true});
     return S;
   }
   for (int c = 0; c < d; ++c)
@@ -344,8 +366,11 @@ std::vector<Field> spanning_set(int family, int d, int k) {
 std::vector<Field> test_fields(bool rt, int m, int j) {
   std::vector<Field> S;
   if (j < 1) return S;
+  // the [P_{j-1}]^m block as Legendre products: in degree order they span the
+  // same nested spaces as the monomials (leading coefficients positive), so the
+  // orthonormalised fields are the same, with a better conditioned Gram matrix
   for (int c = 0; c < m; ++c)
-    for (auto& a : monomials(m, j - 1)) S.push_back(Field{{{c, a}}, {1}});
+    for (auto& a : monomials(m, j - 1)) S.push_back(Field{{{c, a}}, {1}, true});
   auto hom = monomials(m, j - 1, true);
   if (rt) {
     for (auto& a : hom) {
@@ -458,9 +483,10 @@ int build_functionals(int family, int d, int k, std::vector<Functional>& F) {
         F.push_back(f);
       }
   };
-  // moments int_entity sum_i (u . dirs_i) f_i of test fields f given in the
-  // entity's parameter coordinates, orthonormalised in their order: with
-  // G = L L^T their Gram matrix, functional a uses sum_{b<=a} (L^-1)_ab f_b
+  // moments int_entity sum_i (u . dirs_i) q_i of test fields given in the
+  // entity's parameter coordinates, orthonormalised in their order on the
+  // parameter simplex (modified Gram-Schmidt, twice, on their values at the
+  // quadrature points: the moments need no other values)
   auto add_field_moments = [&](const std::vector<int>& verts, const std::vector<Field>& fields,
                                const std::vector<std::array<ld, 3>>& dirs) {
     const int ek = (int)verts.size() - 1;
@@ -470,31 +496,24 @@ int build_functionals(int family, int d, int k, std::vector<Functional>& F) {
     std::vector<ld> wts;
     simplex_rule(ek, k + 2, pts, wts);
     const int np = (int)pts.size();
-    std::vector<ld> fv((size_t)nf * np * ek);
-    for (int a = 0; a < nf; ++a)
-      for (int p = 0; p < np; ++p) eval_field(fields[a], pts[p].x, ek, &fv[((size_t)a * np + p) * ek], ek);
-    std::vector<ld> L((size_t)nf * nf, 0);
-    for (int a = 0; a < nf; ++a)
-      for (int b = 0; b <= a; ++b) {
-        ld g = 0;
-        for (int p = 0; p < np; ++p)
-          for (int i = 0; i < ek; ++i) g += wts[p] * fv[((size_t)a * np + p) * ek + i] * fv[((size_t)b * np + p) * ek + i];
-        L[(size_t)a * nf + b] = g;
-      }
-    for (int a = 0; a < nf; ++a) {          // Cholesky in place (lower)
-      for (int b = 0; b <= a; ++b) {
-        ld t = L[(size_t)a * nf + b];
-        for (int c = 0; c < b; ++c) t -= L[(size_t)a * nf + c] * L[(size_t)b * nf + c];
-        L[(size_t)a * nf + b] = (a == b) ? std::sqrt(t) : t / L[(size_t)b * nf + b];
-      }
+    const size_t len = (size_t)np * ek;
+    std::vector<std::vector<ld>> q(nf, std::vector<ld>(len));
+    auto ip = [&](const std::vector<ld>& a, const std::vector<ld>& b) {
+      ld t = 0;
+      for (int p = 0; p < np; ++p)
+        for (int i = 0; i < ek; ++i) t += wts[p] * a[(size_t)p * ek + i] * b[(size_t)p * ek + i];
+      return t;
+    };
+    for (int a = 0; a < nf; ++a) {
+      for (int p = 0; p < np; ++p) eval_field(fields[a], pts[p].x, ek, &q[a][(size_t)p * ek], ek);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int b = 0; b < a; ++b) {
+          const ld c = ip(q[b], q[a]);
+          for (size_t t = 0; t < len; ++t) q[a][t] -= c * q[b][t];
+        }
+      const ld nn = std::sqrt(ip(q[a], q[a]));
+      for (auto& x : q[a]) x /= nn;
     }
-    std::vector<ld> Li((size_t)nf * nf, 0);  // L^-1 (lower), forward substitution per column
-    for (int c = 0; c < nf; ++c)
-      for (int a = c; a < nf; ++a) {
-        ld t = (a == c) ? 1 : 0;
-        for (int b = c; b < a; ++b) t -= L[(size_t)a * nf + b] * Li[(size_t)b * nf + c];
-        Li[(size_t)a * nf + c] = t / L[(size_t)a * nf + a];
-      }
     for (int a = 0; a < nf; ++a) {
       Functional f;
       for (int p = 0; p < np; ++p) {
@@ -504,12 +523,9 @@ int build_functionals(int family, int d, int k, std::vector<Functional>& F) {
           for (int j = 0; j < ek; ++j) x.x[i] += pts[p].x[j] * (rv[verts[j + 1]][i] - rv[verts[0]][i]);
         }
         std::array<ld, 3> dir = {0, 0, 0};
-        for (int b = 0; b <= a; ++b) {
-          const ld cb = Li[(size_t)a * nf + b] * wts[p];
-          for (int i = 0; i < ek; ++i) {
-            const ld q = cb * fv[((size_t)b * np + p) * ek + i];
-            for (int c = 0; c < 3; ++c) dir[c] += q * dirs[i][c];
-          }
+        for (int i = 0; i < ek; ++i) {
+          const ld v = q[a][(size_t)p * ek + i] * wts[p];
+          for (int c = 0; c < 3; ++c) dir[c] += v * dirs[i][c];
         }
         f.x.push_back(x);
         f.dir.push_back(dir);

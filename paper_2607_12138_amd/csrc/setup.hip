@@ -552,7 +552,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
   *h = nullptr;
   BRAS_CHECK(n > 0 && E > 0 && n_loc > 0, "sizes must be positive (n=%lld E=%lld n_loc=%d)", (long long)n,
              (long long)E, n_loc);
-  BRAS_CHECK(n_loc <= 88, "n_loc %d above the supported maximum 88", n_loc);
+  BRAS_CHECK(n_loc <= 120, "n_loc %d above the supported maximum 120", n_loc);
   BRAS_CHECK(E * n_loc < (1LL << 31) && n < (1LL << 31), "problem too large for int32 maps");
   BRAS_CHECK(l2g_d && elem_d, "null map or element data");
   BRAS_CHECK(form == BRAS_ELEM_EXPLICIT || form == BRAS_ELEM_SCALED_REF || form == BRAS_ELEM_METRIC_REF,

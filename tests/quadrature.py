@@ -72,7 +72,7 @@ def _exps(d, q, homogeneous=False):
     return out
 
 
-def test_fields_numeric(kind, m, j, n=12):
+def moment_fields_numeric(kind, m, j, n=12):
     """RT_j (kind "RT") or N1curl_j test fields on the m-simplex, in the fixed
     spanning order of the second-kind moments ([P_{j-1}]^m component-major,
     then x q, (-y q, x q) or x cross (e_c q) with dependent ones skipped),

@@ -31,7 +31,7 @@ def test_mesh_bit_exact(dim, N, jit, seed):
 CASES = [("P", 2, 1), ("P", 2, 3), ("P", 3, 1), ("P", 3, 3), ("P", 3, 4), ("N1curl", 3, 1), ("N1curl", 3, 2),
          ("RT", 3, 1), ("RT", 3, 4), ("RT", 2, 2), ("N1curl", 2, 3), ("P", 2, 5), ("B", 2, 3), ("B", 3, 2),
          ("B", 3, 4), ("N2curl", 2, 2), ("N2curl", 3, 1), ("N2curl", 3, 3), ("BDM", 2, 4), ("BDM", 3, 1),
-         ("BDM", 3, 3)]
+         ("BDM", 3, 3), ("BDM", 3, 4), ("N2curl", 2, 6), ("BDM", 2, 7)]
 
 
 @pytest.mark.parametrize("family,dim,deg", CASES)

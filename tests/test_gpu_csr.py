@@ -67,9 +67,9 @@ def test_assembled_operators_match_oracle(case):
         say("csr apply op %d" % op)
         y = gpu.csr_apply((rowptr, col, val), to_t(x)).cpu().numpy()
         assert rel_inf(y, ref @ x) <= max(tol, 1e-13)
-        # the same operator applied matrix-free (the FP32 inverses enter both identically)
+        # the same operator applied matrix-free (whose FP32 form also computes in FP32)
         yf = (gpu.mass if op == L.OP_MASS else gpu.bras)(to_t(x)).cpu().numpy()
-        assert rel_inf(y, yf) <= 1e-12
+        assert rel_inf(y, yf) <= (1e-12 if tol < 1e-13 else tol)
 
 
 def test_bf16_handle_has_no_assembled_bras():

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import fe, mesh, dofmap, assembly
-from tests.quadrature import simplex_rule, gauss01, orthonormal_numeric, test_fields_numeric
+from tests.quadrature import simplex_rule, gauss01, orthonormal_numeric, moment_fields_numeric
 
 ELEMENTS = [("P", 2, 1), ("P", 2, 2), ("P", 2, 3), ("P", 2, 4), ("P", 3, 1), ("P", 3, 2),
             ("P", 3, 3), ("P", 3, 4), ("RT", 2, 1), ("RT", 2, 3), ("N1curl", 2, 2),
@@ -122,13 +122,13 @@ def _second_kind_functionals_numeric(family, d, k):
                 for m in range(q.shape[1]):
                     funcs.append(lambda u, x=x, nv=nrm, qm=q[:, m], w=w: np.sum(w * (u(x) @ nv) * qm))
             elif k >= 2:
-                F = test_fields_numeric("RT", 2, k - 1)(st)              # [npts, nf, 2]
+                F = moment_fields_numeric("RT", 2, k - 1)(st)              # [npts, nf, 2]
                 T = np.stack([t1, t2])                                   # [2, 3]
                 for m in range(F.shape[1]):
                     funcs.append(lambda u, x=x, T=T, Fm=F[:, m, :], w=w:
                                  np.sum(w * np.sum((u(x) @ T.T) * Fm, axis=1)))
     j = k - 1 if (family == "BDM" or d == 2) else k - 2
-    ev = test_fields_numeric("RT" if family == "N2curl" else "N1curl", d, j)
+    ev = moment_fields_numeric("RT" if family == "N2curl" else "N1curl", d, j)
     if ev is not None:
         pts, w = simplex_rule(d, k + 3)
         F = ev(pts)
