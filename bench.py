@@ -107,12 +107,12 @@ def stationary_section(prob, b, w, steps):
     """Section 4's other solvers on the same system: damped fixed point with
     omega_bras = 2/(1 + lambda_max) and omega_diag = 1/lambda_max, and the
     Chebyshev semi-iteration on [1, 1.02 lambda_max] with BRAS (lambda_min >= 1,
-    Cor. bras_lambda_min).  lambda_max by 50 power iterations from a seeded
+    Cor. bras_lambda_min).  lambda_max by 200 power iterations from a seeded
     vector; as in the paper, its estimation is not part of the solve time."""
     import torch
     v0 = workloads.vector(prob.n, w.seed(4))
-    lam_b = prob.lambda_max("bras", v0, 50)
-    lam_d = prob.lambda_max("jacobi", v0, 50)
+    lam_b = prob.lambda_max("bras", v0, 200)
+    lam_d = prob.lambda_max("jacobi", v0, 200)
     runs = {
         "fixed_point_bras": lambda: prob.fixed_point(b, "bras", 2.0 / (1.0 + lam_b), rtol=w.tol),
         "fixed_point_jacobi": lambda: prob.fixed_point(b, "jacobi", 1.0 / lam_d, rtol=w.tol),

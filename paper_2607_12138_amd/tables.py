@@ -24,6 +24,7 @@ from . import _lib as L
 TOL = 1e-10
 MAXIT = 5000
 TARGET_DOFS = 1_000_000
+POWER_ITERS = 200     # power-iteration steps for lambda_max (the paper does not state a count)
 SEED = 0x260712138 + 0x7AB1E
 FAMILIES = ("P", "B", "N1curl", "RT", "N2curl", "BDM")
 
@@ -85,7 +86,7 @@ def run_case(family, dim, degree, N=None, stationary=True):
     out.update(cg_its=cg_its, cg_ms=cg_ms, cg_relres=cg_rel)
     if stationary:
         v0 = workloads.vector(mp.n, seed + 1)
-        lam = [mp.lambda_max(pc, v0, 50) for pc in ("jacobi", "bras")]
+        lam = [mp.lambda_max(pc, v0, POWER_ITERS) for pc in ("jacobi", "bras")]
         om = [1.0 / lam[0], 2.0 / (1.0 + lam[1])]
         fp_its, fp_ms, fp_st = [], [], []
         for pc, w in zip(("jacobi", "bras"), om):
