@@ -51,15 +51,23 @@ def algorithmic_bytes(w, n, E, n_loc, R, prec):
     return 2 * vec + 4.0 * nbr + elem + dinv
 
 
+# sources of the operator passes and their data layout (the kernels the
+# stored counter measurements describe)
+APPLY_SOURCES = ("apply.hip", "elem_lane.h", "lane_*.hip", "elem_mfma.hip", "bf16.hip", "cg_common.h",
+                 "block_reduce.h", "internal.h", "setup.hip")
+
+
 def source_digest():
-    """sha256 over the library's kernel sources (to tell whether a stored
-    counter measurement still describes the kernels being run)."""
+    """sha256 over the sources of the operator passes (to tell whether a
+    stored counter measurement still describes the kernels being run)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2607_12138_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h", ".cpp")):
-            with open(f, "rb") as fh:
-                h.update(os.path.basename(f).encode())
-                h.update(fh.read())
+    files = set()
+    for pat in APPLY_SOURCES:
+        files.update(glob.glob(os.path.join(ROOT, "paper_2607_12138_amd", "csrc", pat)))
+    for f in sorted(files):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

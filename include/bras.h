@@ -240,7 +240,7 @@ int bras_export(bras_handle h, int what, void* dst_d, void* stream);
 #define BRAS_OP_MASS 0
 #define BRAS_OP_BRAS 1
 /* Row pointers and nnz of the pattern (the same for both operators).  EINVAL
- * when a row has more than 1024 candidate columns (max d_i * n_loc) or nnz
+ * when a row has more than 2048 candidate columns (max d_i * n_loc) or nnz
  * reaches 2^31.  Synchronises the stream. */
 int bras_csr_rowptr(bras_handle h, int64_t* rowptr_d, int64_t* nnz_h, void* stream);
 /* Columns and values for rowptr_d from bras_csr_rowptr.  EINVAL for a handle

@@ -14,7 +14,7 @@
 namespace bras {
 namespace {
 
-constexpr int kCsrCap = 1024;   // candidate columns d_i * n_loc of one row
+constexpr int kCsrCap = 2048;   // candidate columns d_i * n_loc of one row
 
 struct ElemView {
   int form, prec, nl, nsym;
