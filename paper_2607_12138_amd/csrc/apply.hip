@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
 #pragma unroll
       for (int u = 0; u < LPT; ++u) {
         const int t = tid + u * kBS;
-        sv[u] = t < cnt ? slot[p0 + t] : 0;
+        sv[u] = t < cnt ? __builtin_nontemporal_load(&slot[p0 + t]) : 0;   // streamed once per pass
       }
     }
     int32_t ra[kRowsPerThread], rb[kRowsPerThread];
@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(kBS) k_reduce_mc(int R, int nchunk, const int3
     const int cnt = rowptr[i1] - p0;
     const bool big = cnt > kChunkCap;
     if (!big)
-      for (int t = tid; t < cnt; t += kBS) sl[t] = slot[p0 + t];
+      for (int t = tid; t < cnt; t += kBS) sl[t] = __builtin_nontemporal_load(&slot[p0 + t]);
     for (int t = tid; t <= nr; t += kBS) rp[t] = rowptr[i0 + t] - p0;
     __syncthreads();
     if (act) {

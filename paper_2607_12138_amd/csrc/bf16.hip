@@ -114,7 +114,11 @@ __global__ void __launch_bounds__(kB16) k_bras_bf16(int64_t E, int R, const int3
 #pragma unroll
     for (int u = 0; u < MPT; ++u) {
       const int q = tid + u * kB16;
-      greg[u] = (ok && q < NPK) ? G[Kx * NPK + q] : zero;
+      // non-temporal: the factors are read once per apply
+      greg[u] = (ok && q < NPK)
+                    ? __builtin_bit_cast(__bf16, __builtin_nontemporal_load(
+                                                     reinterpret_cast<const unsigned short*>(G) + Kx * NPK + q))
+                    : zero;
     }
     const bool cok = ok && r0 < rc0 && act_s[r0];
 #pragma unroll

@@ -77,8 +77,11 @@ __device__ __forceinline__ void touch_all(T (&z)[N]) {
 
 // VAR selects scheduling variants: metric form bit 0 diagonal order, bit 1
 // pinning on the entry values, bits 2-3 and 6-7 the batch size; packed form
-// bits 4-5 the batch size.  The metric variants the library offers to its
-// autotuner are kMetricVar[] below.
+// bits 4-5 the batch size, bit 8 non-temporal loads of the matrix stream
+// (read once per apply, it then does not evict the vectors and the broken
+// values the next pass reads).  The metric variants the library offers to
+// its autotuner are kMetricVar[] below.  The per-element metric
+// coefficients are read non-temporally for the same reason.
 template <int NL, int FORM, int NSYM, typename T, typename ZT, int EPB, int VAR = 0>
 __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32_t* __restrict__ l2g, InArgs in,
                                                    const double* __restrict__ symtab,
@@ -116,7 +119,7 @@ __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32
   double g[NSYM > 0 ? NSYM : 1];
   if (FORM == FORM_METRIC) {
 #pragma unroll
-    for (int p = 0; p < NSYM; ++p) g[p] = p < nsym ? coefK[(int64_t)p * E + K] : 0.0;
+    for (int p = 0; p < NSYM; ++p) g[p] = p < nsym ? __builtin_nontemporal_load(&coefK[(int64_t)p * E + K]) : 0.0;
   }
   for (int col = 0; col < R; ++col) {
     if (!act_s[col]) continue;   // uniform
@@ -237,7 +240,13 @@ __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32
         const vec_t* src = sbase + boff;
 #pragma unroll
         for (int v = 0; v < CV; ++v)
-          if (b * CV + v < NQ) buf[b & 1][v] = src[(int64_t)v * E + lt];
+          if (b * CV + v < NQ) {
+            // VAR bit 8: the matrix stream is read with the non-temporal hint
+            if constexpr ((VAR & 256) != 0)
+              buf[b & 1][v] = __builtin_nontemporal_load(&src[(int64_t)v * E + lt]);
+            else
+              buf[b & 1][v] = src[(int64_t)v * E + lt];
+          }
       };
       load(std::integral_constant<int, 0>{}, pin_s((int64_t)0, wr[0]));
       static_for<NB>([&](auto bc) {

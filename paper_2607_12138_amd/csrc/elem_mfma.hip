@@ -97,7 +97,9 @@ __global__ void __launch_bounds__(kMB) k_elem_mfma(int64_t E, int R, const int32
 #pragma unroll
     for (int u = 0; u < MPT; ++u) {
       const int q = tid + u * kMB;
-      mreg[u] = (ok && q < NPK) ? mat[Kx * NPK + q] : (T)0;
+      // read once per apply: the non-temporal hint keeps the vectors and the
+      // broken values, not this stream, in the caches
+      mreg[u] = (ok && q < NPK) ? __builtin_nontemporal_load(&mat[Kx * NPK + q]) : (T)0;
     }
     const bool cok = ok && r0 < rc0 && act_s[r0];
 #pragma unroll

@@ -4,7 +4,7 @@
 namespace bras {
 
 int lane_packed_f64(Ctx* c, int R, const InArgs& in, const double* ap, double* zb, hipStream_t s) {
-  return lane_dispatch<FORM_PACKED, 0, double, double>(c, R, in, ap, zb, s);
+  return lane_dispatch<FORM_PACKED, 0, double, double, 256>(c, R, in, ap, zb, s);
 }
 
 }  // namespace bras
