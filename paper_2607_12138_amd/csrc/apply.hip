@@ -258,12 +258,14 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
         pre[k][0] = cg.z[ic];
         pre[k][1] = cg.p[ic];
       } else {
+        // q, r, x and the old z are not read again before this pass rewrites
+        // them: non-temporal, so p, z and the new r stay in the caches
         pre[k][0] = scale ? scale[ic] : 1.0;
-        pre[k][1] = cg.q[ic];
-        pre[k][2] = cg.r[ic];
-        pre[k][3] = cg.x[ic];
+        pre[k][1] = __builtin_nontemporal_load(&cg.q[ic]);
+        pre[k][2] = __builtin_nontemporal_load(&cg.r[ic]);
+        pre[k][3] = __builtin_nontemporal_load(&cg.x[ic]);
         pre[k][4] = cg.p[ic];
-        pre[k][5] = cg.flexible ? cg.z[ic] : 0.0;
+        pre[k][5] = cg.flexible ? __builtin_nontemporal_load(&cg.z[ic]) : 0.0;
       }
     }
     if (!big) {
@@ -310,7 +312,7 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
       } else {
         acc *= pre[k][0];
         const double rn = fma(-coef, pre[k][1], pre[k][2]);
-        cg.x[i] = fma(coef, pre[k][4], pre[k][3]);
+        __builtin_nontemporal_store(fma(coef, pre[k][4], pre[k][3]), &cg.x[i]);
         d2 = fma(rn, pre[k][5], d2);
         cg.z[i] = acc;
         cg.r[i] = rn;
