@@ -213,8 +213,8 @@ def main():
     ap.add_argument("--no-assembled", action="store_true", help="skip the assembled (CSR) BRAS comparison")
     ap.add_argument("--stationary-steps", type=int, default=2,
                     help="timed fixed-point / Chebyshev solves of each kind (0: skip)")
-    ap.add_argument("--mode", choices=["full", "apply", "copy"], default="full",
-                    help="apply: only back-to-back BRAS applies (for counter runs); "
+    ap.add_argument("--mode", choices=["full", "apply", "mass", "copy"], default="full",
+                    help="apply / mass: only back-to-back BRAS / mass applies (for counter runs); "
                          "copy: a device copy of known size (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -247,6 +247,13 @@ def main():
           flush=True)
     b_host = workloads.rhs(prob.n, w.nrhs, w.seed(1))
     b = torch.from_numpy(b_host).cuda()
+    if a.mode == "mass":
+        y = prob.vec(w.nrhs)
+        us = time_apply(lambda u, v: L.mass_apply(prob.h, u, v), b, y, a.apply_reps)
+        prob.close()
+        print(json.dumps({"mode": "mass", "workload": w.name, "reps": a.apply_reps, "us_per_apply": round(us, 3),
+                          "source_digest": source_digest()}), flush=True)
+        return
     if a.mode == "apply":
         y = prob.vec(w.nrhs)
         us = time_apply(lambda u, v: L.bras_apply(prob.h, u, v), b, y, a.apply_reps)
