@@ -242,6 +242,7 @@ extern "C" int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t*
   BRAS_CHECK(n >= 0, "negative size");
   if (n == 0) return BRAS_OK;
   BRAS_CHECK(rowptr_d && col_d && val_d && x_d && y_d, "null argument");
+  BRAS_CHECK(x_d != y_d, "x and y must not overlap");
   int dev = 0, ncu = 1;
   BRAS_HIP(hipGetDevice(&dev));
   BRAS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));

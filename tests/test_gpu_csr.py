@@ -77,6 +77,22 @@ def test_assembled_operators_match_oracle(case):
         assert rel_inf(y, yf) <= (1e-12 if tol < 1e-13 else tol)
 
 
+def test_csr_error_paths():
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    from paper_2607_12138_amd.problem import MassProblem
+    gpu = MassProblem("P", 2, 2, 3)
+    rowptr, col, val = gpu.assemble(L.OP_MASS)
+    with pytest.raises(L.BrasError) as e:
+        L.bras_csr_assemble(gpu.h, 7, rowptr, col, val)              # unknown operator
+    assert e.value.code == L.BRAS_EINVAL
+    x = to_t(workloads.vector(gpu.n, 1))
+    with pytest.raises(L.BrasError):
+        L.bras_csr_apply(gpu.n, rowptr, col, val, x, x)             # aliasing rejected
+    L.bras_csr_apply(0, rowptr, col, val, x, gpu.vec())              # empty: nothing to do
+    torch.cuda.synchronize()
+
+
 def test_bf16_handle_has_no_assembled_bras():
     from paper_2607_12138_amd import _lib as L
     from paper_2607_12138_amd.problem import MassProblem
