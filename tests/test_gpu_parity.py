@@ -160,6 +160,24 @@ def test_many_columns(case, R):
         assert np.linalg.norm(X[:, r] - orc.M @ X2[:, r]) <= 1.5e-8 * np.linalg.norm(X[:, r])
 
 
+@pytest.mark.parametrize("case", [("P", 2, 1, 5, 0.2, False, "f64"), ("N1curl", 3, 1, 2, 0.2, False, "f64")], ids=ids)
+def test_max_columns(case):
+    """max_rhs = 256, the largest the library accepts: every column of the
+    operators and of the independent per-column CG against the oracle."""
+    R = 256
+    orc, gpu = build(case, max_rhs=R)
+    X = workloads.rhs(orc.n, R, 79)
+    say("max columns R=%d %s" % (R, case))
+    Yb = gpu.bras(to_t(X)).cpu().numpy()
+    Ym = gpu.mass(to_t(X)).cpu().numpy()
+    assert np.max(np.abs(Yb - orc.B @ X)) <= 1e-13 * np.max(np.abs(orc.B @ X))
+    assert np.max(np.abs(Ym - orc.M @ X)) <= 1e-13 * np.max(np.abs(orc.M @ X))
+    X2, st, its, rel = gpu.solve(to_t(X), "bras", rtol=1e-10)
+    X2 = X2.cpu().numpy()
+    res = np.linalg.norm(X - orc.M @ X2, axis=0) / np.linalg.norm(X, axis=0)
+    assert np.max(res) <= 1.5e-10 and len(its) == R
+
+
 @pytest.mark.parametrize("case", [CASES[2], CASES[6]], ids=ids)
 def test_deterministic(case):
     orc, gpu = build(case)
