@@ -191,7 +191,15 @@ int jacobi_apply(bras_handle h, const double* x_d, double* y_d, int nrhs, void* 
  * iters_h[nrhs]: products M p per column; relres_h[nrhs]: final true
  * ||b - M x|| / ||r_0|| (host, may be NULL).  Blocking.  Returns ENOCONV if a
  * column did not converge and EBREAKDOWN on breakdown; x_d, iters_h and
- * relres_h are written in every case. */
+ * relres_h are written in every case.
+ * Small problems (SCALED_REF form with n_loc of degree 1-4 H1 elements,
+ * FP64, nrhs = 1, n <= 2048, 16 n + 10 n_br <= 160000, at most 1024 times
+ * 2 elements (3 for n_loc 4, 1 for n_loc 20 and 35), maxit <= 100000) run
+ * the whole iteration in one work-group kernel with its vectors in LDS and
+ * registers, unless BRAS_OPT_SMALL_CG is 0; the operators, iteration,
+ * stopping test and outputs are the same, dot products are summed in
+ * another fixed order.  BRAS_INFO_SOLVE_PATH reports which path the last
+ * call took. */
 int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, int nrhs,
               double rtol, int maxit, int* iters_h, double* relres_h, void* stream);
 
@@ -216,6 +224,7 @@ int bras_rho_grad(bras_handle h, const double* x_d, const double* lam_d,
 #define BRAS_INFO_MAXRHS   6
 #define BRAS_INFO_RESTARTS 7   /* refinement restarts in the last pcg_solve     */
 #define BRAS_INFO_VARIANT  8   /* element-pass scheduling variant (-1: built-in) */
+#define BRAS_INFO_SOLVE_PATH 9 /* last pcg_solve: 0 multi-pass, 1 one work-group */
 int bras_info(bras_handle h, int what, int64_t* value_h);
 
 /* Copy derived setup data to device buffers for inspection:
@@ -255,6 +264,8 @@ int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t* col_d, con
 #define BRAS_OPT_GRAPH_ITERS 0  /* CG iterations per captured graph (>= 1)     */
 #define BRAS_OPT_MAX_RESTART 1  /* refinement restarts allowed (>= 0)         */
 #define BRAS_OPT_VARIANT     2  /* force a scheduling variant (-1 = built-in)  */
+#define BRAS_OPT_SMALL_CG    3  /* 1 (default): single work-group pcg_solve for
+                                   small problems; 0: always multi-pass      */
 int bras_set_option(bras_handle h, int opt, double value);
 
 /* ======================================================================== *

@@ -22,9 +22,10 @@ ELEM_EXPLICIT, ELEM_SCALED_REF, ELEM_METRIC_REF = 0, 1, 2
 FP64, FP32, BF16 = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_BRAS = 0, 1, 2
 PC = {"none": PC_NONE, "jacobi": PC_JACOBI, "bras": PC_BRAS}
-INFO = {"n": 0, "E": 1, "nloc": 2, "nbr": 3, "prec": 4, "form": 5, "maxrhs": 6, "restarts": 7, "variant": 8}
+INFO = {"n": 0, "E": 1, "nloc": 2, "nbr": 3, "prec": 4, "form": 5, "maxrhs": 6, "restarts": 7, "variant": 8,
+        "solve_path": 9}
 EXPORT_MULT, EXPORT_ROWPTR, EXPORT_SLOT, EXPORT_DIAG = 0, 1, 2, 3
-OPT_GRAPH_ITERS, OPT_MAX_RESTART, OPT_VARIANT = 0, 1, 2
+OPT_GRAPH_ITERS, OPT_MAX_RESTART, OPT_VARIANT, OPT_SMALL_CG = 0, 1, 2, 3
 FAMILY = {"P": H1, "N1curl": HCURL, "RT": HDIV, "B": H1_BERNSTEIN, "N2curl": HCURL2, "BDM": HDIV2}
 
 

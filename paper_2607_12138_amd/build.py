@@ -29,6 +29,7 @@ SOURCES = [
     ("lane_metric6_v2.hip", []),
     ("elem_mfma.hip", []),
     ("pcg.hip", []),
+    ("pcg_small.hip", []),
     ("bf16.hip", []),
 ]
 

@@ -40,6 +40,7 @@ extern "C" int bras_info(bras_handle h, int what, int64_t* value_h) {
     case BRAS_INFO_MAXRHS: *value_h = c->max_rhs; break;
     case BRAS_INFO_RESTARTS: *value_h = c->last_restarts; break;
     case BRAS_INFO_VARIANT: *value_h = c->variant; break;
+    case BRAS_INFO_SOLVE_PATH: *value_h = c->last_path; break;
     default: return fail(BRAS_EINVAL, "unknown info key %d", what);
   }
   return BRAS_OK;
@@ -62,6 +63,10 @@ extern "C" int bras_set_option(bras_handle h, int opt, double value) {
       BRAS_CHECK(value >= -1 && value < variant_count(c), "variant must be -1 or in 0..%d", variant_count(c) - 1);
       c->variant = (int)value;
       cg_free(c);   // captured CG graphs hold the previous kernels
+      break;
+    case BRAS_OPT_SMALL_CG:
+      BRAS_CHECK(value == 0 || value == 1, "small-problem solver switch must be 0 or 1");
+      c->small_cg = (int)value;
       break;
     default: return fail(BRAS_EINVAL, "unknown option %d", opt);
   }

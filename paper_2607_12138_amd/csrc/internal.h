@@ -48,6 +48,8 @@ struct Ctx {
   int variant = -1;          // element-pass scheduling variant (-1: built-in choice)
   int graph_iters = 8;
   int max_restart = 8;
+  int small_cg = 1;          // solve eligible small problems in one work-group (pcg_small.hip)
+  int last_path = 0;         // path of the last pcg_solve: 0 multi-pass, 1 one work-group
   int64_t last_restarts = 0;
 
   // maps
@@ -137,6 +139,16 @@ int variant_count(const Ctx* c);    // scheduling variants of this handle's elem
 int reduce_float_plain(Ctx* c, const float* zb, double* y, int nrhs, hipStream_t s, const double* dotv,
                        double* dotpart);
 int reduce_float_cg(Ctx* c, const float* zb, int nrhs, hipStream_t s, const CgArgs& cg);
+
+// Single work-group PCG (pcg_small.hip): scaled H1 form, float64, one
+// column, n <= kSmallMaxN, 16 n + 10 n_br <= kSmallLdsBytes (its LDS: two
+// vectors, the broken vector, 16-bit transpose map), maxit <= kSmallMaxIt.
+constexpr int kSmallMaxN = 2048;
+constexpr int kSmallLdsBytes = 160000;
+constexpr int kSmallMaxIt = 100000;
+bool small_cg_eligible(const Ctx* c, int nrhs, int maxit);
+int launch_small_cg(Ctx* c, int pc, const double* b, double* x, double rtol, int maxit, double* sc, int* ic,
+                    hipStream_t s);
 
 // setup internals (setup.hip)
 int element_setup(Ctx* c, const double* elem_d, hipStream_t s);

@@ -25,7 +25,9 @@
 // inverses are FP32/BF16 the flexible beta = r_new.(z_new - z_old)/rho_old
 // is used and, at exit, CG restarts from x while the true residual is above
 // the tolerance.  The fixed-point and Chebyshev iterations at the end of this
-// file share the passes and the graph machinery.
+// file share the passes and the graph machinery.  Small single-column
+// problems of the scaled H1 form run the same iteration in one work-group
+// instead (pcg_small.hip).
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -44,11 +46,11 @@ constexpr int kNumGraphs = 6;   // 1, 2, 4, 8, 16, 32 iterations
 struct CgState {
   int R = 0;
   double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-  double* sc = nullptr;      // [S_NSC][R]
+  double* sc = nullptr;      // [S_NSC][R], followed in the same allocation by
   int* ic = nullptr;         // [I_NIC][R]
   double* part[4] = {nullptr, nullptr, nullptr, nullptr};   // partials [blocks][R]: r.r, r.z, r.z_old, p.q
-  int* ic_host = nullptr;    // pinned copy of ic
-  double* sc_host = nullptr;
+  double* sc_host = nullptr; // pinned copy of sc and ic (same layout)
+  int* ic_host = nullptr;
   double* stcoef = nullptr;  // stationary iterations: a_k [cap], then c_k [cap]
   int stcoef_cap = 0;
   struct Key {
@@ -191,12 +193,12 @@ void cg_free(Ctx* c) {
                     g->stcoef};
   for (double* p : bufs)
     if (p) (void)hipFree(p);
-  if (g->ic) (void)hipFree(g->ic);
-  if (g->ic_host) (void)hipHostFree(g->ic_host);
-  if (g->sc_host) (void)hipHostFree(g->sc_host);
+  if (g->sc_host) (void)hipHostFree(g->sc_host);   // ic and ic_host live in the sc blocks
   delete g;
   c->cg = nullptr;
 }
+
+static size_t state_bytes(int R) { return sizeof(double) * S_NSC * R + sizeof(int) * I_NIC * R; }
 
 static int cg_alloc(Ctx* c, int R) {
   if (c->cg && c->cg->R == R) return BRAS_OK;
@@ -208,17 +210,17 @@ static int cg_alloc(Ctx* c, int R) {
   double** vs[] = {&g->b, &g->x, &g->r, &g->z, &g->p, &g->q};
   for (double** v : vs)
     if (hipMalloc((void**)v, vec) != hipSuccess) return fail(BRAS_ENOMEM, "CG workspace allocation failed");
-  if (hipMalloc((void**)&g->sc, sizeof(double) * S_NSC * R) != hipSuccess ||
-      hipMalloc((void**)&g->ic, sizeof(int) * I_NIC * R) != hipSuccess)
-    return fail(BRAS_ENOMEM, "CG scalar allocation failed");
+  // scalars and flags in one block (one copy reads both back)
+  if (hipMalloc((void**)&g->sc, state_bytes(R)) != hipSuccess) return fail(BRAS_ENOMEM, "CG scalar allocation failed");
+  g->ic = (int*)(g->sc + S_NSC * R);
   const int nb_r = reduce_blocks(c, R), nb_v = vector_blocks(c, R);
   const int nb = nb_r > nb_v ? nb_r : nb_v;
   for (int k = 0; k < 4; ++k)
     if (hipMalloc((void**)&g->part[k], sizeof(double) * (size_t)nb * R) != hipSuccess)
       return fail(BRAS_ENOMEM, "CG partial allocation failed");
-  if (hipHostMalloc((void**)&g->ic_host, sizeof(int) * I_NIC * R, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&g->sc_host, sizeof(double) * S_NSC * R, hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void**)&g->sc_host, state_bytes(R), hipHostMallocDefault) != hipSuccess)
     return fail(BRAS_ENOMEM, "pinned host allocation failed");
+  g->ic_host = (int*)(g->sc_host + S_NSC * R);
   return BRAS_OK;
 }
 
@@ -313,8 +315,7 @@ static int start(Ctx* c, int pc, double rtol, int restart, hipStream_t s) {
 
 static int read_state(Ctx* c, hipStream_t s) {
   CgState* g = c->cg;
-  BRAS_HIP(hipMemcpyAsync(g->ic_host, g->ic, sizeof(int) * I_NIC * g->R, hipMemcpyDeviceToHost, s));
-  BRAS_HIP(hipMemcpyAsync(g->sc_host, g->sc, sizeof(double) * S_NSC * g->R, hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipMemcpyAsync(g->sc_host, g->sc, state_bytes(g->R), hipMemcpyDeviceToHost, s));
   BRAS_HIP(hipStreamSynchronize(s));
   return BRAS_OK;
 }
@@ -398,6 +399,8 @@ static int predict_chunk(CgState* g, int R, int maxit) {
 
 using namespace bras;
 
+static int report(Ctx* c, int R, double rtol, int maxit, int* iters_h, double* relres_h);
+
 extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, int nrhs, double rtol, int maxit,
                          int* iters_h, double* relres_h, void* stream) {
   clear_error();
@@ -414,6 +417,16 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   const size_t vec = sizeof(double) * (size_t)c->n * nrhs;
   // graphs are captured on the idle internal stream before any work is queued
   const int flexible = (pc == BRAS_PC_BRAS && c->prec != BRAS_FP64) ? 1 : 0;
+  // small single-column problems: the whole solve in one work-group, on the
+  // caller's stream (no graphs, so no internal stream)
+  if (small_cg_eligible(c, nrhs, maxit)) {
+    c->last_path = 1;
+    c->last_restarts = 0;
+    if ((st = launch_small_cg(c, pc, b_d, x_d, rtol, maxit, g->sc, g->ic, us))) return st;
+    if ((st = read_state(c, us))) return st;
+    return report(c, nrhs, rtol, maxit, iters_h, relres_h);
+  }
+  c->last_path = 0;
   std::vector<hipGraphExec_t>* graphs = nullptr;
   if ((st = get_graphs(c, pc, flexible, maxit, &graphs))) return st;
   // order the internal stream after the caller's prior work
@@ -462,6 +475,13 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   }
   (void)hipEventDestroy(ev);
   if (st) return st;
+  return report(c, R, rtol, maxit, iters_h, relres_h);
+}
+
+// Per-column results of the last solve (host copies of the state): iteration
+// counts, true relative residuals, and the status code of the call.
+static int report(Ctx* c, int R, double rtol, int maxit, int* iters_h, double* relres_h) {
+  CgState* g = c->cg;
   int result = BRAS_OK;
   for (int col = 0; col < R; ++col) {
     if (iters_h) iters_h[col] = g->ic_host[I_ITERS * R + col];

@@ -79,3 +79,24 @@ def test_host_errors_are_reported():
     assert "ascending" in str(e.value)
     nv = ctypes.c_int64()
     assert L.lib().bras_mesh_size(3, 2, None, ctypes.byref(nv)) == L.BRAS_EINVAL
+
+
+def test_binding_constants_match_header():
+    """Every numeric #define of the header has the same value in the binding."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "bras.h")
+    defs = dict((m.group(1), int(m.group(2)))
+                for m in re.finditer(r"^#define (BRAS_\w+)\s+(-?\d+)", open(path).read(), re.M))
+    py = {"BRAS_" + k: getattr(L, k) for k in ("H1", "HCURL", "HDIV", "H1_BERNSTEIN", "HCURL2", "HDIV2",
+                                               "ELEM_EXPLICIT", "ELEM_SCALED_REF", "ELEM_METRIC_REF",
+                                               "FP64", "FP32", "BF16", "PC_NONE", "PC_JACOBI", "PC_BRAS",
+                                               "EXPORT_MULT", "EXPORT_ROWPTR", "EXPORT_SLOT", "EXPORT_DIAG",
+                                               "OP_MASS", "OP_BRAS", "OPT_GRAPH_ITERS", "OPT_MAX_RESTART",
+                                               "OPT_VARIANT", "OPT_SMALL_CG")}
+    py.update({k: getattr(L, k) for k in ("BRAS_OK", "BRAS_EINVAL", "BRAS_ENOTSPD", "BRAS_EHIP", "BRAS_ENOCONV",
+                                          "BRAS_EBREAKDOWN", "BRAS_ENOMEM")})
+    py.update({"BRAS_INFO_" + k.upper(): v for k, v in L.INFO.items()})
+    assert set(py) == set(defs), set(py) ^ set(defs)
+    for k, v in defs.items():
+        assert py[k] == v, k
