@@ -224,7 +224,8 @@ int bras_rho_grad(bras_handle h, const double* x_d, const double* lam_d,
 #define BRAS_INFO_MAXRHS   6
 #define BRAS_INFO_RESTARTS 7   /* refinement restarts in the last pcg_solve     */
 #define BRAS_INFO_VARIANT  8   /* element-pass scheduling variant (-1: built-in) */
-#define BRAS_INFO_SOLVE_PATH 9 /* last pcg_solve: 0 multi-pass, 1 one work-group */
+#define BRAS_INFO_SOLVE_PATH 9 /* last pcg_solve / fixed_point_solve /
+                                  chebyshev_solve: 0 multi-pass, 1 one work-group */
 int bras_info(bras_handle h, int what, int64_t* value_h);
 
 /* Copy derived setup data to device buffers for inspection:
@@ -264,7 +265,8 @@ int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t* col_d, con
 #define BRAS_OPT_GRAPH_ITERS 0  /* CG iterations per captured graph (>= 1)     */
 #define BRAS_OPT_MAX_RESTART 1  /* refinement restarts allowed (>= 0)         */
 #define BRAS_OPT_VARIANT     2  /* force a scheduling variant (-1 = built-in)  */
-#define BRAS_OPT_SMALL_CG    3  /* 1 (default): single work-group pcg_solve for
+#define BRAS_OPT_SMALL_CG    3  /* 1 (default): single work-group pcg_solve,
+                                   fixed_point_solve and chebyshev_solve for
                                    small problems; 0: always multi-pass      */
 int bras_set_option(bras_handle h, int opt, double value);
 
@@ -286,7 +288,8 @@ int bras_lambda_max(bras_handle h, int pc, const double* v0_d, int iters, double
  * (Section 4) from u_0 = x_d, for every column independently; stops when
  * ||f - M u_k||_2 <= rtol ||f - M u_0||_2 (iters_h = k, the number of
  * updates) or after maxit updates (ENOCONV).  pc: BRAS_PC_JACOBI or
- * BRAS_PC_BRAS.  Arguments and results as pcg_solve.  Synchronous. */
+ * BRAS_PC_BRAS.  Arguments and results as pcg_solve, including the single
+ * work-group path for small problems.  Synchronous. */
 int fixed_point_solve(bras_handle h, int pc, double omega, const double* b_d, double* x_d, int nrhs,
                       double rtol, int maxit, int* iters_h, double* relres_h, void* stream);
 

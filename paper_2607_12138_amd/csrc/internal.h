@@ -149,6 +149,9 @@ constexpr int kSmallMaxIt = 100000;
 bool small_cg_eligible(const Ctx* c, int nrhs, int maxit);
 int launch_small_cg(Ctx* c, int pc, const double* b, double* x, double rtol, int maxit, double* sc, int* ic,
                     hipStream_t s);
+// damped fixed point / Chebyshev with the coefficient table coef [2][cap]
+int launch_small_stationary(Ctx* c, int pc, const double* b, double* x, double rtol, int maxit, const double* coef,
+                            int cap, double* sc, int* ic, hipStream_t s);
 
 // setup internals (setup.hip)
 int element_setup(Ctx* c, const double* elem_d, hipStream_t s);

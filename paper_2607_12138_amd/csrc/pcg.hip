@@ -399,7 +399,7 @@ static int predict_chunk(CgState* g, int R, int maxit) {
 
 using namespace bras;
 
-static int report(Ctx* c, int R, double rtol, int maxit, int* iters_h, double* relres_h);
+static int report(Ctx* c, int R, double rtol, int maxit, int* iters_h, double* relres_h, bool cg = true);
 
 extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, int nrhs, double rtol, int maxit,
                          int* iters_h, double* relres_h, void* stream) {
@@ -480,7 +480,7 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
 
 // Per-column results of the last solve (host copies of the state): iteration
 // counts, true relative residuals, and the status code of the call.
-static int report(Ctx* c, int R, double rtol, int maxit, int* iters_h, double* relres_h) {
+static int report(Ctx* c, int R, double rtol, int maxit, int* iters_h, double* relres_h, bool cg) {
   CgState* g = c->cg;
   int result = BRAS_OK;
   for (int col = 0; col < R; ++col) {
@@ -490,8 +490,10 @@ static int report(Ctx* c, int R, double rtol, int maxit, int* iters_h, double* r
     if (cs == ST_BREAK) result = BRAS_EBREAKDOWN;
     else if (cs == ST_NOCONV && result == BRAS_OK) result = BRAS_ENOCONV;
   }
-  if (result == BRAS_EBREAKDOWN) return fail(result, "PCG breakdown (p.q <= 0, r.z <= 0 or non-finite values)");
-  if (result == BRAS_ENOCONV) return fail(result, "PCG did not reach rtol=%g within maxit=%d", rtol, maxit);
+  if (result == BRAS_EBREAKDOWN)
+    return fail(result, cg ? "PCG breakdown (p.q <= 0, r.z <= 0 or non-finite values)" : "non-finite residual");
+  if (result == BRAS_ENOCONV)
+    return fail(result, "%sdid not reach rtol=%g within maxit=%d", cg ? "PCG " : "", rtol, maxit);
   return BRAS_OK;
 }
 
@@ -620,6 +622,17 @@ static int stationary(Ctx* c, int pc, const std::vector<double>& ca, const std::
     tab[k] = ca[k];
     tab[g->stcoef_cap + k] = cc[k];
   }
+  // small single-column problems: the whole iteration in one work-group, on
+  // the caller's stream
+  if (small_cg_eligible(c, nrhs, maxit)) {
+    c->last_path = 1;
+    BRAS_HIP(hipMemcpyAsync(g->stcoef, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, us));
+    if ((st = launch_small_stationary(c, pc, b_d, x_d, rtol, maxit, g->stcoef, g->stcoef_cap, g->sc, g->ic, us)))
+      return st;
+    if ((st = read_state(c, us))) return st;
+    return report(c, R, rtol, maxit, iters_h, relres_h, false);
+  }
+  c->last_path = 0;
   std::vector<hipGraphExec_t>* graphs = nullptr;
   if ((st = capture_graphs(c, CgState::Key{1, pc, 0, maxit}, [&](hipStream_t ss) { return st_iteration(c, pc, maxit, ss); },
                            &graphs)))
@@ -655,17 +668,7 @@ static int stationary(Ctx* c, int pc, const std::vector<double>& ca, const std::
   }
   (void)hipEventDestroy(ev);
   if (st) return st;
-  int result = BRAS_OK;
-  for (int col = 0; col < R; ++col) {
-    if (iters_h) iters_h[col] = g->ic_host[I_ITERS * R + col];
-    if (relres_h) relres_h[col] = g->sc_host[S_RELRES * R + col];
-    const int cs = g->ic_host[I_STATUS * R + col];
-    if (cs == ST_BREAK) result = BRAS_EBREAKDOWN;
-    else if (cs == ST_NOCONV && result == BRAS_OK) result = BRAS_ENOCONV;
-  }
-  if (result == BRAS_EBREAKDOWN) return fail(result, "non-finite residual");
-  if (result == BRAS_ENOCONV) return fail(result, "did not reach rtol=%g within maxit=%d", rtol, maxit);
-  return BRAS_OK;
+  return report(c, R, rtol, maxit, iters_h, relres_h, false);
 }
 
 static int check_stationary(bras_handle h, int pc, const double* b_d, double* x_d, int nrhs, double rtol, int maxit) {

@@ -196,6 +196,37 @@ __device__ inline double precond(const SmallOp& o, const Elems<NL>& el, int pc, 
   return rzp;
 }
 
+// Set-up shared by the solvers: the transpose map into LDS, the thread's
+// element data and own-DOF values into registers, sv = x (no barrier).
+template <int NL>
+__device__ inline void small_setup(const SmallOp& o, const double* xio, unsigned short* slot, double* sv,
+                                   Elems<NL>& el, int (&r0)[kPerThread], int (&r1)[kPerThread],
+                                   double (&x)[kPerThread], double (&dinv)[kPerThread], double (&jinv)[kPerThread]) {
+  const int t = threadIdx.x;
+  for (int p = t; p < o.nbr; p += kSmallThreads) slot[p] = (unsigned short)o.slot[p];
+#pragma unroll
+  for (int e = 0; e < Elems<NL>::EPT; ++e) {
+    const int K = t + e * kSmallThreads;
+    const int Kc = K < o.E ? K : 0;
+    el.c[e] = o.coef[Kc];
+    el.ic[e] = o.icoef[Kc];
+#pragma unroll
+    for (int j = 0; j < Elems<NL>::MR; ++j) el.m[e][j] = map_in_registers<NL>() ? o.l2g[(int64_t)Kc * NL + j] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int i = t + k * kSmallThreads;
+    const bool own = i < o.n;
+    const int ii = own ? i : 0;
+    r0[k] = own ? o.rowptr[ii] : 0;
+    r1[k] = own ? o.rowptr[ii + 1] : 0;
+    x[k] = own ? xio[ii] : 0.0;
+    dinv[k] = o.invd[ii];
+    jinv[k] = o.invdiag[ii];
+    if (own) sv[i] = x[k];
+  }
+}
+
 // One work-group.  xio: initial guess on entry, solution on exit.  Writes
 // sc / ic (one column) as the multi-pass solver leaves them.
 template <int NL>
@@ -209,35 +240,14 @@ __global__ void __launch_bounds__(kSmallThreads) k_cg_small(SmallOp o, int pc, c
   double* sv = lds + n;                  // d^-1 r, or x for M x [n]
   double* zb = lds + 2 * n;              // [n_loc][E]
   unsigned short* slot = (unsigned short*)(lds + 2 * n + o.nbr);   // [n_br]
-  // set-up: map, coefficients, own DOFs
-  for (int p = t; p < o.nbr; p += kSmallThreads) slot[p] = (unsigned short)o.slot[p];
   Elems<NL> el;
-#pragma unroll
-  for (int e = 0; e < Elems<NL>::EPT; ++e) {
-    const int K = t + e * kSmallThreads;
-    const int Kc = K < o.E ? K : 0;
-    el.c[e] = o.coef[Kc];
-    el.ic[e] = o.icoef[Kc];
-#pragma unroll
-    for (int j = 0; j < Elems<NL>::MR; ++j) el.m[e][j] = map_in_registers<NL>() ? o.l2g[(int64_t)Kc * NL + j] : 0;
-  }
   int r0[kPerThread], r1[kPerThread];
   double x[kPerThread], r[kPerThread], z[kPerThread], q[kPerThread], dinv[kPerThread], jinv[kPerThread];
+  small_setup<NL>(o, xio, slot, sv, el, r0, r1, x, dinv, jinv);
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    const int i = t + k * kSmallThreads;
-    const bool own = i < n;
-    const int ii = own ? i : 0;
-    r0[k] = own ? o.rowptr[ii] : 0;
-    r1[k] = own ? o.rowptr[ii + 1] : 0;
-    x[k] = own ? xio[ii] : 0.0;
-    dinv[k] = o.invd[ii];
-    jinv[k] = o.invdiag[ii];
     r[k] = z[k] = q[k] = 0.0;
-    if (own) {
-      sv[i] = x[k];
-      pv[i] = 0.0;
-    }
+    if (t + k * kSmallThreads < n) pv[t + k * kSmallThreads] = 0.0;
   }
   __syncthreads();
   // r_0 = b - M x_0
@@ -341,6 +351,109 @@ __global__ void __launch_bounds__(kSmallThreads) k_cg_small(SmallOp o, int pc, c
   }
 }
 
+// Stationary iteration (Section 4) in one work-group, the iteration of the
+// multi-pass stationary driver:
+//   r_0 = b - M x_0;  stop if ||r_k|| <= rtol ||r_0||;
+//   d_k = a_k d_{k-1} + c_k C r_k;  x_{k+1} = x_k + d_k;  r_{k+1} = b - M x_{k+1}
+// with the coefficient table coef[0 .. cap) = a_k, coef[cap ..) = c_k.
+template <int NL>
+__global__ void __launch_bounds__(kSmallThreads) k_st_small(SmallOp o, int pc, const double* __restrict__ bg,
+                                                            double* __restrict__ xio, double rtol, int maxit,
+                                                            const double* __restrict__ coef, int cap,
+                                                            double* __restrict__ sc, int* __restrict__ ic) {
+  __shared__ double lds[kLdsDoubles];
+  __shared__ double red[2 * kSmallWaves];
+  const int t = threadIdx.x, n = o.n;
+  double* sv = lds + n;                  // x for M x, or d^-1 r
+  double* zb = lds + 2 * n;              // [n_loc][E]
+  unsigned short* slot = (unsigned short*)(lds + 2 * n + o.nbr);   // [n_br]
+  Elems<NL> el;
+  int r0[kPerThread], r1[kPerThread];
+  double x[kPerThread], r[kPerThread], d[kPerThread], b[kPerThread], q[kPerThread], dinv[kPerThread],
+      jinv[kPerThread];
+  small_setup<NL>(o, xio, slot, sv, el, r0, r1, x, dinv, jinv);
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int i = t + k * kSmallThreads;
+    b[k] = i < n ? bg[i] : 0.0;
+    d[k] = 0.0;
+  }
+  __syncthreads();
+  // r = b - M x (sv holds x; called after a barrier that follows the writes
+  // of sv and the last reads of zb); returns the thread's part of r.r
+  auto residual = [&]() {
+    elem_pass<NL, false>(o, el, o.ref, sv, zb);
+    __syncthreads();
+    reduce_pass(r0, r1, slot, zb, q);
+    double rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      r[k] = b[k] - q[k];
+      rr = fma(r[k], r[k], rr);
+    }
+    return rr;
+  };
+  double rr = residual(), dummy = 0.0;
+  wg_sum2(rr, dummy, red);
+  const double rn0 = sqrt(rr), target = rtol * rn0;
+  int status = ST_RUN, it = 0;
+  double relres = rn0 > 0.0 ? 1.0 : 0.0;
+  if (!isfinite(rn0)) status = ST_BREAK;
+  else if (rn0 == 0.0) status = ST_OK;
+  while (status == ST_RUN) {
+    const double a = coef[it], c = coef[cap + it];
+    // d = a d + c C r; x += d
+    if (pc == BRAS_PC_BRAS) {
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        const int i = t + k * kSmallThreads;
+        if (i < n) sv[i] = r[k] * dinv[k];
+      }
+      __syncthreads();
+      elem_pass<NL, true>(o, el, o.refinv, sv, zb);
+      __syncthreads();
+      reduce_pass(r0, r1, slot, zb, q);
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) d[k] = fma(a, d[k], c * (q[k] * dinv[k]));
+    } else {
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) d[k] = fma(a, d[k], c * (r[k] * jinv[k]));
+    }
+    // (every thread has passed the barrier after the element pass that read
+    // sv, so sv can take x)
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int i = t + k * kSmallThreads;
+      x[k] = x[k] + d[k];
+      if (i < n) sv[i] = x[k];
+    }
+    __syncthreads();
+    double rrp = residual();
+    wg_sum2(rrp, dummy, red);
+    ++it;
+    const double nrm = sqrt(rrp);
+    relres = nrm / rn0;
+    if (!isfinite(nrm)) status = ST_BREAK;
+    else if (nrm <= target) status = ST_OK;
+    else if (it >= maxit) status = ST_NOCONV;
+    rr = rrp;
+  }
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int i = t + k * kSmallThreads;
+    if (i < n) xio[i] = x[k];
+  }
+  if (t == 0) {
+    sc[S_R0] = rn0;
+    sc[S_TARGET] = target;
+    sc[S_RR] = rr;
+    sc[S_RELRES] = relres;
+    ic[I_ITERS] = it;
+    ic[I_STATUS] = status;
+    ic[I_ACTIVE] = 0;
+  }
+}
+
 }  // namespace
 
 // the H1 element sizes of degrees 1-4 (2D: 3, 6, 10, 15; 3D: 4, 10, 20, 35)
@@ -363,9 +476,7 @@ bool small_cg_eligible(const Ctx* c, int nrhs, int maxit) {
          16 * c->n + 10 * c->nbr <= kSmallLdsBytes && maxit <= kSmallMaxIt;
 }
 
-int launch_small_cg(Ctx* c, int pc, const double* b, double* x, double rtol, int maxit, double* sc, int* ic,
-                    hipStream_t s) {
-  BRAS_CHECK(small_cg_eligible(c, 1, maxit), "problem not eligible for the single work-group solver");
+static SmallOp small_op(const Ctx* c) {
   SmallOp o;
   o.E = (int)c->E;
   o.n = (int)c->n;
@@ -379,9 +490,33 @@ int launch_small_cg(Ctx* c, int pc, const double* b, double* x, double rtol, int
   o.icoef = c->icoef;
   o.invd = c->invd;
   o.invdiag = c->invdiag;
+  return o;
+}
+
+int launch_small_cg(Ctx* c, int pc, const double* b, double* x, double rtol, int maxit, double* sc, int* ic,
+                    hipStream_t s) {
+  BRAS_CHECK(small_cg_eligible(c, 1, maxit), "problem not eligible for the single work-group solver");
+  const SmallOp o = small_op(c);
 #define CASE(N)                                                                  \
   case N:                                                                        \
     k_cg_small<N><<<1, kSmallThreads, 0, s>>>(o, pc, b, x, rtol, maxit, sc, ic); \
+    break;
+  switch (c->nl) {
+    SMALL_NL_CASES(CASE)
+    default: return fail(BRAS_EINVAL, "n_loc %d has no single work-group solver", c->nl);
+  }
+#undef CASE
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+int launch_small_stationary(Ctx* c, int pc, const double* b, double* x, double rtol, int maxit, const double* coef,
+                            int cap, double* sc, int* ic, hipStream_t s) {
+  BRAS_CHECK(small_cg_eligible(c, 1, maxit) && cap >= maxit, "problem not eligible for the single work-group solver");
+  const SmallOp o = small_op(c);
+#define CASE(N)                                                                                \
+  case N:                                                                                      \
+    k_st_small<N><<<1, kSmallThreads, 0, s>>>(o, pc, b, x, rtol, maxit, coef, cap, sc, ic);    \
     break;
   switch (c->nl) {
     SMALL_NL_CASES(CASE)

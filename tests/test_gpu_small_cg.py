@@ -163,3 +163,68 @@ def test_problems_outside_the_small_solver_use_multipass():
         L.bras_set_option(gpu.h, L.OPT_SMALL_CG, 2)
     assert e.value.code == L.BRAS_EINVAL
     gpu.close()
+
+
+def stationary(gpu, kind, b, pc, small, **kw):
+    from paper_2607_12138_amd import _lib as L
+    L.bras_set_option(gpu.h, L.OPT_SMALL_CG, 1 if small else 0)
+    fn = gpu.fixed_point if kind == "fp" else gpu.chebyshev
+    x, st, its, rel = fn(b, pc, **kw)
+    assert gpu.info("solve_path") == (1 if small else 0)
+    return x.cpu().numpy(), st, int(its[0]), float(rel[0])
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[4], CASES[6]], ids=ids)
+def test_small_stationary_matches_oracle_and_multipass(case):
+    """Damped fixed point (BRAS and Jacobi weights from the power iteration)
+    and Chebyshev with BRAS on [1, 1.02 lambda_max] (Section 4)."""
+    import torch
+    from oracle import stationary as ost
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(case)
+    f = workloads.rhs(orc.n, 1, 12)
+    ft = torch.from_numpy(f).cuda()
+    nf = np.linalg.norm(f)
+    v0 = workloads.vector(orc.n, 7)
+    runs = []
+    for pc, C in (("bras", orc.B.dot), ("jacobi", opcg.jacobi(orc.diag))):
+        lam = ost.power_lambda_max(orc.M, C, v0, iters=50)
+        om = 2.0 / (1.0 + lam) if pc == "bras" else 1.0 / lam
+        runs.append(("fp", pc, dict(omega=om), ost.fixed_point(orc.M, f, C, om, tol=TOL)))
+        if pc == "bras":
+            runs.append(("cheb", pc, dict(lmin=1.0, lmax=1.02 * lam),
+                         ost.chebyshev(orc.M, f, C, 1.0, 1.02 * lam, tol=TOL)))
+    for kind, pc, kw, (xo, ito, ok, _) in runs:
+        assert ok
+        xs, sts, its_s, rel_s = stationary(gpu, kind, ft, pc, True, rtol=TOL, **kw)
+        xm, stm, its_m, rel_m = stationary(gpu, kind, ft, pc, False, rtol=TOL, **kw)
+        say("  %s %s: oracle %d, one work-group %d, multi-pass %d" % (kind, pc, ito, its_s, its_m))
+        assert sts == stm == L.BRAS_OK
+        assert abs(its_s - ito) <= 1 and abs(its_s - its_m) <= 1
+        # relres is the residual of the returned iterate
+        assert abs(np.linalg.norm(f - orc.M @ xs) / nf - rel_s) <= 1e-3 * TOL + 1e-14
+        for other in (xo, xm):
+            assert np.linalg.norm(orc.M @ (xs - other)) <= 4 * TOL * nf
+    gpu.close()
+
+
+def test_small_stationary_maxit_and_zero_rhs():
+    import torch
+    from oracle import stationary as ost
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(("P", 2, 2, 10, 0.2, True))
+    f = workloads.rhs(orc.n, 1, 13)
+    ft = torch.from_numpy(f).cuda()
+    lam = ost.power_lambda_max(orc.M, orc.B.dot, workloads.vector(orc.n, 7), iters=50)
+    om = 2.0 / (1.0 + lam)
+    xo, ito, ok, _ = ost.fixed_point(orc.M, f, orc.B.dot, om, tol=TOL, maxit=3)
+    assert not ok and ito == 3
+    xs, sts, its_s, _ = stationary(gpu, "fp", ft, "bras", True, omega=om, rtol=TOL, maxit=3)
+    xm, stm, its_m, _ = stationary(gpu, "fp", ft, "bras", False, omega=om, rtol=TOL, maxit=3)
+    assert sts == stm == L.BRAS_ENOCONV and its_s == its_m == 3
+    assert np.linalg.norm(xs - xm) <= 1e-13 * np.linalg.norm(xm)
+    assert np.linalg.norm(xs - xo) <= 1e-12 * np.linalg.norm(xo)
+    zero = torch.zeros(orc.n, dtype=torch.float64, device="cuda")
+    x, st, its, rel = stationary(gpu, "cheb", zero, "bras", True, lmin=1.0, lmax=1.02 * lam, rtol=TOL)
+    assert st == L.BRAS_OK and its == 0 and rel == 0.0 and not x.any()
+    gpu.close()
