@@ -111,6 +111,43 @@ def time_apply(fn, x, y, reps):
     return e0.elapsed_time(e1) / reps * 1e3   # microseconds
 
 
+def time_apply_cold(fn, x, y, reps, flush_bytes=1 << 29):
+    """Average duration of fn with none of its data in the 256 MB Infinity
+    Cache: a 512 MiB buffer is written on the same stream before each call,
+    outside the HIP events that bracket the call."""
+    import torch
+    s = torch.cuda.current_stream()
+    junk = torch.empty(flush_bytes // 8, dtype=torch.float64, device=x.device)
+    fn(x, y)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for k in range(reps):
+        junk.fill_(float(k))
+        ev[k][0].record(s)
+        fn(x, y)
+        ev[k][1].record(s)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps * 1e3   # microseconds
+
+
+def device_copy_gbs(reps=5):
+    """Bytes read plus written per second by a plain 1 GiB device-to-device
+    copy: the streaming rate HBM actually delivers, beside its 8 TB/s peak."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(s)
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / reps * 1e-3
+    del src, dst
+    return 2 * (1 << 30) / sec / 1e9
+
+
 def stationary_section(prob, b, w, steps):
     """Section 4's other solvers on the same system: damped fixed point with
     omega_bras = 2/(1 + lambda_max) and omega_diag = 1/lambda_max, and the
@@ -279,6 +316,8 @@ def main():
     y = prob.vec(w.nrhs)
     bras_us = time_apply(lambda u, v: L.bras_apply(prob.h, u, v), x, y, a.apply_reps)
     mass_us = time_apply(lambda u, v: L.mass_apply(prob.h, u, v), x, y, a.apply_reps)
+    cold_us = time_apply_cold(lambda u, v: L.bras_apply(prob.h, u, v), x, y, 20)
+    copy_gbs = device_copy_gbs()
     nbytes = algorithmic_bytes(w, prob.n, prob.E, prob.n_loc, w.nrhs, w.prec)
     achieved = nbytes / (bras_us * 1e-6) / 1e9
     assembled = None
@@ -312,10 +351,13 @@ def main():
         "bras_apply_us": round(bras_us, 3),
         "mass_apply_us": round(mass_us, 3),
         "bras_apply_gbs": round(achieved, 1),
+        "bras_apply_cold_us": round(cold_us, 3),
+        "bras_apply_cold_gbs": round(nbytes / (cold_us * 1e-6) / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "bras_apply (element pass + transpose-map reduce)",
-                     "bytes_per_launch": int(nbytes), "us_per_launch": round(bras_us, 3)},
+                     "bytes_per_launch": int(nbytes), "us_per_launch": round(bras_us, 3),
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "source_digest": source_digest(),
         "setup_s": round(setup_s, 3),
         "element_pass_variant": int(variant),

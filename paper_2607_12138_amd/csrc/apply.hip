@@ -51,8 +51,11 @@ enum { OUT_PLAIN = 0, OUT_MASS_CG = 1, OUT_BRAS_CG = 2, OUT_RES = 3, OUT_STAT = 
 constexpr int kEPB = 64;        // elements per work-group (one per lane)
 constexpr int kWS = kEPB + 1;   // LDS row stride
 
+// Up to n_loc 36 the register allocator is asked for 4 waves per SIMD (at
+// most 128 VGPRs), which it meets without spilling (n_loc 35: 131 -> 123
+// VGPRs, 3 -> 4 waves); larger n_loc keep their natural allocation.
 template <int NL, bool DS>
-__global__ void __launch_bounds__(kEB) k_elem(int64_t E, int R, const int32_t* __restrict__ l2g, InArgs in,
+__global__ void __launch_bounds__(kEB) __attribute__((amdgpu_waves_per_eu(NL <= 36 ? 4 : 1))) k_elem(int64_t E, int R, const int32_t* __restrict__ l2g, InArgs in,
                                               const double* __restrict__ dscale, const double* __restrict__ A,
                                               const double* __restrict__ coefK, double* __restrict__ zb) {
   typedef double T;
