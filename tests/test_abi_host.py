@@ -100,3 +100,38 @@ def test_binding_constants_match_header():
     assert set(py) == set(defs), set(py) ^ set(defs)
     for k, v in defs.items():
         assert py[k] == v, k
+
+
+def test_setup_and_geometry_reject_bad_arguments():
+    """Empty inputs, sizes beyond the documented limits and unsupported form /
+    precision pairs are rejected with EINVAL by checks that run before any
+    device call (placeholder pointers are never dereferenced)."""
+    lib = L.lib()
+    P = ctypes.c_void_p(0x1000)   # non-null placeholder, never dereferenced on these paths
+    h = ctypes.c_void_p()
+
+    def setup(n=10, E=4, nl=3, l2g=P, form=L.ELEM_SCALED_REF, ref=P, elem=P, nsym=0, prec=L.FP64, rhs=1):
+        return lib.bras_setup(ctypes.byref(h), n, E, nl, l2g, form, ref, elem, nsym, prec, rhs, None)
+
+    cases = {
+        "empty n": dict(n=0), "empty E": dict(E=0), "n_loc 0": dict(nl=0), "n_loc 121": dict(nl=121),
+        "E * n_loc >= 2^31": dict(E=1 << 28, nl=8), "null map": dict(l2g=None), "null elements": dict(elem=None),
+        "unknown form": dict(form=7), "metric without nsym": dict(form=L.ELEM_METRIC_REF, nsym=0),
+        "missing tables": dict(ref=None), "unknown precision": dict(prec=5),
+        "BF16 scaled": dict(prec=L.BF16), "FP32 scaled": dict(prec=L.FP32),
+        "max_rhs 0": dict(rhs=0), "max_rhs 257": dict(rhs=257), "block vector >= 4 GiB": dict(n=1 << 28, rhs=2),
+    }
+    for name, kw in cases.items():
+        assert setup(**kw) == L.BRAS_EINVAL, name
+        assert h.value is None, name
+        assert lib.bras_last_error(), name
+    assert lib.bras_setup(None, 10, 4, 3, P, L.ELEM_SCALED_REF, P, P, 0, L.FP64, 1, None) == L.BRAS_EINVAL
+    geo = lib.bras_geometry
+    assert geo(L.H1, 4, 3, P, 1, P, None, P, None) == L.BRAS_EINVAL          # dim
+    assert geo(9, 2, 3, P, 1, P, None, P, None) == L.BRAS_EINVAL             # family
+    assert geo(L.H1, 2, 3, None, 1, P, None, P, None) == L.BRAS_EINVAL       # null coordinates
+    assert geo(L.H1, 2, 3, P, 0, P, None, P, None) == L.BRAS_EINVAL          # empty mesh
+    # calls on a null handle
+    for fn in ("bras_apply", "mass_apply", "jacobi_apply"):
+        assert getattr(lib, fn)(None, P, P, 1, None) == L.BRAS_EINVAL, fn
+    assert lib.pcg_solve(None, L.PC_BRAS, P, P, 1, 1e-8, 10, None, None, None) == L.BRAS_EINVAL
