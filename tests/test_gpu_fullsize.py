@@ -32,6 +32,8 @@ def test_sampled_rows_and_solve(w):
     say("full-size setup %s n=%d E=%d" % (w.name, n, len(cells)))
     gpu = MassProblem(w.family, w.dim, w.degree, w.N, jitter=w.jitter, seed=w.mesh_seed, rho=rho, prec=w.prec)
     assert gpu.n == n and np.array_equal(gpu.l2g, pi.astype(np.int32))
+    variant = gpu.autotune(w.nrhs)        # the element-pass variant the benchmark times with
+    say("  autotuned variant %d" % variant)
     x = workloads.vector(n, w.seed(4))
     rows = workloads.sample(n, 48, w.seed(4))
     say("  sampled mass/bras rows")
