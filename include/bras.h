@@ -262,6 +262,34 @@ int bras_csr_assemble(bras_handle h, int op, const int64_t* rowptr_d, int32_t* c
 int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t* col_d, const double* val_d,
                    const double* x_d, double* y_d, void* stream);
 
+/* ---- sparse products for Schur-complement approximations (Section 5:
+ * -St = C + G Mt^-1 G^T, eq. approx_positive_schur_general, sparse when Mt^-1
+ * is the assembled M_bras^-1; formed as (G M_bras^-1) G^T with these calls) --
+ * CSR on the device as above: int64 row pointers (non-decreasing, from 0 to
+ * nnz), int32 columns ascending and distinct within each row, float64
+ * values.  Buffers are caller allocated; sizes below 2^31.
+ * C = A B for A (m x k) and B (k x n).  bras_spgemm_rowptr writes C's row
+ * pointers c_rowptr_d [m+1] and nnz(C) (synchronises the stream);
+ * bras_spgemm_fill writes C's columns (ascending) and values, each entry the
+ * sum of its products in the order of A's columns (fma, one B row at a time):
+ * the same result for every launch shape.  EINVAL when a row of A has a
+ * column outside [0, k), malformed row pointers, more than 2048 candidate
+ * products in one row (the sum over the row of A of the selected B row
+ * lengths), nnz(C) >= 2^31, or (fill) row pointers that do not match the
+ * counts.  Synchronous. */
+int bras_spgemm_rowptr(int64_t m, int64_t k, const int64_t* a_rowptr_d, const int32_t* a_col_d,
+                       const int64_t* b_rowptr_d, const int32_t* b_col_d, int64_t* c_rowptr_d, int64_t* nnz_h,
+                       void* stream);
+int bras_spgemm_fill(int64_t m, int64_t k, const int64_t* a_rowptr_d, const int32_t* a_col_d, const double* a_val_d,
+                     const int64_t* b_rowptr_d, const int32_t* b_col_d, const double* b_val_d,
+                     const int64_t* c_rowptr_d, int32_t* c_col_d, double* c_val_d, void* stream);
+/* A^T (n x m) of A (m x n): row j of A^T lists the rows of A holding column
+ * j, ascending, with their values (a stable sort by column; exact).  EINVAL
+ * for malformed row pointers or a column outside [0, n).  Synchronous;
+ * allocates temporary device memory. */
+int bras_csr_transpose(int64_t m, int64_t n, const int64_t* rowptr_d, const int32_t* col_d, const double* val_d,
+                       int64_t* rowptr_t_d, int32_t* col_t_d, double* val_t_d, void* stream);
+
 #define BRAS_OPT_GRAPH_ITERS 0  /* CG iterations per captured graph (>= 1)     */
 #define BRAS_OPT_MAX_RESTART 1  /* refinement restarts allowed (>= 0)         */
 #define BRAS_OPT_VARIANT     2  /* force a scheduling variant (-1 = built-in)  */

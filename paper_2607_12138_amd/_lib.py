@@ -75,6 +75,9 @@ _SIGS = {
     "bras_csr_rowptr": [vp, vp, P_i64, vp],
     "bras_csr_assemble": [vp, i32, vp, vp, vp, vp],
     "bras_csr_apply": [i64, vp, vp, vp, vp, vp, vp],
+    "bras_spgemm_rowptr": [i64, i64, vp, vp, vp, vp, vp, P_i64, vp],
+    "bras_spgemm_fill": [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+    "bras_csr_transpose": [i64, i64, vp, vp, vp, vp, vp, vp, vp],
 }
 
 
@@ -289,6 +292,24 @@ def bras_csr_assemble(h, op, rowptr_d, col_d, val_d, stream=None):
 
 def bras_csr_apply(n, rowptr_d, col_d, val_d, x_d, y_d, stream=None):
     check(lib().bras_csr_apply(n, _dev(rowptr_d), _dev(col_d), _dev(val_d), _dev(x_d), _dev(y_d), _stream(stream)))
+
+
+def bras_spgemm_rowptr(m, k, a, b, c_rowptr_d, stream=None):
+    """Row pointers of C = A B (a, b: (rowptr, col, val) device tensors); returns nnz(C)."""
+    nnz = C.c_int64()
+    check(lib().bras_spgemm_rowptr(m, k, _dev(a[0]), _dev(a[1]), _dev(b[0]), _dev(b[1]), _dev(c_rowptr_d),
+                                   C.byref(nnz), _stream(stream)))
+    return nnz.value
+
+
+def bras_spgemm_fill(m, k, a, b, c, stream=None):
+    check(lib().bras_spgemm_fill(m, k, _dev(a[0]), _dev(a[1]), _dev(a[2]), _dev(b[0]), _dev(b[1]), _dev(b[2]),
+                                 _dev(c[0]), _dev(c[1]), _dev(c[2]), _stream(stream)))
+
+
+def bras_csr_transpose(m, n, a, t, stream=None):
+    check(lib().bras_csr_transpose(m, n, _dev(a[0]), _dev(a[1]), _dev(a[2]), _dev(t[0]), _dev(t[1]), _dev(t[2]),
+                                   _stream(stream)))
 
 
 def bras_set_option(h, opt, value):

@@ -21,6 +21,7 @@ SOURCES = [
     ("setup.hip", []),
     ("apply.hip", []),
     ("csr.hip", []),
+    ("spgemm.hip", []),
     ("lane_packed_f64.hip", []),
     ("lane_packed_f32.hip", []),
     ("lane_metric3.hip", []),

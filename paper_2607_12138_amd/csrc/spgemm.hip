@@ -1,0 +1,352 @@
+// Sparse products for the Schur-complement approximations of Section 5:
+// -St = C + G Mt^-1 G^T (eq. approx_positive_schur_general) is sparse when
+// Mt^-1 is (M_bras^-1 has the sparsity of M), and is formed from the
+// assembled operator as two products, (G Mt^-1) G^T, with the transpose of G.
+//
+// C = A B (CSR, int64 row pointers, int32 columns ascending and distinct
+// within each row, float64 values): one wavefront per row of C.  The
+// candidate columns of row i (the columns of the B rows that row i of A
+// selects) are gathered into LDS, sorted (bitonic) and counted or written
+// distinct; each entry then sums its products in the order of A's columns,
+// one B row at a time, so the result does not depend on the launch shape.
+//
+// A^T: a stable radix sort of the entries by column (hipCUB), so each row of
+// A^T lists A's rows in ascending order; exact (no arithmetic).
+#include <vector>
+
+#include <hipcub/hipcub.hpp>
+
+#include "internal.h"
+
+namespace bras {
+namespace {
+
+constexpr int kGemmCap = 2048;   // candidate products of one row of C
+
+template <int FILL>
+__global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64_t* __restrict__ a_rp,
+                                               const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
+                                               const int64_t* __restrict__ b_rp, const int32_t* __restrict__ b_col,
+                                               const double* __restrict__ b_val, int32_t* __restrict__ cnt,
+                                               const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
+                                               double* __restrict__ c_val, int* __restrict__ flag) {
+  __shared__ int32_t cand[kGemmCap];
+  __shared__ int32_t ucol[kGemmCap];
+  __shared__ double acc[kGemmCap];
+  __shared__ int32_t pre[kGemmCap + 1];   // prefix sums of the selected B row lengths
+  __shared__ int ok_s, tot_s;
+  const int t = threadIdx.x;
+  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const int64_t p0 = a_rp[i];
+    const int64_t na64 = a_rp[i + 1] - p0;
+    if (t == 0) {
+      // rows are validated before any candidate is read: row pointers of A
+      // and of the selected B rows inside [0, nnz] and non-decreasing, A's
+      // columns indexing rows of B, the candidates fitting in LDS
+      const int64_t annz = a_rp[m], bnnz = b_rp[k];
+      int ok = na64 >= 0 && na64 <= kGemmCap && p0 >= 0 && p0 + na64 <= annz;
+      int64_t tot = 0;
+      if (ok) {
+        pre[0] = 0;
+        for (int p = 0; p < (int)na64; ++p) {
+          const int32_t a = a_col[p0 + p];
+          if (a < 0 || a >= k) {
+            ok = 0;
+            break;
+          }
+          const int64_t b0 = b_rp[a], b1 = b_rp[a + 1];
+          if (b0 < 0 || b1 < b0 || b1 > bnnz) {
+            ok = 0;
+            break;
+          }
+          tot += b1 - b0;
+          if (tot > kGemmCap) {
+            ok = 0;
+            break;
+          }
+          pre[p + 1] = (int32_t)tot;
+        }
+      }
+      ok_s = ok;
+      tot_s = ok ? (int)tot : 0;
+    }
+    __syncthreads();
+    if (!ok_s) {
+      if (t == 0) {
+        flag[0] = 1;
+        if (!FILL) cnt[i] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const int na = (int)na64, mt = tot_s;
+    int m2 = 1;
+    while (m2 < mt) m2 <<= 1;
+    for (int q = t; q < m2; q += 64) {
+      int32_t cv = 0x7fffffff;
+      if (q < mt) {
+        // the A entry whose B row holds candidate q: the largest p with
+        // pre[p] <= q (empty B rows share their prefix with the next row)
+        int lo = 0, hi = na - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pre[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const int32_t a = a_col[p0 + lo];
+        cv = b_col[b_rp[a] + (q - pre[lo])];
+      }
+      cand[q] = cv;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= m2; kk <<= 1)
+      for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+        for (int q = t; q < m2; q += 64) {
+          const int pq = q ^ jj;
+          if (pq > q) {
+            const int32_t x = cand[q], y = cand[pq];
+            if ((x > y) == ((q & kk) == 0)) {
+              cand[q] = y;
+              cand[pq] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    int u = 0;   // distinct columns, compacted in ascending order
+    for (int q0 = 0; q0 < mt; q0 += 64) {
+      const int q = q0 + t;
+      const bool head = q < mt && (q == 0 || cand[q] != cand[q - 1]);
+      const uint64_t mask = __ballot(head);
+      if (head) ucol[u + __popcll(mask & ((1ull << t) - 1ull))] = cand[q];
+      u += __popcll(mask);
+    }
+    __syncthreads();
+    if (!FILL) {
+      if (t == 0) cnt[i] = u;
+      __syncthreads();
+      continue;
+    }
+    for (int q = t; q < u; q += 64) acc[q] = 0.0;
+    __syncthreads();
+    for (int p = 0; p < na; ++p) {
+      const int32_t a = a_col[p0 + p];
+      const double av = a_val[p0 + p];
+      const int64_t bs = b_rp[a];
+      const int lb = (int)(b_rp[a + 1] - bs);
+      // the columns of one B row are distinct: no two lanes share a position
+      for (int q = t; q < lb; q += 64) {
+        const int32_t cj = b_col[bs + q];
+        int lo = 0, hi = u - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (ucol[mid] < cj) lo = mid + 1; else hi = mid;
+        }
+        acc[lo] = fma(av, b_val[bs + q], acc[lo]);
+      }
+      __syncthreads();
+    }
+    // the output row must have exactly the counted length inside [0, nnz(C)]
+    const int64_t o = c_rp[i];
+    if (o < 0 || c_rp[i + 1] - o != u || c_rp[i + 1] > c_rp[m]) {
+      if (t == 0) flag[0] = 1;
+      __syncthreads();
+      continue;
+    }
+    for (int q = t; q < u; q += 64) {
+      c_col[o + q] = ucol[q];
+      c_val[o + q] = acc[q];
+    }
+    __syncthreads();
+  }
+}
+
+// row index of every entry; rows whose pointers leave [0, nnz] or decrease
+// raise the flag and write nothing
+__global__ void __launch_bounds__(256) k_row_of(int64_t m, int64_t nnz, const int64_t* __restrict__ rp,
+                                                int32_t* __restrict__ rowof, int* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const int64_t r0 = rp[i], r1 = rp[i + 1];
+    if (r0 < 0 || r1 < r0 || r1 > nnz) {
+      flag[0] = 1;
+      continue;
+    }
+    for (int64_t p = r0; p < r1; ++p) rowof[p] = (int32_t)i;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_iota(int64_t nnz, int32_t* __restrict__ idx) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride) idx[p] = (int32_t)p;
+}
+
+__global__ void __launch_bounds__(256) k_gather_t(int64_t nnz, const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ rowof, const double* __restrict__ val,
+                                                  int32_t* __restrict__ col_t, double* __restrict__ val_t) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nnz; r += stride) {
+    const int32_t p = perm[r];
+    col_t[r] = rowof[p];
+    val_t[r] = val[p];
+  }
+}
+
+// rp_t[j] = number of sorted keys below j, j = 0..n
+__global__ void __launch_bounds__(256) k_col_starts(int64_t n, const int32_t* __restrict__ keys, int64_t nnz,
+                                                    int64_t* __restrict__ rp_t) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= n; j += stride) {
+    int64_t lo = 0, hi = nnz;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)keys[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    rp_t[j] = lo;
+  }
+}
+
+unsigned grid_of(int64_t work, int per_cu) {
+  int dev = 0, ncu = 1;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    ncu = 1;
+  const int64_t want = (int64_t)ncu * per_cu;
+  const int64_t g = work < want ? work : want;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Frees what it holds at scope exit (the entry points return on every error).
+struct DevBufs {
+  std::vector<void*> p;
+  template <typename T>
+  int get(T** out, size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, count ? count * sizeof(T) : 1) != hipSuccess) return fail(BRAS_ENOMEM, "device allocation failed");
+    p.push_back(q);
+    *out = (T*)q;
+    return BRAS_OK;
+  }
+  ~DevBufs() {
+    for (void* q : p) (void)hipFree(q);
+  }
+};
+
+}  // namespace
+}  // namespace bras
+
+using namespace bras;
+
+extern "C" int bras_spgemm_rowptr(int64_t m, int64_t k, const int64_t* a_rowptr_d, const int32_t* a_col_d,
+                                  const int64_t* b_rowptr_d, const int32_t* b_col_d, int64_t* c_rowptr_d,
+                                  int64_t* nnz_h, void* stream) {
+  clear_error();
+  BRAS_CHECK(m >= 0 && k >= 0, "negative size");
+  BRAS_CHECK(m < (1LL << 31) && k < (1LL << 31), "sizes must stay below 2^31");
+  BRAS_CHECK(a_rowptr_d && a_col_d && b_rowptr_d && b_col_d && c_rowptr_d && nnz_h, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int64_t> rp(m + 1, 0);
+  if (m > 0) {
+    DevBufs tmp;
+    int32_t* cnt = nullptr;
+    int* flag = nullptr;
+    int st;
+    if ((st = tmp.get(&cnt, (size_t)m)) || (st = tmp.get(&flag, 1))) return st;
+    BRAS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_spgemm<0><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rowptr_d, a_col_d, nullptr, b_rowptr_d, b_col_d, nullptr, cnt,
+                                              nullptr, nullptr, nullptr, flag);
+    BRAS_HIP(hipGetLastError());
+    std::vector<int32_t> hc(m);
+    int hf = 0;
+    BRAS_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+    BRAS_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    BRAS_HIP(hipStreamSynchronize(s));
+    BRAS_CHECK(!hf, "a row of A has a column outside [0, %lld) or selects more than %d products", (long long)k,
+               kGemmCap);
+    for (int64_t i = 0; i < m; ++i) rp[i + 1] = rp[i] + hc[i];
+  }
+  BRAS_CHECK(rp[m] < (1LL << 31), "the product has %lld entries; at most 2^31 - 1 are supported", (long long)rp[m]);
+  BRAS_HIP(hipMemcpyAsync(c_rowptr_d, rp.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  *nnz_h = rp[m];
+  return BRAS_OK;
+}
+
+extern "C" int bras_spgemm_fill(int64_t m, int64_t k, const int64_t* a_rowptr_d, const int32_t* a_col_d,
+                                const double* a_val_d, const int64_t* b_rowptr_d, const int32_t* b_col_d,
+                                const double* b_val_d, const int64_t* c_rowptr_d, int32_t* c_col_d, double* c_val_d,
+                                void* stream) {
+  clear_error();
+  BRAS_CHECK(m >= 0 && k >= 0, "negative size");
+  BRAS_CHECK(m < (1LL << 31) && k < (1LL << 31), "sizes must stay below 2^31");
+  if (m == 0) return BRAS_OK;
+  BRAS_CHECK(a_rowptr_d && a_col_d && a_val_d && b_rowptr_d && b_col_d && b_val_d && c_rowptr_d && c_col_d && c_val_d,
+             "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  DevBufs tmp;
+  int* flag = nullptr;
+  int st;
+  if ((st = tmp.get(&flag, 1))) return st;
+  BRAS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  k_spgemm<1><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rowptr_d, a_col_d, a_val_d, b_rowptr_d, b_col_d, b_val_d, nullptr,
+                                            c_rowptr_d, c_col_d, c_val_d, flag);
+  BRAS_HIP(hipGetLastError());
+  int hf = 0;
+  BRAS_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  BRAS_CHECK(!hf, "a row of A has a column outside [0, %lld) or selects more than %d products", (long long)k, kGemmCap);
+  return BRAS_OK;
+}
+
+extern "C" int bras_csr_transpose(int64_t m, int64_t n, const int64_t* rowptr_d, const int32_t* col_d,
+                                  const double* val_d, int64_t* rowptr_t_d, int32_t* col_t_d, double* val_t_d,
+                                  void* stream) {
+  clear_error();
+  BRAS_CHECK(m >= 0 && n >= 0, "negative size");
+  BRAS_CHECK(m < (1LL << 31) && n < (1LL << 31), "sizes must stay below 2^31");
+  BRAS_CHECK(rowptr_d && rowptr_t_d, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  int64_t ends[2] = {0, 0};
+  BRAS_HIP(hipMemcpyAsync(ends, rowptr_d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipMemcpyAsync(ends + 1, rowptr_d + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  BRAS_CHECK(ends[0] == 0 && ends[1] >= 0 && ends[1] < (1LL << 31), "row pointers must start at 0 and end below 2^31");
+  const int64_t nnz = ends[1];
+  DevBufs tmp;
+  int st;
+  if (nnz == 0) {
+    std::vector<int64_t> z(n + 1, 0);
+    BRAS_HIP(hipMemcpyAsync(rowptr_t_d, z.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    BRAS_HIP(hipStreamSynchronize(s));
+    return BRAS_OK;
+  }
+  BRAS_CHECK(col_d && val_d && col_t_d && val_t_d, "null argument");
+  int32_t *rowof = nullptr, *idx = nullptr, *key_out = nullptr, *idx_out = nullptr;
+  int* flag = nullptr;
+  if ((st = tmp.get(&rowof, (size_t)nnz)) || (st = tmp.get(&idx, (size_t)nnz)) ||
+      (st = tmp.get(&key_out, (size_t)nnz)) || (st = tmp.get(&idx_out, (size_t)nnz)) || (st = tmp.get(&flag, 1)))
+    return st;
+  BRAS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  BRAS_HIP(hipMemsetAsync(rowof, 0, sizeof(int32_t) * nnz, s));
+  if (m > 0) k_row_of<<<grid_of((m + 255) / 256, 8), 256, 0, s>>>(m, nnz, rowptr_d, rowof, flag);
+  k_iota<<<grid_of((nnz + 255) / 256, 8), 256, 0, s>>>(nnz, idx);
+  BRAS_HIP(hipGetLastError());
+  size_t bytes = 0;
+  BRAS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, col_d, key_out, idx, idx_out, (int)nnz, 0, 32, s));
+  void* cub_tmp = nullptr;
+  if ((st = tmp.get((char**)&cub_tmp, bytes))) return st;
+  // stable: entries of one column keep their (row-major) order
+  BRAS_HIP(hipcub::DeviceRadixSort::SortPairs(cub_tmp, bytes, col_d, key_out, idx, idx_out, (int)nnz, 0, 32, s));
+  k_gather_t<<<grid_of((nnz + 255) / 256, 8), 256, 0, s>>>(nnz, idx_out, rowof, val_d, col_t_d, val_t_d);
+  k_col_starts<<<grid_of((n + 256) / 256, 8), 256, 0, s>>>(n, key_out, nnz, rowptr_t_d);
+  BRAS_HIP(hipGetLastError());
+  // every column inside [0, n): the first start is 0 and the last is nnz
+  int64_t tb[2] = {-1, -1};
+  int hf = 0;
+  BRAS_HIP(hipMemcpyAsync(tb, rowptr_t_d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipMemcpyAsync(tb + 1, rowptr_t_d + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  BRAS_CHECK(!hf, "row pointers must be non-decreasing from 0 to nnz");
+  BRAS_CHECK(tb[0] == 0 && tb[1] == nnz, "a column index lies outside [0, %lld)", (long long)n);
+  return BRAS_OK;
+}

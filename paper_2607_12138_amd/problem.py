@@ -152,3 +152,45 @@ class MassProblem:
             out = torch.empty(self.n, dtype=torch.float64, device=self.device)
         L.bras_export(self.h, what, out)
         return out
+
+    def schur(self, G, op=None):
+        """-St = G Mt^-1 G^T (Section 5, eq. approx_positive_schur_general with
+        C = 0) for a CSR coupling G = (rowptr, col, val) of shape m x n on the
+        device, Mt^-1 the assembled operator op (default L.OP_BRAS): the two
+        sparse products (G Mt^-1) G^T.  Returns the CSR of St (m x m)."""
+        op = L.OP_BRAS if op is None else op
+        m = G[0].numel() - 1
+        Bop = self.assemble(op)
+        T = spgemm(G, Bop, m, self.n)
+        Gt = csr_transpose(G, m, self.n)
+        return spgemm(T, Gt, m, self.n)
+
+
+def spgemm(a, b, m, k):
+    """C = A B for CSR device tensors a (m x k) and b (k x n), each
+    (rowptr int64, col int32, val float64); returns C as such a triple."""
+    import torch
+    dev = a[0].device
+    if a[1].numel() == 0 or b[1].numel() == 0:
+        return (torch.zeros(m + 1, dtype=torch.int64, device=dev), torch.empty(0, dtype=torch.int32, device=dev),
+                torch.empty(0, dtype=torch.float64, device=dev))
+    rp = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    nnz = L.bras_spgemm_rowptr(m, k, a, b, rp)
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+    L.bras_spgemm_fill(m, k, a, b, (rp, col, val))
+    return rp, col[:nnz], val[:nnz]
+
+
+def csr_transpose(a, m, n):
+    """A^T (n x m) of a CSR device triple a (m x n)."""
+    import torch
+    dev = a[0].device
+    nnz = a[1].numel()
+    rp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+    if nnz == 0:
+        return torch.zeros(n + 1, dtype=torch.int64, device=dev), col[:0], val[:0]
+    L.bras_csr_transpose(m, n, a, (rp, col, val))
+    return rp, col, val
