@@ -197,6 +197,44 @@ def assembled_section(prob, x, y, bras_us, reps):
             "gbs": round(nbytes / (us * 1e-6) / 1e9, 1), "time_vs_matrix_free": round(us / bras_us, 3)}
 
 
+def schur_section(prob, w, reps=3):
+    """Section 5's sparse Schur-complement approximation -St = G M_bras^-1 G^T
+    (eq. approx_positive_schur_general, C = 0) for a coupling G with one row per
+    element holding its DOFs (the pattern of a discrete divergence or gradient
+    on the cells) with seeded U[-1,1] values: the assembled BRAS operator, then
+    the two device products (G M_bras^-1) G^T.  Best of reps, each from the
+    assembled operator (its assembly is timed separately above)."""
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    from paper_2607_12138_amd.problem import spgemm, csr_transpose
+    E, nl, n = prob.E, prob.n_loc, prob.n
+    rp = torch.arange(0, (E + 1) * nl, nl, dtype=torch.int64, device="cuda")
+    col = torch.from_numpy(np.ascontiguousarray(np.sort(prob.l2g, axis=1), dtype=np.int32).reshape(-1)).cuda()
+    val = torch.from_numpy(workloads.vector(E * nl, w.seed(5))).cuda()
+    G = (rp, col, val)
+    B = prob.assemble(L.OP_BRAS)
+    best, out = None, None
+    try:
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            T = spgemm(G, B, E, n)
+            Gt = csr_transpose(G, E, n)
+            S = spgemm(T, Gt, E, n)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+            out = {"m": E, "n": n, "nnz_G": E * nl, "nnz_B": int(B[1].numel()), "nnz_T": int(T[1].numel()),
+                   "nnz_St": int(S[1].numel())}
+            del T, Gt, S
+        out["ms"] = round(best * 1e3, 3)
+    except L.BrasError as e:     # e.g. a row beyond the candidate cap: reported, not fatal to the bench
+        out = {"error": str(e)}
+    del B, G
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, its_gpu, budget_s=20.0):
     """The oracle's BRAS-PCG on the same workload, matrix-free (its element
     route), one thread.  Setup (mesh, numbering, element matrices and
@@ -247,7 +285,7 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(workloads.BY_NAME))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=50)
-    ap.add_argument("--no-assembled", action="store_true", help="skip the assembled (CSR) BRAS comparison")
+    ap.add_argument("--no-assembled", action="store_true", help="skip the assembled (CSR) BRAS comparison and the Schur-complement products")
     ap.add_argument("--stationary-steps", type=int, default=2,
                     help="timed fixed-point / Chebyshev solves of each kind (0: skip)")
     ap.add_argument("--mode", choices=["full", "apply", "mass", "copy"], default="full",
@@ -321,9 +359,12 @@ def main():
     nbytes = algorithmic_bytes(w, prob.n, prob.E, prob.n_loc, w.nrhs, w.prec)
     achieved = nbytes / (bras_us * 1e-6) / 1e9
     assembled = None
+    schur = None
     if w.nrhs == 1 and w.prec != "bf16" and not a.no_assembled:
         assembled = assembled_section(prob, x, y, bras_us, a.apply_reps)
         print("assembled done: %s" % json.dumps(assembled), file=sys.stderr, flush=True)
+        schur = schur_section(prob, w)
+        print("schur done: %s" % json.dumps(schur), file=sys.stderr, flush=True)
     traffic = stored_traffic(w.name)
     out = {
         "metric": METRIC,
@@ -363,6 +404,7 @@ def main():
         "element_pass_variant": int(variant),
         "stationary": stat,
         "assembled_bras": assembled,
+        "schur_bras": schur,
     }
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)

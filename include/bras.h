@@ -271,8 +271,8 @@ int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t* col_d, con
  * C = A B for A (m x k) and B (k x n).  bras_spgemm_rowptr writes C's row
  * pointers c_rowptr_d [m+1] and nnz(C) (synchronises the stream);
  * bras_spgemm_fill writes C's columns (ascending) and values, each entry the
- * sum of its products in the order of A's columns (fma, one B row at a time):
- * the same result for every launch shape.  EINVAL when a row of A has a
+ * sum of its products a_ip b_pj taken in the order of A's columns: the same
+ * result for every launch shape.  EINVAL when a row of A has a
  * column outside [0, k), malformed row pointers, more than 2048 candidate
  * products in one row (the sum over the row of A of the selected B row
  * lengths), nnz(C) >= 2^31, or (fill) row pointers that do not match the

@@ -5,10 +5,12 @@
 //
 // C = A B (CSR, int64 row pointers, int32 columns ascending and distinct
 // within each row, float64 values): one wavefront per row of C.  The
-// candidate columns of row i (the columns of the B rows that row i of A
-// selects) are gathered into LDS, sorted (bitonic) and counted or written
-// distinct; each entry then sums its products in the order of A's columns,
-// one B row at a time, so the result does not depend on the launch shape.
+// candidates of row i (the entries of the B rows that row i of A selects)
+// are keyed (column, candidate index) in LDS and sorted (bitonic); the
+// distinct columns are counted, or each sums its products in candidate
+// order, i.e. in the order of A's columns, so the result does not depend on
+// the launch shape.  Every step is parallel over the wavefront: a wave scan
+// of the B row lengths, independent loads of all products.
 //
 // A^T: a stable radix sort of the entries by column (hipCUB), so each row of
 // A^T lists A's rows in ascending order; exact (no arithmetic).
@@ -23,6 +25,35 @@ namespace {
 
 constexpr int kGemmCap = 2048;   // candidate products of one row of C
 
+// Bitonic sort of key[0 .. m2) (m2 a power of two, at most kGemmCap) by one
+// wavefront: every stage first loads all of this lane's pairs, then
+// compares and stores, so a stage costs one LDS round trip, not one per pair.
+__device__ inline void wave_bitonic(uint64_t* key, int m2) {
+  constexpr int kPer = kGemmCap / 64;
+  const int t = threadIdx.x;
+  for (int kk = 2; kk <= m2; kk <<= 1)
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      uint64_t xa[kPer], xb[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int q = t + 64 * u, pq = q ^ jj;
+        if (q < m2 && pq > q) {
+          xa[u] = key[q];
+          xb[u] = key[pq];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int q = t + 64 * u, pq = q ^ jj;
+        if (q < m2 && pq > q && ((xa[u] > xb[u]) == ((q & kk) == 0))) {
+          key[q] = xb[u];
+          key[pq] = xa[u];
+        }
+      }
+      __syncthreads();
+    }
+}
+
 template <int FILL>
 __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64_t* __restrict__ a_rp,
                                                const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
@@ -30,48 +61,55 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
                                                const double* __restrict__ b_val, int32_t* __restrict__ cnt,
                                                const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
                                                double* __restrict__ c_val, int* __restrict__ flag) {
-  __shared__ int32_t cand[kGemmCap];
-  __shared__ int32_t ucol[kGemmCap];
-  __shared__ double acc[kGemmCap];
+  __shared__ uint64_t key[kGemmCap];      // (column << 32) | candidate index, sorted
   __shared__ int32_t pre[kGemmCap + 1];   // prefix sums of the selected B row lengths
-  __shared__ int ok_s, tot_s;
+  __shared__ int32_t bst[kGemmCap];       // start of each selected B row
+  __shared__ int16_t own[kGemmCap];       // the A entry (index in the row) of each candidate
+  __shared__ double prod[kGemmCap];       // products, in sorted order
   const int t = threadIdx.x;
   for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
     const int64_t p0 = a_rp[i];
     const int64_t na64 = a_rp[i + 1] - p0;
-    if (t == 0) {
-      // rows are validated before any candidate is read: row pointers of A
-      // and of the selected B rows inside [0, nnz] and non-decreasing, A's
-      // columns indexing rows of B, the candidates fitting in LDS
-      const int64_t annz = a_rp[m], bnnz = b_rp[k];
-      int ok = na64 >= 0 && na64 <= kGemmCap && p0 >= 0 && p0 + na64 <= annz;
-      int64_t tot = 0;
-      if (ok) {
-        pre[0] = 0;
-        for (int p = 0; p < (int)na64; ++p) {
+    // validation before any candidate is read (all lanes, uniform result):
+    // row pointers of A and of the selected B rows inside [0, nnz] and
+    // non-decreasing, A's columns indexing rows of B, at most kGemmCap
+    // candidates; lengths summed by a wave scan, 64 entries at a time
+    const int64_t annz = a_rp[m], bnnz = b_rp[k];
+    bool ok = na64 >= 0 && na64 <= kGemmCap && p0 >= 0 && p0 + na64 <= annz;
+    int tot = 0;
+    if (ok) {
+      const int na = (int)na64;
+      bool bad = false;
+      if (t == 0) pre[0] = 0;
+      for (int c0 = 0; c0 < na && tot <= kGemmCap; c0 += 64) {
+        const int p = c0 + t;
+        int len = 0;
+        if (p < na) {
           const int32_t a = a_col[p0 + p];
           if (a < 0 || a >= k) {
-            ok = 0;
-            break;
+            bad = true;
+          } else {
+            const int64_t b0 = b_rp[a], b1 = b_rp[a + 1];
+            if (b0 < 0 || b1 < b0 || b1 > bnnz) {
+              bad = true;
+            } else {
+              len = (int)(b1 - b0 < (int64_t)kGemmCap + 1 ? b1 - b0 : (int64_t)kGemmCap + 1);
+              bst[p] = (int32_t)b0;
+            }
           }
-          const int64_t b0 = b_rp[a], b1 = b_rp[a + 1];
-          if (b0 < 0 || b1 < b0 || b1 > bnnz) {
-            ok = 0;
-            break;
-          }
-          tot += b1 - b0;
-          if (tot > kGemmCap) {
-            ok = 0;
-            break;
-          }
-          pre[p + 1] = (int32_t)tot;
         }
+        int x = len;   // inclusive scan over the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int y = __shfl_up(x, off, 64);
+          if (t >= off) x += y;
+        }
+        if (p < na) pre[p + 1] = tot + x;
+        tot += __shfl(x, 63, 64);
       }
-      ok_s = ok;
-      tot_s = ok ? (int)tot : 0;
+      ok = __ballot(bad) == 0 && tot <= kGemmCap;
     }
-    __syncthreads();
-    if (!ok_s) {
+    if (!ok) {
       if (t == 0) {
         flag[0] = 1;
         if (!FILL) cnt[i] = 0;
@@ -79,71 +117,36 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
       __syncthreads();
       continue;
     }
-    const int na = (int)na64, mt = tot_s;
+    __syncthreads();
+    const int na = (int)na64, mt = tot;
     int m2 = 1;
     while (m2 < mt) m2 <<= 1;
+    // owner of each candidate: A entry p covers candidates pre[p] .. pre[p+1)
+    for (int p = t; p < na; p += 64)
+      for (int q = pre[p]; q < pre[p + 1]; ++q) own[q] = (int16_t)p;
+    __syncthreads();
     for (int q = t; q < m2; q += 64) {
-      int32_t cv = 0x7fffffff;
+      uint64_t kv = ~0ull;
       if (q < mt) {
-        // the A entry whose B row holds candidate q: the largest p with
-        // pre[p] <= q (empty B rows share their prefix with the next row)
-        int lo = 0, hi = na - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (pre[mid] <= q) lo = mid; else hi = mid - 1;
-        }
-        const int32_t a = a_col[p0 + lo];
-        cv = b_col[b_rp[a] + (q - pre[lo])];
+        const int pa = own[q];
+        const uint32_t cj = (uint32_t)b_col[(int64_t)bst[pa] + (q - pre[pa])];
+        kv = ((uint64_t)cj << 32) | (uint32_t)q;
       }
-      cand[q] = cv;
+      key[q] = kv;
     }
     __syncthreads();
-    for (int kk = 2; kk <= m2; kk <<= 1)
-      for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-        for (int q = t; q < m2; q += 64) {
-          const int pq = q ^ jj;
-          if (pq > q) {
-            const int32_t x = cand[q], y = cand[pq];
-            if ((x > y) == ((q & kk) == 0)) {
-              cand[q] = y;
-              cand[pq] = x;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    int u = 0;   // distinct columns, compacted in ascending order
+    wave_bitonic(key, m2);
+    // distinct columns: the heads of runs of equal column
+    int u = 0;
     for (int q0 = 0; q0 < mt; q0 += 64) {
       const int q = q0 + t;
-      const bool head = q < mt && (q == 0 || cand[q] != cand[q - 1]);
-      const uint64_t mask = __ballot(head);
-      if (head) ucol[u + __popcll(mask & ((1ull << t) - 1ull))] = cand[q];
-      u += __popcll(mask);
+      const bool head = q < mt && (q == 0 || (key[q] >> 32) != (key[q - 1] >> 32));
+      u += __popcll(__ballot(head));
     }
-    __syncthreads();
     if (!FILL) {
       if (t == 0) cnt[i] = u;
       __syncthreads();
       continue;
-    }
-    for (int q = t; q < u; q += 64) acc[q] = 0.0;
-    __syncthreads();
-    for (int p = 0; p < na; ++p) {
-      const int32_t a = a_col[p0 + p];
-      const double av = a_val[p0 + p];
-      const int64_t bs = b_rp[a];
-      const int lb = (int)(b_rp[a + 1] - bs);
-      // the columns of one B row are distinct: no two lanes share a position
-      for (int q = t; q < lb; q += 64) {
-        const int32_t cj = b_col[bs + q];
-        int lo = 0, hi = u - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (ucol[mid] < cj) lo = mid + 1; else hi = mid;
-        }
-        acc[lo] = fma(av, b_val[bs + q], acc[lo]);
-      }
-      __syncthreads();
     }
     // the output row must have exactly the counted length inside [0, nnz(C)]
     const int64_t o = c_rp[i];
@@ -152,9 +155,28 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
       __syncthreads();
       continue;
     }
-    for (int q = t; q < u; q += 64) {
-      c_col[o + q] = ucol[q];
-      c_val[o + q] = acc[q];
+    // products of every candidate (independent loads), in sorted order
+    for (int r = t; r < mt; r += 64) {
+      const int q = (int)(uint32_t)key[r];
+      const int pa = own[q];
+      prod[r] = a_val[p0 + pa] * b_val[(int64_t)bst[pa] + (q - pre[pa])];
+    }
+    __syncthreads();
+    // each head sums its run in candidate order (A's column order)
+    int base = 0;
+    for (int q0 = 0; q0 < mt; q0 += 64) {
+      const int q = q0 + t;
+      const bool head = q < mt && (q == 0 || (key[q] >> 32) != (key[q - 1] >> 32));
+      const uint64_t mask = __ballot(head);
+      if (head) {
+        const uint64_t cbits = key[q] >> 32;
+        double s = prod[q];
+        for (int r = q + 1; r < mt && (key[r] >> 32) == cbits; ++r) s += prod[r];
+        const int64_t at = o + base + __popcll(mask & ((1ull << t) - 1ull));
+        c_col[at] = (int32_t)(uint32_t)cbits;
+        c_val[at] = s;
+      }
+      base += __popcll(mask);
     }
     __syncthreads();
   }
