@@ -23,13 +23,15 @@
 namespace bras {
 namespace {
 
-constexpr int kGemmCap = 2048;   // candidate products of one row of C
+constexpr int kGemmCap = 2048;    // candidate products of one row of C
+constexpr int kGemmSmall = 1024;  // rows up to this many run with half the LDS (twice the work-groups per CU)
 
 // Bitonic sort of key[0 .. m2) (m2 a power of two, at most kGemmCap) by one
 // wavefront: every stage first loads all of this lane's pairs, then
 // compares and stores, so a stage costs one LDS round trip, not one per pair.
+template <int CAP>
 __device__ inline void wave_bitonic(uint64_t* key, int m2) {
-  constexpr int kPer = kGemmCap / 64;
+  constexpr int kPer = CAP / 64;
   const int t = threadIdx.x;
   for (int kk = 2; kk <= m2; kk <<= 1)
     for (int jj = kk >> 1; jj > 0; jj >>= 1) {
@@ -54,18 +56,22 @@ __device__ inline void wave_bitonic(uint64_t* key, int m2) {
     }
 }
 
-template <int FILL>
+// Two variants: CAP = kGemmSmall (half the LDS) takes the rows with at most
+// kGemmSmall A entries and candidates, and raises flag[1] for the others;
+// CAP = kGemmCap takes exactly those others.  Malformed rows, or rows beyond
+// kGemmCap, raise flag[0].
+template <int CAP, int FILL>
 __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64_t* __restrict__ a_rp,
                                                const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
                                                const int64_t* __restrict__ b_rp, const int32_t* __restrict__ b_col,
                                                const double* __restrict__ b_val, int32_t* __restrict__ cnt,
                                                const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
                                                double* __restrict__ c_val, int* __restrict__ flag) {
-  __shared__ uint64_t key[kGemmCap];      // (column << 32) | candidate index, sorted
-  __shared__ int32_t pre[kGemmCap + 1];   // prefix sums of the selected B row lengths
-  __shared__ int32_t bst[kGemmCap];       // start of each selected B row
-  __shared__ int16_t own[kGemmCap];       // the A entry (index in the row) of each candidate
-  __shared__ double prod[kGemmCap];       // products, in sorted order
+  __shared__ uint64_t key[CAP];      // (column << 32) | candidate index, sorted
+  __shared__ int32_t pre[CAP + 1];   // prefix sums of the selected B row lengths
+  __shared__ int32_t bst[CAP];       // start of each selected B row
+  __shared__ int16_t own[CAP];       // the A entry (index in the row) of each candidate
+  __shared__ double prod[CAP];       // products, in sorted order
   const int t = threadIdx.x;
   for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
     const int64_t p0 = a_rp[i];
@@ -77,10 +83,11 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
     const int64_t annz = a_rp[m], bnnz = b_rp[k];
     bool ok = na64 >= 0 && na64 <= kGemmCap && p0 >= 0 && p0 + na64 <= annz;
     int tot = 0;
+    bool big = ok && na64 > CAP;   // past this variant's tables: stop writing them
     if (ok) {
       const int na = (int)na64;
       bool bad = false;
-      if (t == 0) pre[0] = 0;
+      if (t == 0 && !big) pre[0] = 0;
       for (int c0 = 0; c0 < na && tot <= kGemmCap; c0 += 64) {
         const int p = c0 + t;
         int len = 0;
@@ -94,7 +101,7 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
               bad = true;
             } else {
               len = (int)(b1 - b0 < (int64_t)kGemmCap + 1 ? b1 - b0 : (int64_t)kGemmCap + 1);
-              bst[p] = (int32_t)b0;
+              if (!big) bst[p] = (int32_t)b0;
             }
           }
         }
@@ -104,8 +111,9 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
           const int y = __shfl_up(x, off, 64);
           if (t >= off) x += y;
         }
-        if (p < na) pre[p + 1] = tot + x;
+        if (p < na && !big && tot + x <= CAP) pre[p + 1] = tot + x;
         tot += __shfl(x, 63, 64);
+        if (tot > CAP) big = true;
       }
       ok = __ballot(bad) == 0 && tot <= kGemmCap;
     }
@@ -114,6 +122,13 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
         flag[0] = 1;
         if (!FILL) cnt[i] = 0;
       }
+      __syncthreads();
+      continue;
+    }
+    const bool needs_large = na64 > kGemmSmall || tot > kGemmSmall;
+    if (needs_large != (CAP == kGemmCap)) {
+      // the other variant's row
+      if (t == 0 && needs_large) flag[1] = 1;
       __syncthreads();
       continue;
     }
@@ -135,7 +150,7 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
       key[q] = kv;
     }
     __syncthreads();
-    wave_bitonic(key, m2);
+    wave_bitonic<CAP>(key, m2);
     // distinct columns: the heads of runs of equal column
     int u = 0;
     for (int q0 = 0; q0 < mt; q0 += 64) {
@@ -227,6 +242,32 @@ __global__ void __launch_bounds__(256) k_col_starts(int64_t n, const int32_t* __
   }
 }
 
+unsigned grid_of(int64_t work, int per_cu);
+
+// Both variants of a pass (the large one only when the small one left rows);
+// *bad: a malformed or over-long row was found.
+template <int FILL>
+int spgemm_pass(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
+                const int64_t* b_rp, const int32_t* b_col, const double* b_val, int32_t* cnt, const int64_t* c_rp,
+                int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int* bad) {
+  int hf[2] = {0, 0};
+  BRAS_HIP(hipMemsetAsync(flag_d, 0, 2 * sizeof(int), s));
+  k_spgemm<kGemmSmall, FILL><<<grid_of(m, 32), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp,
+                                                            c_col, c_val, flag_d);
+  BRAS_HIP(hipGetLastError());
+  BRAS_HIP(hipMemcpyAsync(hf, flag_d, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  if (!hf[0] && hf[1]) {
+    k_spgemm<kGemmCap, FILL><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp,
+                                                            c_col, c_val, flag_d);
+    BRAS_HIP(hipGetLastError());
+    BRAS_HIP(hipMemcpyAsync(hf, flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
+    BRAS_HIP(hipStreamSynchronize(s));
+  }
+  *bad = hf[0];
+  return BRAS_OK;
+}
+
 unsigned grid_of(int64_t work, int per_cu) {
   int dev = 0, ncu = 1;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
@@ -271,16 +312,13 @@ extern "C" int bras_spgemm_rowptr(int64_t m, int64_t k, const int64_t* a_rowptr_
     DevBufs tmp;
     int32_t* cnt = nullptr;
     int* flag = nullptr;
-    int st;
-    if ((st = tmp.get(&cnt, (size_t)m)) || (st = tmp.get(&flag, 1))) return st;
-    BRAS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-    k_spgemm<0><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rowptr_d, a_col_d, nullptr, b_rowptr_d, b_col_d, nullptr, cnt,
-                                              nullptr, nullptr, nullptr, flag);
-    BRAS_HIP(hipGetLastError());
+    int st, hf = 0;
+    if ((st = tmp.get(&cnt, (size_t)m)) || (st = tmp.get(&flag, 2))) return st;
+    if ((st = spgemm_pass<0>(m, k, a_rowptr_d, a_col_d, nullptr, b_rowptr_d, b_col_d, nullptr, cnt, nullptr, nullptr,
+                             nullptr, flag, s, &hf)))
+      return st;
     std::vector<int32_t> hc(m);
-    int hf = 0;
     BRAS_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
-    BRAS_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     BRAS_HIP(hipStreamSynchronize(s));
     BRAS_CHECK(!hf, "a row of A has a column outside [0, %lld) or selects more than %d products", (long long)k,
                kGemmCap);
@@ -306,15 +344,11 @@ extern "C" int bras_spgemm_fill(int64_t m, int64_t k, const int64_t* a_rowptr_d,
   hipStream_t s = (hipStream_t)stream;
   DevBufs tmp;
   int* flag = nullptr;
-  int st;
-  if ((st = tmp.get(&flag, 1))) return st;
-  BRAS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-  k_spgemm<1><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rowptr_d, a_col_d, a_val_d, b_rowptr_d, b_col_d, b_val_d, nullptr,
-                                            c_rowptr_d, c_col_d, c_val_d, flag);
-  BRAS_HIP(hipGetLastError());
-  int hf = 0;
-  BRAS_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  BRAS_HIP(hipStreamSynchronize(s));
+  int st, hf = 0;
+  if ((st = tmp.get(&flag, 2))) return st;
+  if ((st = spgemm_pass<1>(m, k, a_rowptr_d, a_col_d, a_val_d, b_rowptr_d, b_col_d, b_val_d, nullptr, c_rowptr_d,
+                           c_col_d, c_val_d, flag, s, &hf)))
+    return st;
   BRAS_CHECK(!hf, "a row of A has a column outside [0, %lld) or selects more than %d products", (long long)k, kGemmCap);
   return BRAS_OK;
 }
