@@ -289,6 +289,17 @@ int bras_spgemm_fill(int64_t m, int64_t k, const int64_t* a_rowptr_d, const int3
  * allocates temporary device memory. */
 int bras_csr_transpose(int64_t m, int64_t n, const int64_t* rowptr_d, const int32_t* col_d, const double* val_d,
                        int64_t* rowptr_t_d, int32_t* col_t_d, double* val_t_d, void* stream);
+/* C = A + B for A, B (m x n), e.g. the C term of eq.
+ * approx_positive_schur_general: rows merged by column; an entry present in
+ * both is a + b.  bras_csr_add_rowptr writes C's row pointers and nnz(C);
+ * bras_csr_add_fill its columns and values.  EINVAL for malformed row
+ * pointers, nnz(C) >= 2^31, or (fill) row pointers that do not match the
+ * counts.  Synchronous. */
+int bras_csr_add_rowptr(int64_t m, const int64_t* a_rowptr_d, const int32_t* a_col_d, const int64_t* b_rowptr_d,
+                        const int32_t* b_col_d, int64_t* c_rowptr_d, int64_t* nnz_h, void* stream);
+int bras_csr_add_fill(int64_t m, const int64_t* a_rowptr_d, const int32_t* a_col_d, const double* a_val_d,
+                      const int64_t* b_rowptr_d, const int32_t* b_col_d, const double* b_val_d,
+                      const int64_t* c_rowptr_d, int32_t* c_col_d, double* c_val_d, void* stream);
 
 #define BRAS_OPT_GRAPH_ITERS 0  /* CG iterations per captured graph (>= 1)     */
 #define BRAS_OPT_MAX_RESTART 1  /* refinement restarts allowed (>= 0)         */

@@ -78,6 +78,8 @@ _SIGS = {
     "bras_spgemm_rowptr": [i64, i64, vp, vp, vp, vp, vp, P_i64, vp],
     "bras_spgemm_fill": [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
     "bras_csr_transpose": [i64, i64, vp, vp, vp, vp, vp, vp, vp],
+    "bras_csr_add_rowptr": [i64, vp, vp, vp, vp, vp, P_i64, vp],
+    "bras_csr_add_fill": [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
 }
 
 
@@ -310,6 +312,19 @@ def bras_spgemm_fill(m, k, a, b, c, stream=None):
 def bras_csr_transpose(m, n, a, t, stream=None):
     check(lib().bras_csr_transpose(m, n, _dev(a[0]), _dev(a[1]), _dev(a[2]), _dev(t[0]), _dev(t[1]), _dev(t[2]),
                                    _stream(stream)))
+
+
+def bras_csr_add_rowptr(m, a, b, c_rowptr_d, stream=None):
+    """Row pointers of C = A + B; returns nnz(C)."""
+    nnz = C.c_int64()
+    check(lib().bras_csr_add_rowptr(m, _dev(a[0]), _dev(a[1]), _dev(b[0]), _dev(b[1]), _dev(c_rowptr_d),
+                                    C.byref(nnz), _stream(stream)))
+    return nnz.value
+
+
+def bras_csr_add_fill(m, a, b, c, stream=None):
+    check(lib().bras_csr_add_fill(m, _dev(a[0]), _dev(a[1]), _dev(a[2]), _dev(b[0]), _dev(b[1]), _dev(b[2]),
+                                  _dev(c[0]), _dev(c[1]), _dev(c[2]), _stream(stream)))
 
 
 def bras_set_option(h, opt, value):

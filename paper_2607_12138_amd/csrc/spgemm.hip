@@ -244,6 +244,66 @@ __global__ void __launch_bounds__(256) k_col_starts(int64_t n, const int32_t* __
 
 unsigned grid_of(int64_t work, int per_cu);
 
+// C = A + B (both m x n): one thread per row merges the two ascending column
+// lists; an entry present in both is a + b.  Rows with malformed pointers
+// (or, when filling, an output row whose length differs from the merge)
+// raise the flag and write nothing.
+template <int FILL>
+__global__ void __launch_bounds__(256) k_csr_add(int64_t m, const int64_t* __restrict__ a_rp,
+                                                 const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
+                                                 const int64_t* __restrict__ b_rp, const int32_t* __restrict__ b_col,
+                                                 const double* __restrict__ b_val, int32_t* __restrict__ cnt,
+                                                 const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
+                                                 double* __restrict__ c_val, int* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t annz = a_rp[m], bnnz = b_rp[m];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const int64_t a0 = a_rp[i], a1 = a_rp[i + 1], b0 = b_rp[i], b1 = b_rp[i + 1];
+    if (a0 < 0 || a1 < a0 || a1 > annz || b0 < 0 || b1 < b0 || b1 > bnnz) {
+      flag[0] = 1;
+      if (!FILL) cnt[i] = 0;
+      continue;
+    }
+    int64_t o = 0, lim = 0;
+    if (FILL) {
+      o = c_rp[i];
+      lim = c_rp[i + 1];
+      if (o < 0 || lim < o || lim > c_rp[m]) {
+        flag[0] = 1;
+        continue;
+      }
+    }
+    int64_t pa = a0, pb = b0, u = 0;
+    while (pa < a1 || pb < b1) {
+      const int32_t ca = pa < a1 ? a_col[pa] : 0x7fffffff, cb = pb < b1 ? b_col[pb] : 0x7fffffff;
+      int32_t cc;
+      double v = 0.0;
+      if (ca < cb || pb >= b1) {
+        cc = ca;
+        if (FILL) v = a_val[pa];
+        ++pa;
+      } else if (cb < ca || pa >= a1) {
+        cc = cb;
+        if (FILL) v = b_val[pb];
+        ++pb;
+      } else {
+        cc = ca;
+        if (FILL) v = a_val[pa] + b_val[pb];
+        ++pa;
+        ++pb;
+      }
+      if (FILL) {
+        if (o + u >= lim) break;   // the output row is too short: flagged below
+        c_col[o + u] = cc;
+        c_val[o + u] = v;
+      }
+      ++u;
+    }
+    if (!FILL) cnt[i] = (int32_t)u;
+    else if (o + u != lim || pa < a1 || pb < b1) flag[0] = 1;
+  }
+}
+
 // Both variants of a pass (the large one only when the small one left rows);
 // *bad: a malformed or over-long row was found.
 template <int FILL>
@@ -404,5 +464,60 @@ extern "C" int bras_csr_transpose(int64_t m, int64_t n, const int64_t* rowptr_d,
   BRAS_HIP(hipStreamSynchronize(s));
   BRAS_CHECK(!hf, "row pointers must be non-decreasing from 0 to nnz");
   BRAS_CHECK(tb[0] == 0 && tb[1] == nnz, "a column index lies outside [0, %lld)", (long long)n);
+  return BRAS_OK;
+}
+
+extern "C" int bras_csr_add_rowptr(int64_t m, const int64_t* a_rowptr_d, const int32_t* a_col_d,
+                                   const int64_t* b_rowptr_d, const int32_t* b_col_d, int64_t* c_rowptr_d,
+                                   int64_t* nnz_h, void* stream) {
+  clear_error();
+  BRAS_CHECK(m >= 0 && m < (1LL << 31), "size outside [0, 2^31)");
+  BRAS_CHECK(a_rowptr_d && a_col_d && b_rowptr_d && b_col_d && c_rowptr_d && nnz_h, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int64_t> rp(m + 1, 0);
+  if (m > 0) {
+    DevBufs tmp;
+    int32_t* cnt = nullptr;
+    int* flag = nullptr;
+    int st, hf = 0;
+    if ((st = tmp.get(&cnt, (size_t)m)) || (st = tmp.get(&flag, 1))) return st;
+    BRAS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_csr_add<0><<<grid_of((m + 255) / 256, 8), 256, 0, s>>>(m, a_rowptr_d, a_col_d, nullptr, b_rowptr_d, b_col_d,
+                                                            nullptr, cnt, nullptr, nullptr, nullptr, flag);
+    BRAS_HIP(hipGetLastError());
+    std::vector<int32_t> hc(m);
+    BRAS_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+    BRAS_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    BRAS_HIP(hipStreamSynchronize(s));
+    BRAS_CHECK(!hf, "malformed row pointers");
+    for (int64_t i = 0; i < m; ++i) rp[i + 1] = rp[i] + hc[i];
+  }
+  BRAS_CHECK(rp[m] < (1LL << 31), "the sum has %lld entries; at most 2^31 - 1 are supported", (long long)rp[m]);
+  BRAS_HIP(hipMemcpyAsync(c_rowptr_d, rp.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  *nnz_h = rp[m];
+  return BRAS_OK;
+}
+
+extern "C" int bras_csr_add_fill(int64_t m, const int64_t* a_rowptr_d, const int32_t* a_col_d, const double* a_val_d,
+                                 const int64_t* b_rowptr_d, const int32_t* b_col_d, const double* b_val_d,
+                                 const int64_t* c_rowptr_d, int32_t* c_col_d, double* c_val_d, void* stream) {
+  clear_error();
+  BRAS_CHECK(m >= 0 && m < (1LL << 31), "size outside [0, 2^31)");
+  if (m == 0) return BRAS_OK;
+  BRAS_CHECK(a_rowptr_d && a_col_d && a_val_d && b_rowptr_d && b_col_d && b_val_d && c_rowptr_d && c_col_d && c_val_d,
+             "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  DevBufs tmp;
+  int* flag = nullptr;
+  int st, hf = 0;
+  if ((st = tmp.get(&flag, 1))) return st;
+  BRAS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  k_csr_add<1><<<grid_of((m + 255) / 256, 8), 256, 0, s>>>(m, a_rowptr_d, a_col_d, a_val_d, b_rowptr_d, b_col_d,
+                                                          b_val_d, nullptr, c_rowptr_d, c_col_d, c_val_d, flag);
+  BRAS_HIP(hipGetLastError());
+  BRAS_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  BRAS_CHECK(!hf, "malformed row pointers, or output rows that do not match the counts");
   return BRAS_OK;
 }

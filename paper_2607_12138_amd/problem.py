@@ -153,17 +153,19 @@ class MassProblem:
         L.bras_export(self.h, what, out)
         return out
 
-    def schur(self, G, op=None):
-        """-St = G Mt^-1 G^T (Section 5, eq. approx_positive_schur_general with
-        C = 0) for a CSR coupling G = (rowptr, col, val) of shape m x n on the
-        device, Mt^-1 the assembled operator op (default L.OP_BRAS): the two
-        sparse products (G Mt^-1) G^T.  Returns the CSR of St (m x m)."""
+    def schur(self, G, op=None, C=None):
+        """-St = C + G Mt^-1 G^T (Section 5, eq. approx_positive_schur_general)
+        for a CSR coupling G = (rowptr, col, val) of shape m x n on the device,
+        Mt^-1 the assembled operator op (default L.OP_BRAS) and an optional
+        CSR C (m x m): the sparse products (G Mt^-1) G^T, then the sum with C.
+        Returns the CSR of -St (m x m)."""
         op = L.OP_BRAS if op is None else op
         m = G[0].numel() - 1
         Bop = self.assemble(op)
         T = spgemm(G, Bop, m, self.n)
         Gt = csr_transpose(G, m, self.n)
-        return spgemm(T, Gt, m, self.n)
+        S = spgemm(T, Gt, m, self.n)
+        return S if C is None else csr_add(S, C, m)
 
 
 def spgemm(a, b, m, k):
@@ -194,3 +196,19 @@ def csr_transpose(a, m, n):
         return torch.zeros(n + 1, dtype=torch.int64, device=dev), col[:0], val[:0]
     L.bras_csr_transpose(m, n, a, (rp, col, val))
     return rp, col, val
+
+
+def csr_add(a, b, m):
+    """A + B for CSR device triples of the same shape (m rows)."""
+    import torch
+    dev = a[0].device
+    if a[1].numel() == 0:
+        return b
+    if b[1].numel() == 0:
+        return a
+    rp = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    nnz = L.bras_csr_add_rowptr(m, a, b, rp)
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+    L.bras_csr_add_fill(m, a, b, (rp, col, val))
+    return rp, col[:nnz], val[:nnz]
