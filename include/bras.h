@@ -264,10 +264,12 @@ int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t* col_d, con
 
 /* ---- sparse products for Schur-complement approximations (Section 5:
  * -St = C + G Mt^-1 G^T, eq. approx_positive_schur_general, sparse when Mt^-1
- * is the assembled M_bras^-1; formed as (G M_bras^-1) G^T with these calls) --
+ * is the assembled M_bras^-1; formed as (G M_bras^-1) G^T, then + C, with
+ * these calls) -------------------------------------------------------------
  * CSR on the device as above: int64 row pointers (non-decreasing, from 0 to
  * nnz), int32 columns ascending and distinct within each row, float64
- * values.  Buffers are caller allocated; sizes below 2^31.
+ * values.  Output buffers are caller allocated; each call allocates small
+ * temporary device buffers of its own; sizes below 2^31.
  * C = A B for A (m x k) and B (k x n).  bras_spgemm_rowptr writes C's row
  * pointers c_rowptr_d [m+1] and nnz(C) (synchronises the stream);
  * bras_spgemm_fill writes C's columns (ascending) and values, each entry the
@@ -285,8 +287,7 @@ int bras_spgemm_fill(int64_t m, int64_t k, const int64_t* a_rowptr_d, const int3
                      const int64_t* c_rowptr_d, int32_t* c_col_d, double* c_val_d, void* stream);
 /* A^T (n x m) of A (m x n): row j of A^T lists the rows of A holding column
  * j, ascending, with their values (a stable sort by column; exact).  EINVAL
- * for malformed row pointers or a column outside [0, n).  Synchronous;
- * allocates temporary device memory. */
+ * for malformed row pointers or a column outside [0, n).  Synchronous. */
 int bras_csr_transpose(int64_t m, int64_t n, const int64_t* rowptr_d, const int32_t* col_d, const double* val_d,
                        int64_t* rowptr_t_d, int32_t* col_t_d, double* val_t_d, void* stream);
 /* C = A + B for A, B (m x n), e.g. the C term of eq.
