@@ -249,6 +249,7 @@ int bras_export(bras_handle h, int what, void* dst_d, void* stream);
  * inverses) with pi(K, m) = j.  Buffers are caller allocated. */
 #define BRAS_OP_MASS 0
 #define BRAS_OP_BRAS 1
+#define BRAS_OP_JACOBI 2   /* diag(M)^-1: see bras_csr_jacobi (its own pattern) */
 /* Row pointers and nnz of the pattern (the same for both operators).  EINVAL
  * when a row has more than 2048 candidate columns (max d_i * n_loc) or nnz
  * reaches 2^31.  Synchronises the stream. */
@@ -261,6 +262,10 @@ int bras_csr_assemble(bras_handle h, int op, const int64_t* rowptr_d, int32_t* c
  * x and y must not overlap. */
 int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t* col_d, const double* val_d,
                    const double* x_d, double* y_d, void* stream);
+/* diag(M)^-1 (Section 2.1, the diagonal mass-inverse approximation BRAS is
+ * compared with) as CSR: rowptr_d [n+1] = 0..n, col_d [n] = 0..n-1, val_d [n]
+ * = 1 / M_ii.  Asynchronous on the stream. */
+int bras_csr_jacobi(bras_handle h, int64_t* rowptr_d, int32_t* col_d, double* val_d, void* stream);
 
 /* ---- sparse products for Schur-complement approximations (Section 5:
  * -St = C + G Mt^-1 G^T, eq. approx_positive_schur_general, sparse when Mt^-1

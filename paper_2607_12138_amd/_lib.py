@@ -79,6 +79,7 @@ _SIGS = {
     "bras_spgemm_fill": [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
     "bras_csr_transpose": [i64, i64, vp, vp, vp, vp, vp, vp, vp],
     "bras_csr_add_rowptr": [i64, vp, vp, vp, vp, vp, P_i64, vp],
+    "bras_csr_jacobi": [vp, vp, vp, vp, vp],
     "bras_csr_add_fill": [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
 }
 
@@ -279,7 +280,7 @@ def bras_export(h, what, dst_d, stream=None):
     check(lib().bras_export(h, what, _dev(dst_d), _stream(stream)))
 
 
-OP_MASS, OP_BRAS = 0, 1
+OP_MASS, OP_BRAS, OP_JACOBI = 0, 1, 2
 
 
 def bras_csr_rowptr(h, rowptr_d, stream=None):
@@ -312,6 +313,10 @@ def bras_spgemm_fill(m, k, a, b, c, stream=None):
 def bras_csr_transpose(m, n, a, t, stream=None):
     check(lib().bras_csr_transpose(m, n, _dev(a[0]), _dev(a[1]), _dev(a[2]), _dev(t[0]), _dev(t[1]), _dev(t[2]),
                                    _stream(stream)))
+
+
+def bras_csr_jacobi(h, rowptr_d, col_d, val_d, stream=None):
+    check(lib().bras_csr_jacobi(h, _dev(rowptr_d), _dev(col_d), _dev(val_d), _stream(stream)))
 
 
 def bras_csr_add_rowptr(m, a, b, c_rowptr_d, stream=None):

@@ -170,6 +170,19 @@ int max_candidates(const Ctx* c, hipStream_t s, int64_t* out) {
   return BRAS_OK;
 }
 
+__global__ void __launch_bounds__(256) k_csr_diag(int64_t n, const double* __restrict__ invdiag,
+                                                  int64_t* __restrict__ rowptr, int32_t* __restrict__ col,
+                                                  double* __restrict__ val) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+    rowptr[i] = i;
+    if (i < n) {
+      col[i] = (int32_t)i;
+      val[i] = invdiag[i];
+    }
+  }
+}
+
 unsigned row_grid(const Ctx* c) {
   const int64_t want = (int64_t)c->ncu * 32;
   return (unsigned)(c->n < want ? c->n : want);
@@ -232,6 +245,18 @@ extern "C" int bras_csr_assemble(bras_handle h, int op, const int64_t* rowptr_d,
   else
     k_csr_rows<BRAS_OP_BRAS><<<row_grid(c), 64, 0, s>>>(1, v, c->n, c->rowptr, c->slot, c->l2g, nullptr, rowptr_d,
                                                          col_d, val_d);
+  BRAS_HIP(hipGetLastError());
+  return BRAS_OK;
+}
+
+extern "C" int bras_csr_jacobi(bras_handle h, int64_t* rowptr_d, int32_t* col_d, double* val_d, void* stream) {
+  clear_error();
+  BRAS_CHECK(h && rowptr_d && col_d && val_d, "null argument");
+  Ctx* c = (Ctx*)h;
+  const int64_t blocks = (c->n + 256) / 256;
+  const int64_t want = (int64_t)c->ncu * 8;
+  k_csr_diag<<<(unsigned)(blocks < want ? blocks : want), 256, 0, (hipStream_t)stream>>>(c->n, c->invdiag, rowptr_d,
+                                                                                        col_d, val_d);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }

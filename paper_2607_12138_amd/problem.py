@@ -125,10 +125,15 @@ class MassProblem:
         return L.bras_info(self.h, "variant")
 
     def assemble(self, op):
-        """The assembled operator (L.OP_MASS or L.OP_BRAS) as CSR device tensors
-        (rowptr int64, col int32, val float64)."""
+        """The assembled operator (L.OP_MASS, L.OP_BRAS or L.OP_JACOBI) as CSR
+        device tensors (rowptr int64, col int32, val float64)."""
         import torch
         rowptr = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        if op == L.OP_JACOBI:
+            col = torch.empty(self.n, dtype=torch.int32, device=self.device)
+            val = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            L.bras_csr_jacobi(self.h, rowptr, col, val)
+            return rowptr, col, val
         nnz = L.bras_csr_rowptr(self.h, rowptr)
         col = torch.empty(nnz, dtype=torch.int32, device=self.device)
         val = torch.empty(nnz, dtype=torch.float64, device=self.device)

@@ -92,7 +92,7 @@ def test_binding_constants_match_header():
                                                "ELEM_EXPLICIT", "ELEM_SCALED_REF", "ELEM_METRIC_REF",
                                                "FP64", "FP32", "BF16", "PC_NONE", "PC_JACOBI", "PC_BRAS",
                                                "EXPORT_MULT", "EXPORT_ROWPTR", "EXPORT_SLOT", "EXPORT_DIAG",
-                                               "OP_MASS", "OP_BRAS", "OPT_GRAPH_ITERS", "OPT_MAX_RESTART",
+                                               "OP_MASS", "OP_BRAS", "OP_JACOBI", "OPT_GRAPH_ITERS", "OPT_MAX_RESTART",
                                                "OPT_VARIANT", "OPT_SMALL_CG")}
     py.update({k: getattr(L, k) for k in ("BRAS_OK", "BRAS_EINVAL", "BRAS_ENOTSPD", "BRAS_EHIP", "BRAS_ENOCONV",
                                           "BRAS_EBREAKDOWN", "BRAS_ENOMEM")})

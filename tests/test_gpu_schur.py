@@ -190,3 +190,34 @@ def test_schur_with_c_term_matches_oracle():
     ac, bc = oschur.generalized_extremes(St, oschur.exact_schur(G, orc.M, Cm))
     assert bc / ac <= max(1.0, b0) / min(1.0, a0) * (1 + 1e-9)
     gpu.close()
+
+
+@pytest.mark.parametrize("case", SCHUR[:3], ids=lambda c: "%s%d-%dd-N%d" % (c[0], c[2], c[1], c[3]))
+def test_diagonal_schur_and_bras_comparison(case):
+    """-St with diag(M)^-1 (the approximation BRAS is compared with in
+    Section 5) against the oracle, and the BRAS St closer to S: its
+    beta_0 / alpha_0 below the diagonal one, both from the GPU's products."""
+    from paper_2607_12138_amd import _lib as L
+    from paper_2607_12138_amd.problem import MassProblem
+    family, dim, deg, N, jit = case
+    coords, cells = omesh.structured_mesh(dim, N, jitter=jit, seed=4)
+    orc = oasm.Problem(ofe.reference_element(family, dim, deg), coords, cells)
+    gpu = MassProblem(family, dim, deg, N, jitter=jit, seed=4)
+    D = gpu.assemble(L.OP_JACOBI)
+    assert np.array_equal(D[0].cpu().numpy(), np.arange(orc.n + 1)) and np.array_equal(D[1].cpu().numpy(), np.arange(orc.n))
+    assert np.max(np.abs(D[2].cpu().numpy() * orc.diag - 1.0)) <= 1e-14
+    m = min(len(orc.pi), orc.n // 2)
+    rows = np.repeat(np.arange(m), orc.pi.shape[1])
+    G = sp.csr_matrix((workloads.vector(rows.size, 19), (rows, orc.pi[:m].ravel())), shape=(m, orc.n))
+    Sd = to_host(gpu.schur(to_dev(G), L.OP_JACOBI), (m, m))
+    Sdr = oschur.schur_approx(G, sp.diags(1.0 / orc.diag))
+    scale = abs(G) @ sp.diags(1.0 / orc.diag) @ abs(G).T
+    assert same_pattern(Sd, scale)
+    assert abs(Sd - Sdr).max() <= 1e-13 * scale.max()
+    Sb = to_host(gpu.schur(to_dev(G), L.OP_BRAS), (m, m))
+    S = oschur.exact_schur(G, orc.M)
+    ab, bb = oschur.generalized_extremes(Sb, S)
+    ad, bd = oschur.generalized_extremes(Sd, S)
+    say("  kappa(S, St): BRAS %.3f, diagonal %.3f" % (bb / ab, bd / ad))
+    assert bb / ab < bd / ad
+    gpu.close()
