@@ -282,7 +282,7 @@ int bras_csr_jacobi(bras_handle h, int64_t* rowptr_d, int32_t* col_d, double* va
  * result for every launch shape.  EINVAL when a row of A has a
  * column outside [0, k), malformed row pointers, more than 2048 candidate
  * products in one row (the sum over the row of A of the selected B row
- * lengths), nnz(C) >= 2^31, or (fill) row pointers that do not match the
+ * lengths) or more than 2048 entries in one row of A, nnz(C) >= 2^31, or (fill) row pointers that do not match the
  * counts.  Synchronous. */
 int bras_spgemm_rowptr(int64_t m, int64_t k, const int64_t* a_rowptr_d, const int32_t* a_col_d,
                        const int64_t* b_rowptr_d, const int32_t* b_col_d, int64_t* c_rowptr_d, int64_t* nnz_h,

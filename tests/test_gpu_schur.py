@@ -221,3 +221,48 @@ def test_diagonal_schur_and_bras_comparison(case):
     say("  kappa(S, St): BRAS %.3f, diagonal %.3f" % (bb / ab, bd / ad))
     assert bb / ab < bd / ad
     gpu.close()
+
+
+def test_spgemm_candidate_cap_boundaries():
+    """Rows at the two LDS variants' limits: 1024 candidates (the half-LDS
+    variant), 1056 and 2048 (the full one), more than 1024 A entries with
+    few candidates (empty B rows), all against SciPy in one product; 2049
+    candidates, or 2049 entries in a row of A, are rejected."""
+    from paper_2607_12138_amd import _lib as L
+    from paper_2607_12138_amd.problem import spgemm
+    import torch
+    k, n = 3000, 4000
+    rng = np.random.default_rng(17)
+    # B: rows 0..1999 of length 32, rows 2000..2999 empty
+    brows = np.repeat(np.arange(2000), 32)
+    bcols = np.concatenate([rng.choice(n, 32, replace=False) for _ in range(2000)])
+    B = sp.csr_matrix((rng.uniform(-1, 1, brows.size), (brows, bcols)), shape=(k, n))
+    B.sort_indices()
+    # A rows selecting 32, 33 and 64 non-empty B rows (1024, 1056, 2048
+    # candidates), one selecting 1499 empty rows and 10 non-empty ones
+    sel = [np.arange(0, 32), np.arange(100, 133), np.arange(500, 564), np.concatenate([np.arange(2000, 2750),
+                                                                                      np.arange(10, 20),
+                                                                                      np.arange(2250, 2999)])]
+    arows = np.concatenate([np.full(len(s), i) for i, s in enumerate(sel)])
+    acols = np.concatenate(sel)
+    A = sp.csr_matrix((rng.uniform(-1, 1, arows.size), (arows, acols)), shape=(len(sel), k))
+    A.sort_indices()
+    assert [int((B[A[i].indices].getnnz())) for i in range(len(sel))] == [1024, 1056, 2048, 320]
+    say("spgemm at the candidate caps")
+    Cg = to_host(spgemm(to_dev(A), to_dev(B), len(sel), k), (len(sel), n))
+    Cr = (A @ B).tocsr()
+    assert same_pattern(Cg, (abs(A) @ abs(B)))
+    assert np.abs((Cg - Cr).toarray()).max() <= 1e-13 * (abs(A) @ abs(B)).toarray().max()
+    # 2049 candidates: one more non-empty B row of length 1
+    B2 = sp.vstack([B, sp.csr_matrix(([1.0], ([0], [0])), shape=(1, n))]).tocsr()
+    A2 = sp.csr_matrix((np.ones(65), (np.zeros(65, dtype=int), np.r_[np.arange(64), 3000])), shape=(1, k + 1))
+    with pytest.raises(L.BrasError) as e:
+        L.bras_spgemm_rowptr(1, k + 1, to_dev(A2), to_dev(B2), torch.empty(2, dtype=torch.int64, device="cuda"))
+    assert e.value.code == L.BRAS_EINVAL
+    # 2049 entries in one row of A, all of them empty rows of B
+    A3 = sp.csr_matrix((np.ones(2049), (np.zeros(2049, dtype=int), np.arange(2049))), shape=(1, 3 * 2049))
+    B3 = sp.csr_matrix(([1.0], ([3 * 2049 - 1], [0])), shape=(3 * 2049, n))   # one entry, in a row not selected
+    with pytest.raises(L.BrasError) as e:
+        L.bras_spgemm_rowptr(1, 3 * 2049, to_dev(A3), to_dev(B3), torch.empty(2, dtype=torch.int64, device="cuda"))
+    assert e.value.code == L.BRAS_EINVAL
+    torch.cuda.synchronize()
