@@ -273,17 +273,22 @@ int bras_csr_jacobi(bras_handle h, int64_t* rowptr_d, int32_t* col_d, double* va
  * these calls) -------------------------------------------------------------
  * CSR on the device as above: int64 row pointers (non-decreasing, from 0 to
  * nnz), int32 columns ascending and distinct within each row, float64
- * values.  Output buffers are caller allocated; each call allocates small
+ * values.  Output buffers are caller allocated; each call allocates
  * temporary device buffers of its own; sizes below 2^31.
  * C = A B for A (m x k) and B (k x n).  bras_spgemm_rowptr writes C's row
  * pointers c_rowptr_d [m+1] and nnz(C) (synchronises the stream);
  * bras_spgemm_fill writes C's columns (ascending) and values, each entry the
  * sum of its products a_ip b_pj taken in the order of A's columns: the same
- * result for every launch shape.  EINVAL when a row of A has a
- * column outside [0, k), malformed row pointers, more than 2048 candidate
- * products in one row (the sum over the row of A of the selected B row
- * lengths) or more than 2048 entries in one row of A, nnz(C) >= 2^31, or (fill) row pointers that do not match the
- * counts.  Synchronous. */
+ * result for every launch shape.  A row's candidate products are the sum
+ * over its entries of the selected B row lengths; rows with at most 2048 of
+ * them and at most 2048 entries are formed in LDS, longer rows through a
+ * sort in device memory, in batches of at most 2^27 candidates (16 bytes
+ * each for the row pointers, 32 for the fill; the environment variable
+ * BRAS_SPGEMM_BATCH, a positive integer, sets another batch size; a row
+ * longer than a batch forms one alone, below 2^31 candidates).  EINVAL when
+ * a row of A has a column outside [0, k), malformed row pointers, a row of
+ * 2^31 or more candidates, nnz(C) >= 2^31, or (fill) row pointers that do
+ * not match the counts.  Synchronous. */
 int bras_spgemm_rowptr(int64_t m, int64_t k, const int64_t* a_rowptr_d, const int32_t* a_col_d,
                        const int64_t* b_rowptr_d, const int32_t* b_col_d, int64_t* c_rowptr_d, int64_t* nnz_h,
                        void* stream);

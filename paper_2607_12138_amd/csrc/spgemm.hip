@@ -10,10 +10,14 @@
 // distinct columns are counted, or each sums its products in candidate
 // order, i.e. in the order of A's columns, so the result does not depend on
 // the launch shape.  Every step is parallel over the wavefront: a wave scan
-// of the B row lengths, independent loads of all products.
+// of the B row lengths, independent loads of all products.  Rows past 2048
+// A entries or candidates (high-order H1 rows of G Mt^-1) are sorted in
+// device memory instead, in batches, by a stable radix sort that keeps the
+// candidate order within a column: the same sums, bit for bit.
 //
 // A^T: a stable radix sort of the entries by column (hipCUB), so each row of
 // A^T lists A's rows in ascending order; exact (no arithmetic).
+#include <cstdlib>
 #include <vector>
 
 #include <hipcub/hipcub.hpp>
@@ -58,8 +62,9 @@ __device__ inline void wave_bitonic(uint64_t* key, int m2) {
 
 // Two variants: CAP = kGemmSmall (half the LDS) takes the rows with at most
 // kGemmSmall A entries and candidates, and raises flag[1] for the others;
-// CAP = kGemmCap takes exactly those others.  Malformed rows, or rows beyond
-// kGemmCap, raise flag[0].
+// CAP = kGemmCap takes exactly those others.  Malformed rows raise flag[0];
+// rows beyond kGemmCap (A entries or candidates) are left to the sort in
+// device memory, and the small variant raises flag[2] for them.
 template <int CAP, int FILL>
 __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64_t* __restrict__ a_rp,
                                                const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
@@ -78,13 +83,15 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
     const int64_t na64 = a_rp[i + 1] - p0;
     // validation before any candidate is read (all lanes, uniform result):
     // row pointers of A and of the selected B rows inside [0, nnz] and
-    // non-decreasing, A's columns indexing rows of B, at most kGemmCap
-    // candidates; lengths summed by a wave scan, 64 entries at a time
+    // non-decreasing, A's columns indexing rows of B; lengths summed by a
+    // wave scan, 64 entries at a time, until they pass kGemmCap (a long row,
+    // validated in full by the sort's own pass)
     const int64_t annz = a_rp[m], bnnz = b_rp[k];
-    bool ok = na64 >= 0 && na64 <= kGemmCap && p0 >= 0 && p0 + na64 <= annz;
+    bool ok = na64 >= 0 && p0 >= 0 && p0 + na64 <= annz;
+    bool longrow = ok && na64 > kGemmCap;   // sorted in device memory instead
     int tot = 0;
     bool big = ok && na64 > CAP;   // past this variant's tables: stop writing them
-    if (ok) {
+    if (ok && !longrow) {
       const int na = (int)na64;
       bool bad = false;
       if (t == 0 && !big) pre[0] = 0;
@@ -115,11 +122,13 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
         tot += __shfl(x, 63, 64);
         if (tot > CAP) big = true;
       }
-      ok = __ballot(bad) == 0 && tot <= kGemmCap;
+      ok = __ballot(bad) == 0;
+      longrow = ok && tot > kGemmCap;
     }
-    if (!ok) {
+    if (!ok || longrow) {
       if (t == 0) {
-        flag[0] = 1;
+        if (!ok) flag[0] = 1;
+        else if (CAP == kGemmSmall) flag[2] = 1;
         if (!FILL) cnt[i] = 0;
       }
       __syncthreads();
@@ -242,6 +251,113 @@ __global__ void __launch_bounds__(256) k_col_starts(int64_t n, const int32_t* __
   }
 }
 
+// Rows of C = A B past kGemmCap (A entries or candidate products): their
+// candidates are written to device memory keyed (row in the batch, column),
+// sorted by a stable radix sort, so each column's products keep their
+// candidate order, and each run of equal keys is summed in that order: the
+// same result, bit for bit, as the LDS variants give a shorter row.
+
+// One thread per row of A: validation in full, and len[i] = the candidate
+// count of a long row (0 included), -1 for the other rows.
+__global__ void __launch_bounds__(256) k_long_len(int64_t m, int64_t k, const int64_t* __restrict__ a_rp,
+                                                  const int32_t* __restrict__ a_col,
+                                                  const int64_t* __restrict__ b_rp, int64_t* __restrict__ len,
+                                                  int* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t annz = a_rp[m], bnnz = b_rp[k];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const int64_t p0 = a_rp[i], p1 = a_rp[i + 1];
+    bool bad = p0 < 0 || p1 < p0 || p1 > annz;
+    int64_t tot = 0;
+    for (int64_t p = p0; !bad && p < p1; ++p) {
+      const int32_t a = a_col[p];
+      if (a < 0 || a >= k) {
+        bad = true;
+        break;
+      }
+      const int64_t b0 = b_rp[a], b1 = b_rp[a + 1];
+      if (b0 < 0 || b1 < b0 || b1 > bnnz) {
+        bad = true;
+        break;
+      }
+      tot += b1 - b0;
+    }
+    if (bad) flag[0] = 1;
+    len[i] = (!bad && (p1 - p0 > kGemmCap || tot > kGemmCap)) ? tot : -1;
+  }
+}
+
+// One wavefront per row of the batch: row rows[r]'s candidates, in candidate
+// order, at off[r] .. off[r+1): key (r << 32) | column, value the product.
+template <int FILL>
+__global__ void __launch_bounds__(64) k_long_expand(int nb, const int32_t* __restrict__ rows,
+                                                    const int64_t* __restrict__ off, const int64_t* __restrict__ a_rp,
+                                                    const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
+                                                    const int64_t* __restrict__ b_rp, const int32_t* __restrict__ b_col,
+                                                    const double* __restrict__ b_val, uint64_t* __restrict__ key,
+                                                    double* __restrict__ val) {
+  const int t = threadIdx.x;
+  for (int r = blockIdx.x; r < nb; r += gridDim.x) {
+    const int64_t i = rows[r], p1 = a_rp[i + 1], end = off[r + 1];
+    int64_t at = off[r];
+    for (int64_t p = a_rp[i]; p < p1; ++p) {
+      const int32_t a = a_col[p];
+      const int64_t b0 = b_rp[a], n = b_rp[a + 1] - b0;
+      const double av = FILL ? a_val[p] : 0.0;
+      for (int64_t q = t; q < n && at + q < end; q += 64) {
+        key[at + q] = ((uint64_t)(uint32_t)r << 32) | (uint32_t)b_col[b0 + q];
+        if (FILL) val[at + q] = av * b_val[b0 + q];
+      }
+      at += n;
+    }
+  }
+}
+
+// One wavefront per row of the batch over its sorted candidates: the count
+// of distinct keys, or (fill) each run summed in order and written, in
+// column order, at c_rp[row].  An output row of another length raises the
+// flag and writes nothing.
+template <int FILL>
+__global__ void __launch_bounds__(64) k_long_runs(int64_t m, int nb, const int32_t* __restrict__ rows,
+                                                  const int64_t* __restrict__ off, const uint64_t* __restrict__ key,
+                                                  const double* __restrict__ val, int32_t* __restrict__ cnt,
+                                                  const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
+                                                  double* __restrict__ c_val, int* __restrict__ flag) {
+  const int t = threadIdx.x;
+  for (int r = blockIdx.x; r < nb; r += gridDim.x) {
+    const int64_t i = rows[r], q0 = off[r], q1 = off[r + 1];
+    int64_t u = 0;
+    for (int64_t c = q0; c < q1; c += 64) {
+      const int64_t q = c + t;
+      u += __popcll(__ballot(q < q1 && (q == q0 || key[q] != key[q - 1])));
+    }
+    if (!FILL) {
+      if (t == 0) cnt[i] = (int32_t)u;
+      continue;
+    }
+    const int64_t o = c_rp[i];
+    if (o < 0 || c_rp[i + 1] - o != u || c_rp[i + 1] > c_rp[m]) {
+      if (t == 0) flag[0] = 1;
+      continue;
+    }
+    int64_t base = 0;
+    for (int64_t c = q0; c < q1; c += 64) {
+      const int64_t q = c + t;
+      const bool head = q < q1 && (q == q0 || key[q] != key[q - 1]);
+      const uint64_t mask = __ballot(head);
+      if (head) {
+        const uint64_t kq = key[q];
+        double sum = val[q];
+        for (int64_t x = q + 1; x < q1 && key[x] == kq; ++x) sum += val[x];
+        const int64_t at = o + base + __popcll(mask & ((1ull << t) - 1ull));
+        c_col[at] = (int32_t)(uint32_t)kq;
+        c_val[at] = sum;
+      }
+      base += __popcll(mask);
+    }
+  }
+}
+
 unsigned grid_of(int64_t work, int per_cu);
 
 // C = A + B (both m x n): one thread per row merges the two ascending column
@@ -307,15 +423,20 @@ __global__ void __launch_bounds__(256) k_csr_add(int64_t m, const int64_t* __res
 // Both variants of a pass (the large one only when the small one left rows);
 // *bad: a malformed or over-long row was found.
 template <int FILL>
+int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
+              const int64_t* b_rp, const int32_t* b_col, const double* b_val, int32_t* cnt, const int64_t* c_rp,
+              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int* bad);
+
+template <int FILL>
 int spgemm_pass(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
                 const int64_t* b_rp, const int32_t* b_col, const double* b_val, int32_t* cnt, const int64_t* c_rp,
                 int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int* bad) {
-  int hf[2] = {0, 0};
-  BRAS_HIP(hipMemsetAsync(flag_d, 0, 2 * sizeof(int), s));
+  int hf[3] = {0, 0, 0};
+  BRAS_HIP(hipMemsetAsync(flag_d, 0, 3 * sizeof(int), s));
   k_spgemm<kGemmSmall, FILL><<<grid_of(m, 32), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp,
                                                             c_col, c_val, flag_d);
   BRAS_HIP(hipGetLastError());
-  BRAS_HIP(hipMemcpyAsync(hf, flag_d, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipMemcpyAsync(hf, flag_d, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   BRAS_HIP(hipStreamSynchronize(s));
   if (!hf[0] && hf[1]) {
     k_spgemm<kGemmCap, FILL><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp,
@@ -324,6 +445,8 @@ int spgemm_pass(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col,
     BRAS_HIP(hipMemcpyAsync(hf, flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
     BRAS_HIP(hipStreamSynchronize(s));
   }
+  if (!hf[0] && hf[2])
+    return long_rows<FILL>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp, c_col, c_val, flag_d, s, bad);
   *bad = hf[0];
   return BRAS_OK;
 }
@@ -354,6 +477,111 @@ struct DevBufs {
   }
 };
 
+constexpr int64_t kLongBatch = (int64_t)1 << 27;   // candidates sorted at once (32 bytes each when filling)
+
+// BRAS_SPGEMM_BATCH (a positive integer) replaces kLongBatch: less device
+// memory per call, more sorts.
+int64_t long_batch() {
+  const char* e = std::getenv("BRAS_SPGEMM_BATCH");
+  const long long v = e ? std::atoll(e) : 0;
+  return v > 0 ? (int64_t)v : kLongBatch;
+}
+
+// The rows past kGemmCap, in row order, in batches of at most long_batch()
+// candidates (a longer row alone): expand, stable radix sort over the bits
+// the keys use, runs.  *bad: a malformed row (or, when filling, an output
+// row of the wrong length).
+template <int FILL>
+int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
+              const int64_t* b_rp, const int32_t* b_col, const double* b_val, int32_t* cnt, const int64_t* c_rp,
+              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int* bad) {
+  DevBufs tmp;
+  int64_t* len = nullptr;
+  int st, hf = 0;
+  if ((st = tmp.get(&len, (size_t)m))) return st;
+  BRAS_HIP(hipMemsetAsync(flag_d, 0, sizeof(int), s));
+  k_long_len<<<grid_of((m + 255) / 256, 8), 256, 0, s>>>(m, k, a_rp, a_col, b_rp, len, flag_d);
+  BRAS_HIP(hipGetLastError());
+  std::vector<int64_t> hl(m);
+  BRAS_HIP(hipMemcpyAsync(hl.data(), len, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipMemcpyAsync(&hf, flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  if (hf) {
+    *bad = 1;
+    return BRAS_OK;
+  }
+  std::vector<std::vector<int32_t>> rows;
+  std::vector<std::vector<int64_t>> offs;
+  const int64_t batch = long_batch();
+  for (int64_t i = 0; i < m; ++i) {
+    if (hl[i] < 0) continue;
+    if (rows.empty() || (!rows.back().empty() && offs.back().back() + hl[i] > batch)) {
+      rows.emplace_back();
+      offs.emplace_back(1, 0);
+    }
+    rows.back().push_back((int32_t)i);
+    offs.back().push_back(offs.back().back() + hl[i]);
+  }
+  // sizes: the largest batch, and the sort's scratch for every batch
+  auto end_bit = [](size_t nb) {
+    int eb = 32;
+    while (((size_t)1 << (eb - 32)) < nb) ++eb;
+    return eb;
+  };
+  int64_t cap = 1;
+  size_t maxnb = 1, bytes = 0;
+  for (size_t b = 0; b < rows.size(); ++b) {
+    const int64_t L = offs[b].back();
+    BRAS_CHECK(L < (1LL << 31), "a row of A selects %lld candidate products; at most 2^31 - 1 are supported",
+               (long long)L);
+    cap = L > cap ? L : cap;
+    maxnb = rows[b].size() > maxnb ? rows[b].size() : maxnb;
+    size_t need = 0;
+    hipcub::DoubleBuffer<uint64_t> kq(nullptr, nullptr);
+    hipcub::DoubleBuffer<double> vq(nullptr, nullptr);
+    if (FILL)
+      BRAS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kq, vq, (int)L, 0, end_bit(rows[b].size()), s));
+    else
+      BRAS_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, need, kq, (int)L, 0, end_bit(rows[b].size()), s));
+    bytes = need > bytes ? need : bytes;
+  }
+  int32_t* rows_d = nullptr;
+  int64_t* off_d = nullptr;
+  uint64_t *k0 = nullptr, *k1 = nullptr;
+  double *v0 = nullptr, *v1 = nullptr;
+  char* cub_tmp = nullptr;
+  if ((st = tmp.get(&rows_d, maxnb)) || (st = tmp.get(&off_d, maxnb + 1)) || (st = tmp.get(&k0, (size_t)cap)) ||
+      (st = tmp.get(&k1, (size_t)cap)) || (st = tmp.get(&v0, FILL ? (size_t)cap : 1)) ||
+      (st = tmp.get(&v1, FILL ? (size_t)cap : 1)) || (st = tmp.get(&cub_tmp, bytes)))
+    return st;
+  for (size_t b = 0; b < rows.size(); ++b) {
+    const int nb = (int)rows[b].size();
+    const int64_t L = offs[b].back();
+    BRAS_HIP(hipMemcpyAsync(rows_d, rows[b].data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
+    BRAS_HIP(hipMemcpyAsync(off_d, offs[b].data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s));
+    hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
+    hipcub::DoubleBuffer<double> vb(v0, v1);
+    if (L > 0) {
+      k_long_expand<FILL><<<grid_of(nb, 16), 64, 0, s>>>(nb, rows_d, off_d, a_rp, a_col, a_val, b_rp, b_col, b_val,
+                                                          k0, v0);
+      BRAS_HIP(hipGetLastError());
+      size_t have = bytes;
+      if (FILL)
+        BRAS_HIP(hipcub::DeviceRadixSort::SortPairs(cub_tmp, have, kb, vb, (int)L, 0, end_bit(nb), s));
+      else
+        BRAS_HIP(hipcub::DeviceRadixSort::SortKeys(cub_tmp, have, kb, (int)L, 0, end_bit(nb), s));
+    }
+    k_long_runs<FILL><<<grid_of(nb, 16), 64, 0, s>>>(m, nb, rows_d, off_d, kb.Current(), FILL ? vb.Current() : nullptr,
+                                                      cnt, c_rp, c_col, c_val, flag_d);
+    BRAS_HIP(hipGetLastError());
+    BRAS_HIP(hipStreamSynchronize(s));   // the next batch reuses the buffers and the host lists stay valid
+  }
+  BRAS_HIP(hipMemcpyAsync(&hf, flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  *bad = hf;
+  return BRAS_OK;
+}
+
 }  // namespace
 }  // namespace bras
 
@@ -373,15 +601,15 @@ extern "C" int bras_spgemm_rowptr(int64_t m, int64_t k, const int64_t* a_rowptr_
     int32_t* cnt = nullptr;
     int* flag = nullptr;
     int st, hf = 0;
-    if ((st = tmp.get(&cnt, (size_t)m)) || (st = tmp.get(&flag, 2))) return st;
+    if ((st = tmp.get(&cnt, (size_t)m)) || (st = tmp.get(&flag, 3))) return st;
     if ((st = spgemm_pass<0>(m, k, a_rowptr_d, a_col_d, nullptr, b_rowptr_d, b_col_d, nullptr, cnt, nullptr, nullptr,
                              nullptr, flag, s, &hf)))
       return st;
     std::vector<int32_t> hc(m);
     BRAS_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
     BRAS_HIP(hipStreamSynchronize(s));
-    BRAS_CHECK(!hf, "a row of A has a column outside [0, %lld) or selects more than %d products", (long long)k,
-               kGemmCap);
+    BRAS_CHECK(!hf, "a row of A has a column outside [0, %lld), or row pointers of A or B are malformed",
+               (long long)k);
     for (int64_t i = 0; i < m; ++i) rp[i + 1] = rp[i] + hc[i];
   }
   BRAS_CHECK(rp[m] < (1LL << 31), "the product has %lld entries; at most 2^31 - 1 are supported", (long long)rp[m]);
@@ -405,11 +633,12 @@ extern "C" int bras_spgemm_fill(int64_t m, int64_t k, const int64_t* a_rowptr_d,
   DevBufs tmp;
   int* flag = nullptr;
   int st, hf = 0;
-  if ((st = tmp.get(&flag, 2))) return st;
+  if ((st = tmp.get(&flag, 3))) return st;
   if ((st = spgemm_pass<1>(m, k, a_rowptr_d, a_col_d, a_val_d, b_rowptr_d, b_col_d, b_val_d, nullptr, c_rowptr_d,
                            c_col_d, c_val_d, flag, s, &hf)))
     return st;
-  BRAS_CHECK(!hf, "a row of A has a column outside [0, %lld) or selects more than %d products", (long long)k, kGemmCap);
+  BRAS_CHECK(!hf, "a row of A has a column outside [0, %lld), malformed row pointers, or C's row pointers do not match "
+                  "the counts", (long long)k);
   return BRAS_OK;
 }
 

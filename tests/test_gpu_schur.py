@@ -78,7 +78,8 @@ def test_spgemm_and_transpose_match_scipy(m, k, n, ra, rb):
     assert same_pattern(At, Ar) and np.array_equal(At.data, Ar.data)
 
 
-SCHUR = [("P", 2, 2, 6, 0.2), ("N1curl", 3, 1, 3, 0.2), ("RT", 2, 2, 5, 0.2), ("BDM", 3, 1, 2, 0.0)]
+SCHUR = [("P", 2, 2, 6, 0.2), ("N1curl", 3, 1, 3, 0.2), ("RT", 2, 2, 5, 0.2), ("BDM", 3, 1, 2, 0.0),
+         ("P", 3, 3, 4, 0.2)]   # P3: 36 rows of (G M_bras^-1) G^T past 2048 candidates (the sort in HBM)
 
 
 @pytest.mark.parametrize("case", SCHUR, ids=lambda c: "%s%d-%dd-N%d" % (c[0], c[2], c[1], c[3]))
@@ -129,11 +130,12 @@ def test_spgemm_is_reproducible_and_rejects_bad_input():
     with pytest.raises(L.BrasError) as e:
         L.bras_spgemm_rowptr(500, 100, a, b, rp)          # A's columns reach 299
     assert e.value.code == L.BRAS_EINVAL
-    # more than 2048 candidate products in one row
+    # a column of A outside the rows of B in a row past 2048 candidates (the
+    # sort's own validation)
     W = sp.csr_matrix(np.ones((2, 40)))
     Wb = sp.csr_matrix(np.ones((40, 60)))
     with pytest.raises(L.BrasError) as e:
-        L.bras_spgemm_rowptr(2, 40, to_dev(W), to_dev(Wb), torch.empty(3, dtype=torch.int64, device="cuda"))
+        L.bras_spgemm_rowptr(2, 39, to_dev(W), to_dev(Wb), torch.empty(3, dtype=torch.int64, device="cuda"))
     assert e.value.code == L.BRAS_EINVAL
     # row pointers of C that do not match the counts
     bad = (c1[0].clone(), c1[1].clone(), c1[2].clone())
@@ -223,46 +225,90 @@ def test_diagonal_schur_and_bras_comparison(case):
     gpu.close()
 
 
-def test_spgemm_candidate_cap_boundaries():
-    """Rows at the two LDS variants' limits: 1024 candidates (the half-LDS
-    variant), 1056 and 2048 (the full one), more than 1024 A entries with
-    few candidates (empty B rows), all against SciPy in one product; 2049
-    candidates, or 2049 entries in a row of A, are rejected."""
-    from paper_2607_12138_amd import _lib as L
-    from paper_2607_12138_amd.problem import spgemm
-    import torch
-    k, n = 3000, 4000
+def ordered_product(A, B):
+    """C = A B with each entry the sum of its products taken in the order of
+    A's columns, then B's (the order the library documents), in float64."""
+    A, B = sp.csr_matrix(A), sp.csr_matrix(B)
+    A.sort_indices()
+    B.sort_indices()
+    rp, cols, vals = [0], [], []
+    for i in range(A.shape[0]):
+        acc = {}
+        for p in range(A.indptr[i], A.indptr[i + 1]):
+            a, av = A.indices[p], float(A.data[p])
+            for q in range(B.indptr[a], B.indptr[a + 1]):
+                j, v = int(B.indices[q]), av * float(B.data[q])
+                acc[j] = acc[j] + v if j in acc else v
+        ks = sorted(acc)
+        cols += ks
+        vals += [acc[j] for j in ks]
+        rp.append(len(cols))
+    return sp.csr_matrix((np.array(vals, dtype=np.float64), np.array(cols, dtype=np.int64), np.array(rp)),
+                         shape=(A.shape[0], B.shape[1]))
+
+
+def cap_case():
+    """B (6000 x 4000): rows 0..1999 of 32 seeded columns, row 2999 of one,
+    the rest empty.  Rows of A at and past the LDS variants' limits: 1024
+    candidates (half-LDS variant), 1056 and 2048 (full), 1509 entries with
+    320 candidates (full, by entries), 2049 candidates, 2120 entries with 640
+    candidates and the same row without its empty B rows, 2100 entries all
+    selecting empty B rows, 22400 candidates, an empty row, a short row."""
+    k, n = 6000, 4000
     rng = np.random.default_rng(17)
-    # B: rows 0..1999 of length 32, rows 2000..2999 empty
-    brows = np.repeat(np.arange(2000), 32)
-    bcols = np.concatenate([rng.choice(n, 32, replace=False) for _ in range(2000)])
+    brows = np.r_[np.repeat(np.arange(2000), 32), 2999]
+    bcols = np.r_[np.concatenate([rng.choice(n, 32, replace=False) for _ in range(2000)]), 5]
     B = sp.csr_matrix((rng.uniform(-1, 1, brows.size), (brows, bcols)), shape=(k, n))
     B.sort_indices()
-    # A rows selecting 32, 33 and 64 non-empty B rows (1024, 1056, 2048
-    # candidates), one selecting 1499 empty rows and 10 non-empty ones
-    sel = [np.arange(0, 32), np.arange(100, 133), np.arange(500, 564), np.concatenate([np.arange(2000, 2750),
-                                                                                      np.arange(10, 20),
-                                                                                      np.arange(2250, 2999)])]
-    arows = np.concatenate([np.full(len(s), i) for i, s in enumerate(sel)])
+    sel = [np.arange(0, 32), np.arange(100, 133), np.arange(500, 564),
+           np.r_[np.arange(10, 20), np.arange(2000, 2999), np.arange(3000, 3500)],
+           np.r_[np.arange(600, 664), 2999],
+           np.r_[np.arange(700, 720), np.arange(3000, 5100)],
+           np.arange(700, 720),
+           np.arange(3000, 5100),
+           np.arange(1000, 1700),
+           np.arange(0, 0),
+           np.array([1, 2999])]
+    arows = np.concatenate([np.full(len(x), i) for i, x in enumerate(sel)])
     acols = np.concatenate(sel)
     A = sp.csr_matrix((rng.uniform(-1, 1, arows.size), (arows, acols)), shape=(len(sel), k))
     A.sort_indices()
-    assert [int((B[A[i].indices].getnnz())) for i in range(len(sel))] == [1024, 1056, 2048, 320]
+    # rows 5 and 6 select the same products in the same order
+    A.data[A.indptr[6]:A.indptr[7]] = A.data[A.indptr[5]:A.indptr[5] + 20]
+    return A, B, k, n
+
+
+def test_spgemm_candidate_cap_boundaries():
+    """Rows at and past the LDS variants' limits (both variants and the sort
+    in device memory) against the candidate-order sums, bit for bit; a row
+    whose extra entries select only empty B rows gives the same row as
+    without them."""
+    from paper_2607_12138_amd.problem import spgemm
+    A, B, k, n = cap_case()
+    bl = np.diff(B.indptr)
+    cand = [int(bl[A.indices[A.indptr[i]:A.indptr[i + 1]]].sum()) for i in range(A.shape[0])]
+    assert cand == [1024, 1056, 2048, 320, 2049, 640, 640, 0, 22400, 0, 33]
     say("spgemm at the candidate caps")
-    Cg = to_host(spgemm(to_dev(A), to_dev(B), len(sel), k), (len(sel), n))
-    Cr = (A @ B).tocsr()
-    assert same_pattern(Cg, (abs(A) @ abs(B)))
-    assert np.abs((Cg - Cr).toarray()).max() <= 1e-13 * (abs(A) @ abs(B)).toarray().max()
-    # 2049 candidates: one more non-empty B row of length 1
-    B2 = sp.vstack([B, sp.csr_matrix(([1.0], ([0], [0])), shape=(1, n))]).tocsr()
-    A2 = sp.csr_matrix((np.ones(65), (np.zeros(65, dtype=int), np.r_[np.arange(64), 3000])), shape=(1, k + 1))
-    with pytest.raises(L.BrasError) as e:
-        L.bras_spgemm_rowptr(1, k + 1, to_dev(A2), to_dev(B2), torch.empty(2, dtype=torch.int64, device="cuda"))
-    assert e.value.code == L.BRAS_EINVAL
-    # 2049 entries in one row of A, all of them empty rows of B
-    A3 = sp.csr_matrix((np.ones(2049), (np.zeros(2049, dtype=int), np.arange(2049))), shape=(1, 3 * 2049))
-    B3 = sp.csr_matrix(([1.0], ([3 * 2049 - 1], [0])), shape=(3 * 2049, n))   # one entry, in a row not selected
-    with pytest.raises(L.BrasError) as e:
-        L.bras_spgemm_rowptr(1, 3 * 2049, to_dev(A3), to_dev(B3), torch.empty(2, dtype=torch.int64, device="cuda"))
-    assert e.value.code == L.BRAS_EINVAL
-    torch.cuda.synchronize()
+    Cg = to_host(spgemm(to_dev(A), to_dev(B), A.shape[0], k), (A.shape[0], n))
+    Cr = ordered_product(A, B)
+    assert np.array_equal(Cg.indptr, Cr.indptr) and np.array_equal(Cg.indices, Cr.indices)
+    assert np.array_equal(Cg.data, Cr.data)
+    assert Cg.indptr[8] == Cg.indptr[7]          # 2100 entries, no candidates
+    assert np.array_equal(Cg[5].toarray(), Cg[6].toarray())
+    assert np.abs((Cg - A @ B).toarray()).max() <= 1e-13 * (abs(A) @ abs(B)).toarray().max()
+
+
+@pytest.mark.parametrize("batch", ["1", "2100", "25000"])
+def test_spgemm_long_rows_in_batches(batch, monkeypatch):
+    """The sort in device memory split into batches of other sizes (one row
+    each, several rows, all rows): the same product, bit for bit."""
+    import torch
+    from paper_2607_12138_amd.problem import spgemm
+    A, B, k, n = cap_case()
+    a, b = to_dev(A), to_dev(B)
+    say("spgemm, long rows in batches of %s" % batch)
+    ref = spgemm(a, b, A.shape[0], k)
+    monkeypatch.setenv("BRAS_SPGEMM_BATCH", batch)
+    got = spgemm(a, b, A.shape[0], k)
+    monkeypatch.delenv("BRAS_SPGEMM_BATCH")
+    assert all(torch.equal(x, y) for x, y in zip(ref, got))
