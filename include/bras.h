@@ -280,12 +280,13 @@ int bras_csr_jacobi(bras_handle h, int64_t* rowptr_d, int32_t* col_d, double* va
  * bras_spgemm_fill writes C's columns (ascending) and values, each entry the
  * sum of its products a_ip b_pj taken in the order of A's columns: the same
  * result for every launch shape.  A row's candidate products are the sum
- * over its entries of the selected B row lengths; rows with at most 2048 of
- * them and at most 2048 entries are formed in LDS, longer rows through a
+ * over its entries of the selected B row lengths; rows with at most 1024 of
+ * them and at most 1024 entries are formed in LDS, longer rows through a
  * sort in device memory, in batches of at most 2^27 candidates (16 bytes
- * each for the row pointers, 32 for the fill; the environment variable
- * BRAS_SPGEMM_BATCH, a positive integer, sets another batch size; a row
- * longer than a batch forms one alone, below 2^31 candidates).  EINVAL when
+ * each for the row pointers, 32 for the fill; a row longer than a batch
+ * forms one alone, below 2^31 candidates).  Both routes give the same sums.
+ * Environment: BRAS_SPGEMM_BATCH (a positive integer) sets another batch
+ * size; BRAS_SPGEMM_LDS_MAX (0 .. 2048) another limit for the LDS route.  EINVAL when
  * a row of A has a column outside [0, k), malformed row pointers, a row of
  * 2^31 or more candidates, nnz(C) >= 2^31, or (fill) row pointers that do
  * not match the counts.  Synchronous. */

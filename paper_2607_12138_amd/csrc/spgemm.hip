@@ -10,10 +10,10 @@
 // distinct columns are counted, or each sums its products in candidate
 // order, i.e. in the order of A's columns, so the result does not depend on
 // the launch shape.  Every step is parallel over the wavefront: a wave scan
-// of the B row lengths, independent loads of all products.  Rows past 2048
-// A entries or candidates (high-order H1 rows of G Mt^-1) are sorted in
-// device memory instead, in batches, by a stable radix sort that keeps the
-// candidate order within a column: the same sums, bit for bit.
+// of the B row lengths, independent loads of all products.  Rows past 1024
+// A entries or candidates (by default; up to 2048 can stay in LDS) are
+// sorted in device memory instead, in batches, by a stable radix sort that
+// keeps the candidate order within a column: the same sums, bit for bit.
 //
 // A^T: a stable radix sort of the entries by column (hipCUB), so each row of
 // A^T lists A's rows in ascending order; exact (no arithmetic).
@@ -29,6 +29,19 @@ namespace {
 
 constexpr int kGemmCap = 2048;    // candidate products of one row of C
 constexpr int kGemmSmall = 1024;  // rows up to this many run with half the LDS (twice the work-groups per CU)
+
+// Rows with more candidates or A entries than this take the sort in device
+// memory.  Default kGemmSmall: on the Schur products of 48^3 N1curl_2 and
+// 24^3 P3 the sort forms the rows between 1024 and 2048 candidates about
+// 2.4x faster than the kGemmCap variant at 3 work-groups per CU, and lower
+// limits gain nothing on G Mt^-1 and lose on (G Mt^-1) G^T.  The
+// environment variable BRAS_SPGEMM_LDS_MAX (0 .. kGemmCap) sets another.
+int lds_max() {
+  const char* e = std::getenv("BRAS_SPGEMM_LDS_MAX");
+  if (!e || !*e) return kGemmSmall;
+  const long long v = std::atoll(e);
+  return v < 0 ? 0 : (v > kGemmCap ? kGemmCap : (int)v);
+}
 
 // Bitonic sort of key[0 .. m2) (m2 a power of two, at most kGemmCap) by one
 // wavefront: every stage first loads all of this lane's pairs, then
@@ -63,15 +76,15 @@ __device__ inline void wave_bitonic(uint64_t* key, int m2) {
 // Two variants: CAP = kGemmSmall (half the LDS) takes the rows with at most
 // kGemmSmall A entries and candidates, and raises flag[1] for the others;
 // CAP = kGemmCap takes exactly those others.  Malformed rows raise flag[0];
-// rows beyond kGemmCap (A entries or candidates) are left to the sort in
-// device memory, and the small variant raises flag[2] for them.
+// rows beyond lmax (A entries or candidates) are left to the sort in device
+// memory, and the small variant raises flag[2] for them.
 template <int CAP, int FILL>
 __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64_t* __restrict__ a_rp,
                                                const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
                                                const int64_t* __restrict__ b_rp, const int32_t* __restrict__ b_col,
                                                const double* __restrict__ b_val, int32_t* __restrict__ cnt,
                                                const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
-                                               double* __restrict__ c_val, int* __restrict__ flag) {
+                                               double* __restrict__ c_val, int* __restrict__ flag, int lmax) {
   __shared__ uint64_t key[CAP];      // (column << 32) | candidate index, sorted
   __shared__ int32_t pre[CAP + 1];   // prefix sums of the selected B row lengths
   __shared__ int32_t bst[CAP];       // start of each selected B row
@@ -84,18 +97,18 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
     // validation before any candidate is read (all lanes, uniform result):
     // row pointers of A and of the selected B rows inside [0, nnz] and
     // non-decreasing, A's columns indexing rows of B; lengths summed by a
-    // wave scan, 64 entries at a time, until they pass kGemmCap (a long row,
-    // validated in full by the sort's own pass)
+    // wave scan, 64 entries at a time, until they pass lmax <= kGemmCap (a
+    // long row, validated in full by the sort's own pass)
     const int64_t annz = a_rp[m], bnnz = b_rp[k];
     bool ok = na64 >= 0 && p0 >= 0 && p0 + na64 <= annz;
-    bool longrow = ok && na64 > kGemmCap;   // sorted in device memory instead
+    bool longrow = ok && na64 > lmax;   // sorted in device memory instead
     int tot = 0;
     bool big = ok && na64 > CAP;   // past this variant's tables: stop writing them
     if (ok && !longrow) {
       const int na = (int)na64;
       bool bad = false;
       if (t == 0 && !big) pre[0] = 0;
-      for (int c0 = 0; c0 < na && tot <= kGemmCap; c0 += 64) {
+      for (int c0 = 0; c0 < na && tot <= lmax; c0 += 64) {
         const int p = c0 + t;
         int len = 0;
         if (p < na) {
@@ -123,7 +136,7 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
         if (tot > CAP) big = true;
       }
       ok = __ballot(bad) == 0;
-      longrow = ok && tot > kGemmCap;
+      longrow = ok && tot > lmax;
     }
     if (!ok || longrow) {
       if (t == 0) {
@@ -262,7 +275,7 @@ __global__ void __launch_bounds__(256) k_col_starts(int64_t n, const int32_t* __
 __global__ void __launch_bounds__(256) k_long_len(int64_t m, int64_t k, const int64_t* __restrict__ a_rp,
                                                   const int32_t* __restrict__ a_col,
                                                   const int64_t* __restrict__ b_rp, int64_t* __restrict__ len,
-                                                  int* __restrict__ flag) {
+                                                  int* __restrict__ flag, int lmax) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t annz = a_rp[m], bnnz = b_rp[k];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
@@ -283,7 +296,7 @@ __global__ void __launch_bounds__(256) k_long_len(int64_t m, int64_t k, const in
       tot += b1 - b0;
     }
     if (bad) flag[0] = 1;
-    len[i] = (!bad && (p1 - p0 > kGemmCap || tot > kGemmCap)) ? tot : -1;
+    len[i] = (!bad && (p1 - p0 > lmax || tot > lmax)) ? tot : -1;
   }
 }
 
@@ -425,7 +438,7 @@ __global__ void __launch_bounds__(256) k_csr_add(int64_t m, const int64_t* __res
 template <int FILL>
 int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
               const int64_t* b_rp, const int32_t* b_col, const double* b_val, int32_t* cnt, const int64_t* c_rp,
-              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int* bad);
+              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int lmax, int* bad);
 
 template <int FILL>
 int spgemm_pass(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
@@ -433,20 +446,22 @@ int spgemm_pass(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col,
                 int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int* bad) {
   int hf[3] = {0, 0, 0};
   BRAS_HIP(hipMemsetAsync(flag_d, 0, 3 * sizeof(int), s));
+  const int lmax = lds_max();
   k_spgemm<kGemmSmall, FILL><<<grid_of(m, 32), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp,
-                                                            c_col, c_val, flag_d);
+                                                            c_col, c_val, flag_d, lmax);
   BRAS_HIP(hipGetLastError());
   BRAS_HIP(hipMemcpyAsync(hf, flag_d, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   BRAS_HIP(hipStreamSynchronize(s));
   if (!hf[0] && hf[1]) {
     k_spgemm<kGemmCap, FILL><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp,
-                                                            c_col, c_val, flag_d);
+                                                            c_col, c_val, flag_d, lmax);
     BRAS_HIP(hipGetLastError());
     BRAS_HIP(hipMemcpyAsync(hf, flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
     BRAS_HIP(hipStreamSynchronize(s));
   }
   if (!hf[0] && hf[2])
-    return long_rows<FILL>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp, c_col, c_val, flag_d, s, bad);
+    return long_rows<FILL>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp, c_col, c_val, flag_d, s, lmax,
+                           bad);
   *bad = hf[0];
   return BRAS_OK;
 }
@@ -494,13 +509,13 @@ int64_t long_batch() {
 template <int FILL>
 int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
               const int64_t* b_rp, const int32_t* b_col, const double* b_val, int32_t* cnt, const int64_t* c_rp,
-              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int* bad) {
+              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int lmax, int* bad) {
   DevBufs tmp;
   int64_t* len = nullptr;
   int st, hf = 0;
   if ((st = tmp.get(&len, (size_t)m))) return st;
   BRAS_HIP(hipMemsetAsync(flag_d, 0, sizeof(int), s));
-  k_long_len<<<grid_of((m + 255) / 256, 8), 256, 0, s>>>(m, k, a_rp, a_col, b_rp, len, flag_d);
+  k_long_len<<<grid_of((m + 255) / 256, 8), 256, 0, s>>>(m, k, a_rp, a_col, b_rp, len, flag_d, lmax);
   BRAS_HIP(hipGetLastError());
   std::vector<int64_t> hl(m);
   BRAS_HIP(hipMemcpyAsync(hl.data(), len, sizeof(int64_t) * m, hipMemcpyDeviceToHost, s));

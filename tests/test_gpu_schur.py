@@ -130,12 +130,13 @@ def test_spgemm_is_reproducible_and_rejects_bad_input():
     with pytest.raises(L.BrasError) as e:
         L.bras_spgemm_rowptr(500, 100, a, b, rp)          # A's columns reach 299
     assert e.value.code == L.BRAS_EINVAL
-    # a column of A outside the rows of B in a row past 2048 candidates (the
-    # sort's own validation)
-    W = sp.csr_matrix(np.ones((2, 40)))
-    Wb = sp.csr_matrix(np.ones((40, 60)))
+    # a column of A outside the rows of B past the entries the LDS route
+    # scans (its first 64 entries already select 3840 candidates): the sort
+    # in device memory validates the whole row
+    W = sp.csr_matrix(np.ones((1, 100)))
+    Wb = sp.csr_matrix(np.ones((100, 60)))
     with pytest.raises(L.BrasError) as e:
-        L.bras_spgemm_rowptr(2, 39, to_dev(W), to_dev(Wb), torch.empty(3, dtype=torch.int64, device="cuda"))
+        L.bras_spgemm_rowptr(1, 99, to_dev(W), to_dev(Wb), torch.empty(2, dtype=torch.int64, device="cuda"))
     assert e.value.code == L.BRAS_EINVAL
     # row pointers of C that do not match the counts
     bad = (c1[0].clone(), c1[1].clone(), c1[2].clone())
@@ -278,13 +279,18 @@ def cap_case():
     return A, B, k, n
 
 
-def test_spgemm_candidate_cap_boundaries():
-    """Rows at and past the LDS variants' limits (both variants and the sort
-    in device memory) against the candidate-order sums, bit for bit; a row
-    whose extra entries select only empty B rows gives the same row as
+@pytest.mark.parametrize("lds_max", ["", "2048", "0"])
+def test_spgemm_candidate_cap_boundaries(lds_max, monkeypatch):
+    """Rows at and past the LDS variants' limits against the candidate-order
+    sums, bit for bit, with the default LDS limit (1024: the half-LDS variant
+    and the sort in device memory), with 2048 (both LDS variants, the sort
+    past 2048) and with 0 (every non-empty row sorted in device memory); a
+    row whose extra entries select only empty B rows gives the same row as
     without them."""
     from paper_2607_12138_amd.problem import spgemm
     A, B, k, n = cap_case()
+    if lds_max:
+        monkeypatch.setenv("BRAS_SPGEMM_LDS_MAX", lds_max)
     bl = np.diff(B.indptr)
     cand = [int(bl[A.indices[A.indptr[i]:A.indptr[i + 1]]].sum()) for i in range(A.shape[0])]
     assert cand == [1024, 1056, 2048, 320, 2049, 640, 640, 0, 22400, 0, 33]
