@@ -228,7 +228,7 @@ def schur_section(prob, w, reps=3):
                    "nnz_St": int(S[1].numel())}
             del T, Gt, S
         out["ms"] = round(best * 1e3, 3)
-    except L.BrasError as e:     # e.g. a row beyond the candidate cap: reported, not fatal to the bench
+    except L.BrasError as e:     # e.g. device memory for the sort of long rows: reported, not fatal to the bench
         out = {"error": str(e)}
     del B, G
     torch.cuda.empty_cache()
