@@ -264,9 +264,10 @@ __global__ void __launch_bounds__(256) k_col_starts(int64_t n, const int32_t* __
   }
 }
 
-// Rows of C = A B past kGemmCap (A entries or candidate products): their
+// Rows of C = A B past the LDS limit (A entries or candidate products): their
 // candidates are written to device memory keyed (row in the batch, column),
-// sorted by a stable radix sort, so each column's products keep their
+// sorted by a stable radix sort over the bits the keys use (the widest
+// column of B, then the batch's row count), so each column's products keep their
 // candidate order, and each run of equal keys is summed in that order: the
 // same result, bit for bit, as the LDS variants give a shorter row.
 
@@ -301,14 +302,15 @@ __global__ void __launch_bounds__(256) k_long_len(int64_t m, int64_t k, const in
 }
 
 // One wavefront per row of the batch: row rows[r]'s candidates, in candidate
-// order, at off[r] .. off[r+1): key (r << 32) | column, value the product.
+// order, at off[r] .. off[r+1): key (r << cbits) | column, value the product
+// (every column of B below 2^cbits).
 template <int FILL>
 __global__ void __launch_bounds__(64) k_long_expand(int nb, const int32_t* __restrict__ rows,
                                                     const int64_t* __restrict__ off, const int64_t* __restrict__ a_rp,
                                                     const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
                                                     const int64_t* __restrict__ b_rp, const int32_t* __restrict__ b_col,
                                                     const double* __restrict__ b_val, uint64_t* __restrict__ key,
-                                                    double* __restrict__ val) {
+                                                    double* __restrict__ val, int cbits) {
   const int t = threadIdx.x;
   for (int r = blockIdx.x; r < nb; r += gridDim.x) {
     const int64_t i = rows[r], p1 = a_rp[i + 1], end = off[r + 1];
@@ -318,7 +320,7 @@ __global__ void __launch_bounds__(64) k_long_expand(int nb, const int32_t* __res
       const int64_t b0 = b_rp[a], n = b_rp[a + 1] - b0;
       const double av = FILL ? a_val[p] : 0.0;
       for (int64_t q = t; q < n && at + q < end; q += 64) {
-        key[at + q] = ((uint64_t)(uint32_t)r << 32) | (uint32_t)b_col[b0 + q];
+        key[at + q] = ((uint64_t)(uint32_t)r << cbits) | (uint32_t)b_col[b0 + q];
         if (FILL) val[at + q] = av * b_val[b0 + q];
       }
       at += n;
@@ -335,8 +337,9 @@ __global__ void __launch_bounds__(64) k_long_runs(int64_t m, int nb, const int32
                                                   const int64_t* __restrict__ off, const uint64_t* __restrict__ key,
                                                   const double* __restrict__ val, int32_t* __restrict__ cnt,
                                                   const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
-                                                  double* __restrict__ c_val, int* __restrict__ flag) {
+                                                  double* __restrict__ c_val, int* __restrict__ flag, int cbits) {
   const int t = threadIdx.x;
+  const uint64_t cmask = (1ull << cbits) - 1ull;
   for (int r = blockIdx.x; r < nb; r += gridDim.x) {
     const int64_t i = rows[r], q0 = off[r], q1 = off[r + 1];
     int64_t u = 0;
@@ -363,7 +366,7 @@ __global__ void __launch_bounds__(64) k_long_runs(int64_t m, int nb, const int32
         double sum = val[q];
         for (int64_t x = q + 1; x < q1 && key[x] == kq; ++x) sum += val[x];
         const int64_t at = o + base + __popcll(mask & ((1ull << t) - 1ull));
-        c_col[at] = (int32_t)(uint32_t)kq;
+        c_col[at] = (int32_t)(uint32_t)(kq & cmask);
         c_val[at] = sum;
       }
       base += __popcll(mask);
@@ -537,10 +540,27 @@ int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, c
     rows.back().push_back((int32_t)i);
     offs.back().push_back(offs.back().back() + hl[i]);
   }
-  // sizes: the largest batch, and the sort's scratch for every batch
-  auto end_bit = [](size_t nb) {
-    int eb = 32;
-    while (((size_t)1 << (eb - 32)) < nb) ++eb;
+  // key bits: the widest column of B (unsigned), then the row in the batch
+  int64_t bnnz = 0;
+  BRAS_HIP(hipMemcpyAsync(&bnnz, b_rp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  uint32_t maxcol = 0;
+  if (bnnz > 0) {
+    uint32_t* mx_d = nullptr;
+    char* red_tmp = nullptr;
+    size_t rbytes = 0;
+    const uint32_t* ucol = reinterpret_cast<const uint32_t*>(b_col);
+    BRAS_HIP(hipcub::DeviceReduce::Max(nullptr, rbytes, ucol, mx_d, (int)bnnz, s));
+    if ((st = tmp.get(&mx_d, 1)) || (st = tmp.get(&red_tmp, rbytes))) return st;
+    BRAS_HIP(hipcub::DeviceReduce::Max(red_tmp, rbytes, ucol, mx_d, (int)bnnz, s));
+    BRAS_HIP(hipMemcpyAsync(&maxcol, mx_d, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    BRAS_HIP(hipStreamSynchronize(s));
+  }
+  int cbits = 1;
+  while (cbits < 32 && (maxcol >> cbits) != 0) ++cbits;
+  auto end_bit = [cbits](size_t nb) {
+    int eb = cbits;
+    while (((size_t)1 << (eb - cbits)) < nb) ++eb;
     return eb;
   };
   int64_t cap = 1;
@@ -578,7 +598,7 @@ int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, c
     hipcub::DoubleBuffer<double> vb(v0, v1);
     if (L > 0) {
       k_long_expand<FILL><<<grid_of(nb, 16), 64, 0, s>>>(nb, rows_d, off_d, a_rp, a_col, a_val, b_rp, b_col, b_val,
-                                                          k0, v0);
+                                                          k0, v0, cbits);
       BRAS_HIP(hipGetLastError());
       size_t have = bytes;
       if (FILL)
@@ -587,7 +607,7 @@ int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, c
         BRAS_HIP(hipcub::DeviceRadixSort::SortKeys(cub_tmp, have, kb, (int)L, 0, end_bit(nb), s));
     }
     k_long_runs<FILL><<<grid_of(nb, 16), 64, 0, s>>>(m, nb, rows_d, off_d, kb.Current(), FILL ? vb.Current() : nullptr,
-                                                      cnt, c_rp, c_col, c_val, flag_d);
+                                                      cnt, c_rp, c_col, c_val, flag_d, cbits);
     BRAS_HIP(hipGetLastError());
     BRAS_HIP(hipStreamSynchronize(s));   // the next batch reuses the buffers and the host lists stay valid
   }
