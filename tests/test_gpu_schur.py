@@ -250,9 +250,9 @@ def ordered_product(A, B):
 
 def cap_case():
     """B (6000 x 4000): rows 0..1999 of 32 seeded columns, row 2999 of one,
-    the rest empty.  Rows of A at and past the LDS variants' limits: 1024
-    candidates (half-LDS variant), 1056 and 2048 (full), 1509 entries with
-    320 candidates (full, by entries), 2049 candidates, 2120 entries with 640
+    the rest empty.  Rows of A at and past the LDS variants' limits (1024
+    and 2048 candidates or entries): 1024 candidates, 1056, 2048, 1509
+    entries with 320 candidates, 2049 candidates, 2120 entries with 640
     candidates and the same row without its empty B rows, 2100 entries all
     selecting empty B rows, 22400 candidates, an empty row, a short row."""
     k, n = 6000, 4000
