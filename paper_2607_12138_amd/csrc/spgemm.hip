@@ -46,13 +46,13 @@ int lds_max() {
 // Bitonic sort of key[0 .. m2) (m2 a power of two, at most kGemmCap) by one
 // wavefront: every stage first loads all of this lane's pairs, then
 // compares and stores, so a stage costs one LDS round trip, not one per pair.
-template <int CAP>
-__device__ inline void wave_bitonic(uint64_t* key, int m2) {
+template <int CAP, typename K>
+__device__ inline void wave_bitonic(K* key, int m2) {
   constexpr int kPer = CAP / 64;
   const int t = threadIdx.x;
   for (int kk = 2; kk <= m2; kk <<= 1)
     for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-      uint64_t xa[kPer], xb[kPer];
+      K xa[kPer], xb[kPer];
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int q = t + 64 * u, pq = q ^ jj;
@@ -78,14 +78,19 @@ __device__ inline void wave_bitonic(uint64_t* key, int m2) {
 // CAP = kGemmCap takes exactly those others.  Malformed rows raise flag[0];
 // rows beyond lmax (A entries or candidates) are left to the sort in device
 // memory, and the small variant raises flag[2] for them.
-template <int CAP, int FILL>
+template <int CAP, int FILL, typename K>
 __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64_t* __restrict__ a_rp,
                                                const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
                                                const int64_t* __restrict__ b_rp, const int32_t* __restrict__ b_col,
                                                const double* __restrict__ b_val, int32_t* __restrict__ cnt,
                                                const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
                                                double* __restrict__ c_val, int* __restrict__ flag, int lmax) {
-  __shared__ uint64_t key[CAP];      // (column << 32) | candidate index, sorted
+  // (column << SH) | candidate index, sorted: 32-bit keys when every column
+  // of B fits in 32 - SH bits (the host decides), else 64-bit
+  constexpr int SH = sizeof(K) == 8 ? 32 : (CAP == 1024 ? 10 : 11);
+  static_assert(sizeof(K) == 8 || (1 << SH) >= CAP, "candidate index bits");
+  constexpr K kQmask = (K)(((uint64_t)1 << SH) - 1);
+  __shared__ K key[CAP];
   __shared__ int32_t pre[CAP + 1];   // prefix sums of the selected B row lengths
   __shared__ int32_t bst[CAP];       // start of each selected B row
   __shared__ int16_t own[CAP];       // the A entry (index in the row) of each candidate
@@ -163,21 +168,21 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
       for (int q = pre[p]; q < pre[p + 1]; ++q) own[q] = (int16_t)p;
     __syncthreads();
     for (int q = t; q < m2; q += 64) {
-      uint64_t kv = ~0ull;
+      K kv = ~(K)0;
       if (q < mt) {
         const int pa = own[q];
         const uint32_t cj = (uint32_t)b_col[(int64_t)bst[pa] + (q - pre[pa])];
-        kv = ((uint64_t)cj << 32) | (uint32_t)q;
+        kv = ((K)cj << SH) | (K)q;
       }
       key[q] = kv;
     }
     __syncthreads();
-    wave_bitonic<CAP>(key, m2);
+    wave_bitonic<CAP, K>(key, m2);
     // distinct columns: the heads of runs of equal column
     int u = 0;
     for (int q0 = 0; q0 < mt; q0 += 64) {
       const int q = q0 + t;
-      const bool head = q < mt && (q == 0 || (key[q] >> 32) != (key[q - 1] >> 32));
+      const bool head = q < mt && (q == 0 || (key[q] >> SH) != (key[q - 1] >> SH));
       u += __popcll(__ballot(head));
     }
     if (!FILL) {
@@ -194,7 +199,7 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
     }
     // products of every candidate (independent loads), in sorted order
     for (int r = t; r < mt; r += 64) {
-      const int q = (int)(uint32_t)key[r];
+      const int q = (int)(key[r] & kQmask);
       const int pa = own[q];
       prod[r] = a_val[p0 + pa] * b_val[(int64_t)bst[pa] + (q - pre[pa])];
     }
@@ -203,12 +208,12 @@ __global__ void __launch_bounds__(64) k_spgemm(int64_t m, int64_t k, const int64
     int base = 0;
     for (int q0 = 0; q0 < mt; q0 += 64) {
       const int q = q0 + t;
-      const bool head = q < mt && (q == 0 || (key[q] >> 32) != (key[q - 1] >> 32));
+      const bool head = q < mt && (q == 0 || (key[q] >> SH) != (key[q - 1] >> SH));
       const uint64_t mask = __ballot(head);
       if (head) {
-        const uint64_t cbits = key[q] >> 32;
+        const K cbits = key[q] >> SH;
         double s = prod[q];
-        for (int r = q + 1; r < mt && (key[r] >> 32) == cbits; ++r) s += prod[r];
+        for (int r = q + 1; r < mt && (key[r] >> SH) == cbits; ++r) s += prod[r];
         const int64_t at = o + base + __popcll(mask & ((1ull << t) - 1ull));
         c_col[at] = (int32_t)(uint32_t)cbits;
         c_val[at] = s;
@@ -441,7 +446,9 @@ __global__ void __launch_bounds__(256) k_csr_add(int64_t m, const int64_t* __res
 template <int FILL>
 int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
               const int64_t* b_rp, const int32_t* b_col, const double* b_val, int32_t* cnt, const int64_t* c_rp,
-              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int lmax, int* bad);
+              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int lmax, uint32_t maxcol, int* bad);
+
+int max_col(int64_t k, const int64_t* b_rp, const int32_t* b_col, hipStream_t s, uint32_t* out);
 
 template <int FILL>
 int spgemm_pass(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
@@ -450,21 +457,34 @@ int spgemm_pass(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col,
   int hf[3] = {0, 0, 0};
   BRAS_HIP(hipMemsetAsync(flag_d, 0, 3 * sizeof(int), s));
   const int lmax = lds_max();
-  k_spgemm<kGemmSmall, FILL><<<grid_of(m, 32), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp,
-                                                            c_col, c_val, flag_d, lmax);
+  uint32_t maxcol = 0;
+  int st = max_col(k, b_rp, b_col, s, &maxcol);
+  if (st) return st;
+  // 32-bit LDS keys when (column << index bits) | index stays below the
+  // padding key 2^32 - 1 for every column
+  if (maxcol < (1u << 22) - 1u)
+    k_spgemm<kGemmSmall, FILL, uint32_t><<<grid_of(m, 32), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val,
+                                                                      cnt, c_rp, c_col, c_val, flag_d, lmax);
+  else
+    k_spgemm<kGemmSmall, FILL, uint64_t><<<grid_of(m, 32), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val,
+                                                                      cnt, c_rp, c_col, c_val, flag_d, lmax);
   BRAS_HIP(hipGetLastError());
   BRAS_HIP(hipMemcpyAsync(hf, flag_d, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   BRAS_HIP(hipStreamSynchronize(s));
   if (!hf[0] && hf[1]) {
-    k_spgemm<kGemmCap, FILL><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp,
-                                                            c_col, c_val, flag_d, lmax);
+    if (maxcol < (1u << 21) - 1u)
+      k_spgemm<kGemmCap, FILL, uint32_t><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val,
+                                                                      cnt, c_rp, c_col, c_val, flag_d, lmax);
+    else
+      k_spgemm<kGemmCap, FILL, uint64_t><<<grid_of(m, 16), 64, 0, s>>>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val,
+                                                                      cnt, c_rp, c_col, c_val, flag_d, lmax);
     BRAS_HIP(hipGetLastError());
     BRAS_HIP(hipMemcpyAsync(hf, flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
     BRAS_HIP(hipStreamSynchronize(s));
   }
   if (!hf[0] && hf[2])
     return long_rows<FILL>(m, k, a_rp, a_col, a_val, b_rp, b_col, b_val, cnt, c_rp, c_col, c_val, flag_d, s, lmax,
-                           bad);
+                           maxcol, bad);
   *bad = hf[0];
   return BRAS_OK;
 }
@@ -495,6 +515,28 @@ struct DevBufs {
   }
 };
 
+// The widest column of B, as unsigned (0 for an empty B).
+int max_col(int64_t k, const int64_t* b_rp, const int32_t* b_col, hipStream_t s, uint32_t* out) {
+  int64_t bnnz = 0;
+  BRAS_HIP(hipMemcpyAsync(&bnnz, b_rp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  *out = 0;
+  if (bnnz <= 0) return BRAS_OK;
+  BRAS_CHECK(bnnz < (1LL << 31), "B has %lld entries; at most 2^31 - 1 are supported", (long long)bnnz);
+  DevBufs tmp;
+  uint32_t* mx_d = nullptr;
+  char* red_tmp = nullptr;
+  size_t rbytes = 0;
+  int st;
+  const uint32_t* ucol = reinterpret_cast<const uint32_t*>(b_col);
+  BRAS_HIP(hipcub::DeviceReduce::Max(nullptr, rbytes, ucol, mx_d, (int)bnnz, s));
+  if ((st = tmp.get(&mx_d, 1)) || (st = tmp.get(&red_tmp, rbytes))) return st;
+  BRAS_HIP(hipcub::DeviceReduce::Max(red_tmp, rbytes, ucol, mx_d, (int)bnnz, s));
+  BRAS_HIP(hipMemcpyAsync(out, mx_d, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  return BRAS_OK;
+}
+
 constexpr int64_t kLongBatch = (int64_t)1 << 27;   // candidates sorted at once (32 bytes each when filling)
 
 // BRAS_SPGEMM_BATCH (a positive integer) replaces kLongBatch: less device
@@ -512,7 +554,7 @@ int64_t long_batch() {
 template <int FILL>
 int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
               const int64_t* b_rp, const int32_t* b_col, const double* b_val, int32_t* cnt, const int64_t* c_rp,
-              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int lmax, int* bad) {
+              int32_t* c_col, double* c_val, int* flag_d, hipStream_t s, int lmax, uint32_t maxcol, int* bad) {
   DevBufs tmp;
   int64_t* len = nullptr;
   int st, hf = 0;
@@ -541,21 +583,6 @@ int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, c
     offs.back().push_back(offs.back().back() + hl[i]);
   }
   // key bits: the widest column of B (unsigned), then the row in the batch
-  int64_t bnnz = 0;
-  BRAS_HIP(hipMemcpyAsync(&bnnz, b_rp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  BRAS_HIP(hipStreamSynchronize(s));
-  uint32_t maxcol = 0;
-  if (bnnz > 0) {
-    uint32_t* mx_d = nullptr;
-    char* red_tmp = nullptr;
-    size_t rbytes = 0;
-    const uint32_t* ucol = reinterpret_cast<const uint32_t*>(b_col);
-    BRAS_HIP(hipcub::DeviceReduce::Max(nullptr, rbytes, ucol, mx_d, (int)bnnz, s));
-    if ((st = tmp.get(&mx_d, 1)) || (st = tmp.get(&red_tmp, rbytes))) return st;
-    BRAS_HIP(hipcub::DeviceReduce::Max(red_tmp, rbytes, ucol, mx_d, (int)bnnz, s));
-    BRAS_HIP(hipMemcpyAsync(&maxcol, mx_d, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    BRAS_HIP(hipStreamSynchronize(s));
-  }
   int cbits = 1;
   while (cbits < 32 && (maxcol >> cbits) != 0) ++cbits;
   auto end_bit = [cbits](size_t nb) {

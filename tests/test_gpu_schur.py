@@ -279,16 +279,22 @@ def cap_case():
     return A, B, k, n
 
 
+@pytest.mark.parametrize("shift", [0, 2095000, 4190400])
 @pytest.mark.parametrize("lds_max", ["", "2048", "0"])
-def test_spgemm_candidate_cap_boundaries(lds_max, monkeypatch):
+def test_spgemm_candidate_cap_boundaries(lds_max, shift, monkeypatch):
     """Rows at and past the LDS variants' limits against the candidate-order
     sums, bit for bit, with the default LDS limit (1024: the half-LDS variant
     and the sort in device memory), with 2048 (both LDS variants, the sort
     past 2048) and with 0 (every non-empty row sorted in device memory); a
     row whose extra entries select only empty B rows gives the same row as
-    without them."""
+    without them.  B's columns shifted up so that the LDS keys are 32-bit in
+    both variants (0), 32-bit in the 1024 variant only (2095000: columns
+    past 2^21) or 64-bit in both (4190400: columns past 2^22)."""
     from paper_2607_12138_amd.problem import spgemm
     A, B, k, n = cap_case()
+    if shift:
+        B = sp.csr_matrix((B.data, B.indices + shift, B.indptr), shape=(k, n + shift))
+        n += shift
     if lds_max:
         monkeypatch.setenv("BRAS_SPGEMM_LDS_MAX", lds_max)
     bl = np.diff(B.indptr)
@@ -300,8 +306,10 @@ def test_spgemm_candidate_cap_boundaries(lds_max, monkeypatch):
     assert np.array_equal(Cg.indptr, Cr.indptr) and np.array_equal(Cg.indices, Cr.indices)
     assert np.array_equal(Cg.data, Cr.data)
     assert Cg.indptr[8] == Cg.indptr[7]          # 2100 entries, no candidates
-    assert np.array_equal(Cg[5].toarray(), Cg[6].toarray())
-    assert np.abs((Cg - A @ B).toarray()).max() <= 1e-13 * (abs(A) @ abs(B)).toarray().max()
+    assert np.array_equal(Cg.indices[Cg.indptr[5]:Cg.indptr[6]], Cg.indices[Cg.indptr[6]:Cg.indptr[7]])
+    assert np.array_equal(Cg.data[Cg.indptr[5]:Cg.indptr[6]], Cg.data[Cg.indptr[6]:Cg.indptr[7]])
+    if not shift:
+        assert np.abs((Cg - A @ B).toarray()).max() <= 1e-13 * (abs(A) @ abs(B)).toarray().max()
 
 
 @pytest.mark.parametrize("batch", ["1", "2100", "25000"])
