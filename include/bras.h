@@ -282,8 +282,8 @@ int bras_csr_jacobi(bras_handle h, int64_t* rowptr_d, int32_t* col_d, double* va
  * result for every launch shape.  A row's candidate products are the sum
  * over its entries of the selected B row lengths; rows with at most 1024 of
  * them and at most 1024 entries are formed in LDS, longer rows through a
- * sort in device memory, in batches of at most 2^27 candidates (16 bytes
- * each for the row pointers, 32 for the fill; a row longer than a batch
+ * sort in device memory, in batches of at most 2^27 candidates (8 bytes
+ * each for the row pointers, 24 for the fill; a row longer than a batch
  * forms one alone, below 2^31 candidates).  Both routes give the same sums.
  * Environment: BRAS_SPGEMM_BATCH (a positive integer) sets another batch
  * size; BRAS_SPGEMM_LDS_MAX (0 .. 2048) another limit for the LDS route.  EINVAL when

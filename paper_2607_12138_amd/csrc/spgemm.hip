@@ -270,11 +270,11 @@ __global__ void __launch_bounds__(256) k_col_starts(int64_t n, const int32_t* __
 }
 
 // Rows of C = A B past the LDS limit (A entries or candidate products): their
-// candidates are written to device memory keyed (row in the batch, column),
-// sorted by a stable radix sort over the bits the keys use (the widest
-// column of B, then the batch's row count), so each column's products keep their
-// candidate order, and each run of equal keys is summed in that order: the
-// same result, bit for bit, as the LDS variants give a shorter row.
+// candidates are written to device memory keyed by column, one segment per
+// row, sorted by a stable segmented radix sort over the bits the widest
+// column of B uses, so each column's products keep their candidate order,
+// and each run of equal keys is summed in that order: the same result, bit
+// for bit, as the LDS variants give a shorter row.
 
 // One thread per row of A: validation in full, and len[i] = the candidate
 // count of a long row (0 included), -1 for the other rows.
@@ -307,15 +307,14 @@ __global__ void __launch_bounds__(256) k_long_len(int64_t m, int64_t k, const in
 }
 
 // One wavefront per row of the batch: row rows[r]'s candidates, in candidate
-// order, at off[r] .. off[r+1): key (r << cbits) | column, value the product
-// (every column of B below 2^cbits).
+// order, at off[r] .. off[r+1): key the column, value the product.
 template <int FILL>
 __global__ void __launch_bounds__(64) k_long_expand(int nb, const int32_t* __restrict__ rows,
                                                     const int64_t* __restrict__ off, const int64_t* __restrict__ a_rp,
                                                     const int32_t* __restrict__ a_col, const double* __restrict__ a_val,
                                                     const int64_t* __restrict__ b_rp, const int32_t* __restrict__ b_col,
-                                                    const double* __restrict__ b_val, uint64_t* __restrict__ key,
-                                                    double* __restrict__ val, int cbits) {
+                                                    const double* __restrict__ b_val, uint32_t* __restrict__ key,
+                                                    double* __restrict__ val) {
   const int t = threadIdx.x;
   for (int r = blockIdx.x; r < nb; r += gridDim.x) {
     const int64_t i = rows[r], p1 = a_rp[i + 1], end = off[r + 1];
@@ -325,7 +324,7 @@ __global__ void __launch_bounds__(64) k_long_expand(int nb, const int32_t* __res
       const int64_t b0 = b_rp[a], n = b_rp[a + 1] - b0;
       const double av = FILL ? a_val[p] : 0.0;
       for (int64_t q = t; q < n && at + q < end; q += 64) {
-        key[at + q] = ((uint64_t)(uint32_t)r << cbits) | (uint32_t)b_col[b0 + q];
+        key[at + q] = (uint32_t)b_col[b0 + q];
         if (FILL) val[at + q] = av * b_val[b0 + q];
       }
       at += n;
@@ -339,12 +338,11 @@ __global__ void __launch_bounds__(64) k_long_expand(int nb, const int32_t* __res
 // flag and writes nothing.
 template <int FILL>
 __global__ void __launch_bounds__(64) k_long_runs(int64_t m, int nb, const int32_t* __restrict__ rows,
-                                                  const int64_t* __restrict__ off, const uint64_t* __restrict__ key,
+                                                  const int64_t* __restrict__ off, const uint32_t* __restrict__ key,
                                                   const double* __restrict__ val, int32_t* __restrict__ cnt,
                                                   const int64_t* __restrict__ c_rp, int32_t* __restrict__ c_col,
-                                                  double* __restrict__ c_val, int* __restrict__ flag, int cbits) {
+                                                  double* __restrict__ c_val, int* __restrict__ flag) {
   const int t = threadIdx.x;
-  const uint64_t cmask = (1ull << cbits) - 1ull;
   for (int r = blockIdx.x; r < nb; r += gridDim.x) {
     const int64_t i = rows[r], q0 = off[r], q1 = off[r + 1];
     int64_t u = 0;
@@ -367,11 +365,11 @@ __global__ void __launch_bounds__(64) k_long_runs(int64_t m, int nb, const int32
       const bool head = q < q1 && (q == q0 || key[q] != key[q - 1]);
       const uint64_t mask = __ballot(head);
       if (head) {
-        const uint64_t kq = key[q];
+        const uint32_t kq = key[q];
         double sum = val[q];
         for (int64_t x = q + 1; x < q1 && key[x] == kq; ++x) sum += val[x];
         const int64_t at = o + base + __popcll(mask & ((1ull << t) - 1ull));
-        c_col[at] = (int32_t)(uint32_t)(kq & cmask);
+        c_col[at] = (int32_t)kq;
         c_val[at] = sum;
       }
       base += __popcll(mask);
@@ -537,7 +535,7 @@ int max_col(int64_t k, const int64_t* b_rp, const int32_t* b_col, hipStream_t s,
   return BRAS_OK;
 }
 
-constexpr int64_t kLongBatch = (int64_t)1 << 27;   // candidates sorted at once (32 bytes each when filling)
+constexpr int64_t kLongBatch = (int64_t)1 << 27;   // candidates sorted at once (24 bytes each when filling)
 
 // BRAS_SPGEMM_BATCH (a positive integer) replaces kLongBatch: less device
 // memory per call, more sorts.
@@ -548,8 +546,8 @@ int64_t long_batch() {
 }
 
 // The rows past kGemmCap, in row order, in batches of at most long_batch()
-// candidates (a longer row alone): expand, stable radix sort over the bits
-// the keys use, runs.  *bad: a malformed row (or, when filling, an output
+// candidates (a longer row alone): expand, stable segmented radix sort
+// (one segment per row), runs.  *bad: a malformed row (or, when filling, an output
 // row of the wrong length).
 template <int FILL>
 int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, const double* a_val,
@@ -582,14 +580,9 @@ int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, c
     rows.back().push_back((int32_t)i);
     offs.back().push_back(offs.back().back() + hl[i]);
   }
-  // key bits: the widest column of B (unsigned), then the row in the batch
+  // key bits: the widest column of B (unsigned); one segment per row
   int cbits = 1;
   while (cbits < 32 && (maxcol >> cbits) != 0) ++cbits;
-  auto end_bit = [cbits](size_t nb) {
-    int eb = cbits;
-    while (((size_t)1 << (eb - cbits)) < nb) ++eb;
-    return eb;
-  };
   int64_t cap = 1;
   size_t maxnb = 1, bytes = 0;
   for (size_t b = 0; b < rows.size(); ++b) {
@@ -599,20 +592,25 @@ int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, c
     cap = L > cap ? L : cap;
     maxnb = rows[b].size() > maxnb ? rows[b].size() : maxnb;
     size_t need = 0;
-    hipcub::DoubleBuffer<uint64_t> kq(nullptr, nullptr);
+    hipcub::DoubleBuffer<uint32_t> kq(nullptr, nullptr);
     hipcub::DoubleBuffer<double> vq(nullptr, nullptr);
+    const int ns = (int)rows[b].size();
     if (FILL)
-      BRAS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kq, vq, (int)L, 0, end_bit(rows[b].size()), s));
+      BRAS_HIP(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, need, kq, vq, (int)L, ns, (const int*)nullptr,
+                                                           (const int*)nullptr, 0, cbits, s));
     else
-      BRAS_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, need, kq, (int)L, 0, end_bit(rows[b].size()), s));
+      BRAS_HIP(hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, need, kq, (int)L, ns, (const int*)nullptr,
+                                                          (const int*)nullptr, 0, cbits, s));
     bytes = need > bytes ? need : bytes;
   }
   int32_t* rows_d = nullptr;
   int64_t* off_d = nullptr;
-  uint64_t *k0 = nullptr, *k1 = nullptr;
+  int* off32_d = nullptr;
+  uint32_t *k0 = nullptr, *k1 = nullptr;
   double *v0 = nullptr, *v1 = nullptr;
   char* cub_tmp = nullptr;
-  if ((st = tmp.get(&rows_d, maxnb)) || (st = tmp.get(&off_d, maxnb + 1)) || (st = tmp.get(&k0, (size_t)cap)) ||
+  if ((st = tmp.get(&rows_d, maxnb)) || (st = tmp.get(&off_d, maxnb + 1)) || (st = tmp.get(&off32_d, maxnb + 1)) ||
+      (st = tmp.get(&k0, (size_t)cap)) ||
       (st = tmp.get(&k1, (size_t)cap)) || (st = tmp.get(&v0, FILL ? (size_t)cap : 1)) ||
       (st = tmp.get(&v1, FILL ? (size_t)cap : 1)) || (st = tmp.get(&cub_tmp, bytes)))
     return st;
@@ -621,20 +619,24 @@ int long_rows(int64_t m, int64_t k, const int64_t* a_rp, const int32_t* a_col, c
     const int64_t L = offs[b].back();
     BRAS_HIP(hipMemcpyAsync(rows_d, rows[b].data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
     BRAS_HIP(hipMemcpyAsync(off_d, offs[b].data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s));
-    hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
+    std::vector<int> o32(offs[b].begin(), offs[b].end());   // below 2^31 (checked above)
+    BRAS_HIP(hipMemcpyAsync(off32_d, o32.data(), sizeof(int) * (nb + 1), hipMemcpyHostToDevice, s));
+    hipcub::DoubleBuffer<uint32_t> kb(k0, k1);
     hipcub::DoubleBuffer<double> vb(v0, v1);
     if (L > 0) {
       k_long_expand<FILL><<<grid_of(nb, 16), 64, 0, s>>>(nb, rows_d, off_d, a_rp, a_col, a_val, b_rp, b_col, b_val,
-                                                          k0, v0, cbits);
+                                                          k0, v0);
       BRAS_HIP(hipGetLastError());
       size_t have = bytes;
       if (FILL)
-        BRAS_HIP(hipcub::DeviceRadixSort::SortPairs(cub_tmp, have, kb, vb, (int)L, 0, end_bit(nb), s));
+        BRAS_HIP(hipcub::DeviceSegmentedRadixSort::SortPairs(cub_tmp, have, kb, vb, (int)L, nb, off32_d, off32_d + 1,
+                                                             0, cbits, s));
       else
-        BRAS_HIP(hipcub::DeviceRadixSort::SortKeys(cub_tmp, have, kb, (int)L, 0, end_bit(nb), s));
+        BRAS_HIP(hipcub::DeviceSegmentedRadixSort::SortKeys(cub_tmp, have, kb, (int)L, nb, off32_d, off32_d + 1, 0,
+                                                            cbits, s));
     }
     k_long_runs<FILL><<<grid_of(nb, 16), 64, 0, s>>>(m, nb, rows_d, off_d, kb.Current(), FILL ? vb.Current() : nullptr,
-                                                      cnt, c_rp, c_col, c_val, flag_d, cbits);
+                                                      cnt, c_rp, c_col, c_val, flag_d);
     BRAS_HIP(hipGetLastError());
     BRAS_HIP(hipStreamSynchronize(s));   // the next batch reuses the buffers and the host lists stay valid
   }
