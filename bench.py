@@ -149,7 +149,7 @@ def device_copy_gbs(reps=5):
 
 
 def stationary_section(prob, b, w, steps):
-    """Section 4's other solvers on the same system: damped fixed point with
+    """Section 3's other solvers on the same system: damped fixed point with
     omega_bras = 2/(1 + lambda_max) and omega_diag = 1/lambda_max, and the
     Chebyshev semi-iteration on [1, 1.02 lambda_max] with BRAS (lambda_min >= 1,
     Cor. bras_lambda_min).  lambda_max by 200 power iterations from a seeded
@@ -198,7 +198,7 @@ def assembled_section(prob, x, y, bras_us, reps):
 
 
 def schur_section(prob, w, reps=3):
-    """Section 5's sparse Schur-complement approximation -St = G M_bras^-1 G^T
+    """Section 4's sparse Schur-complement approximation -St = G M_bras^-1 G^T
     (eq. approx_positive_schur_general, C = 0) for a coupling G with one row per
     element holding its DOFs (the pattern of a discrete divergence or gradient
     on the cells) with seeded U[-1,1] values: the assembled BRAS operator, then

@@ -43,7 +43,7 @@ extern "C" {
 #define BRAS_EBREAKDOWN -5   /* PCG breakdown: p.q <= 0, r.z <= 0, NaN / Inf  */
 #define BRAS_ENOMEM     -6   /* device allocation failed                      */
 
-/* ---- element families (Section 4: Lagrange, Bernstein, N1curl, N2curl, RT, BDM) */
+/* ---- element families (Section 3: Lagrange, Bernstein, N1curl, N2curl, RT, BDM) */
 #define BRAS_H1    0         /* H1 Lagrange P_p, GLL-based nodes             */
 #define BRAS_HCURL 1         /* first-kind Nedelec N1curl_k, covariant Piola */
 #define BRAS_HDIV  2         /* Raviart-Thomas RT_k, contravariant Piola     */
@@ -187,18 +187,23 @@ int jacobi_apply(bras_handle h, const double* x_d, double* y_d, int nrhs, void* 
  * the solution on exit.  Column c stops when ||r_k||_2 / ||r_0||_2 <= rtol
  * (r_k the recursive residual, r_0 = b - M x_0) or after maxit products M p.
  * When the stored inverses are FP32 / BF16, the iteration uses the flexible
- * beta and, at exit, restarts from x while the true residual exceeds rtol.
+ * beta.  At exit the true residual b - M x is recomputed; while it exceeds
+ * rtol ||r_0|| in a column, the iteration restarts from x (iterative
+ * refinement, at most BRAS_OPT_MAX_RESTART times, default 8; the products
+ * of every restart count in iters_h).
  * iters_h[nrhs]: products M p per column; relres_h[nrhs]: final true
  * ||b - M x|| / ||r_0|| (host, may be NULL).  Blocking.  Returns ENOCONV if a
- * column did not converge and EBREAKDOWN on breakdown; x_d, iters_h and
- * relres_h are written in every case.
+ * column did not reach rtol within maxit products, or if its final true
+ * residual is still above rtol after the restarts, and EBREAKDOWN on
+ * breakdown; x_d, iters_h and relres_h are written in every case.
  * Small problems (SCALED_REF form with n_loc of degree 1-4 H1 elements,
  * FP64, nrhs = 1, n <= 2048, 16 n + 10 n_br <= 160000, at most 1024 times
  * 2 elements (3 for n_loc 4, 1 for n_loc 20 and 35), maxit <= 100000) run
  * the whole iteration in one work-group kernel with its vectors in LDS and
  * registers, unless BRAS_OPT_SMALL_CG is 0; the operators, iteration,
  * stopping test and outputs are the same, dot products are summed in
- * another fixed order.  BRAS_INFO_SOLVE_PATH reports which path the last
+ * another fixed order, and there is no restart (a final true residual above
+ * rtol returns ENOCONV).  BRAS_INFO_SOLVE_PATH reports which path the last
  * call took. */
 int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, int nrhs,
               double rtol, int maxit, int* iters_h, double* relres_h, void* stream);
@@ -267,7 +272,7 @@ int bras_csr_apply(int64_t n, const int64_t* rowptr_d, const int32_t* col_d, con
  * = 1 / M_ii.  Asynchronous on the stream. */
 int bras_csr_jacobi(bras_handle h, int64_t* rowptr_d, int32_t* col_d, double* val_d, void* stream);
 
-/* ---- sparse products for Schur-complement approximations (Section 5:
+/* ---- sparse products for Schur-complement approximations (Section 4:
  * -St = C + G Mt^-1 G^T, eq. approx_positive_schur_general, sparse when Mt^-1
  * is the assembled M_bras^-1; formed as (G M_bras^-1) G^T, then + C, with
  * these calls) -------------------------------------------------------------
@@ -313,7 +318,11 @@ int bras_csr_add_fill(int64_t m, const int64_t* a_rowptr_d, const int32_t* a_col
                       const int64_t* b_rowptr_d, const int32_t* b_col_d, const double* b_val_d,
                       const int64_t* c_rowptr_d, int32_t* c_col_d, double* c_val_d, void* stream);
 
-#define BRAS_OPT_GRAPH_ITERS 0  /* CG iterations per captured graph (>= 1)     */
+#define BRAS_OPT_GRAPH_ITERS 0  /* most CG (or stationary) iterations launched
+                                   between two host checks of the convergence
+                                   flags, 1..32 (default 32); the launcher
+                                   predicts the count from the observed rate
+                                   and never exceeds this cap              */
 #define BRAS_OPT_MAX_RESTART 1  /* refinement restarts allowed (>= 0)         */
 #define BRAS_OPT_VARIANT     2  /* force a scheduling variant (-1 = built-in)  */
 #define BRAS_OPT_SMALL_CG    3  /* 1 (default): single work-group pcg_solve,
@@ -322,12 +331,12 @@ int bras_csr_add_fill(int64_t m, const int64_t* a_rowptr_d, const int32_t* a_col
 int bras_set_option(bras_handle h, int opt, double value);
 
 /* ======================================================================== *
- * Stationary iterations with the same operators (Section 4).
+ * Stationary iterations with the same operators (Section 3).
  * ======================================================================== */
 
 /* Power-iteration estimate of lambda_max(C M), C = BRAS (pc = BRAS_PC_BRAS)
  * or diag(M)^-1 (BRAS_PC_JACOBI), used for the fixed-point weights of
- * Section 4 (omega_diag = 1/lambda_max, omega_bras = 2/(1 + lambda_max)):
+ * Section 3 (omega_diag = 1/lambda_max, omega_bras = 2/(1 + lambda_max)):
  * v_0 = v0/||v0||; for k = 1..iters: q = M v, w = C q, lambda = q.w / q.v,
  * v = w/||w||.  v0_d: [n] float64 (device, not modified).  The estimate is a
  * Rayleigh quotient of the M-self-adjoint C M, so it never exceeds
@@ -336,7 +345,7 @@ int bras_set_option(bras_handle h, int opt, double value);
 int bras_lambda_max(bras_handle h, int pc, const double* v0_d, int iters, double* lambda_h, void* stream);
 
 /* Damped fixed-point iteration u_{k+1} = u_k + omega C (f - M u_k)
- * (Section 4) from u_0 = x_d, for every column independently; stops when
+ * (Section 3) from u_0 = x_d, for every column independently; stops when
  * ||f - M u_k||_2 <= rtol ||f - M u_0||_2 (iters_h = k, the number of
  * updates) or after maxit updates (ENOCONV).  pc: BRAS_PC_JACOBI or
  * BRAS_PC_BRAS.  Arguments and results as pcg_solve, including the single
@@ -344,7 +353,7 @@ int bras_lambda_max(bras_handle h, int pc, const double* v0_d, int iters, double
 int fixed_point_solve(bras_handle h, int pc, double omega, const double* b_d, double* x_d, int nrhs,
                       double rtol, int maxit, int* iters_h, double* relres_h, void* stream);
 
-/* Chebyshev semi-iteration for C M on the interval [lmin, lmax] (Section 4
+/* Chebyshev semi-iteration for C M on the interval [lmin, lmax] (Section 3
  * recommends Chebyshev with the BRAS spectral interval, lmin = 1 by Cor.
  * bras_lambda_min): d_0 = C r_0 / theta; rho_0 = 1/sigma; rho_k = 1/(2 sigma -
  * rho_{k-1}); d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k/delta) C r_k;

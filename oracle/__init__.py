@@ -25,7 +25,7 @@ Wimmer), in plain, slow, obviously checkable NumPy/SciPy in float64:
   pcg       textbook preconditioned conjugate gradients with the paper's
             stopping rule (Section 3).
   stationary damped fixed point, Chebyshev iteration and the power iteration
-            for lambda_max (Section 4).
+            for lambda_max (Section 3).
   spectral  dense eigen-checks used as pins: kappa-hat (eq. spectral-kappa),
             Lemma bras_exact_inverse_correction, Cor. bras_lambda_min,
             Thm. bras_lambda_max_projector, Cor. bras_piola_metric_contrast.

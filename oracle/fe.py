@@ -16,7 +16,7 @@ Families (Section 3 names them after Firedrake; the readings used here):
 * "RT"     Raviart-Thomas RT_k = [P_{k-1}]^d + x P~_{k-1}, integral moments.
 * "N2curl" second-kind Nedelec, the full space [P_k]^d (covariant Piola).
 * "BDM"    Brezzi-Douglas-Marini, the full space [P_k]^d (contravariant Piola).
-* "B"      H1 P_p in the Bernstein basis (Section 4, Table h1_mass_solve):
+* "B"      H1 P_p in the Bernstein basis (Section 3, Table h1_mass_solve):
            B_alpha = p!/(alpha_0! ... alpha_d!) lambda_0^alpha_0 ... lambda_d^alpha_d
            over barycentric multi-indices |alpha| = p, lambda_0 = 1 - sum x_i,
            lambda_i = x_i.  A function whose multi-index vanishes off a

@@ -1,5 +1,5 @@
 """Schur-complement approximations built from an approximate mass inverse
-(Section 5, block preconditioning).
+(Section 4, block preconditioning).
 
 Test infrastructure: a plain SciPy statement of what the library's sparse
 products compute.

@@ -1,10 +1,10 @@
 """Damped fixed-point iteration, Chebyshev iteration and the power iteration
-that sets their parameters (Section 4, mass-solve numerics).
+that sets their parameters (Section 3, mass-solve numerics).
 
 Test infrastructure: a plain NumPy statement of what the library's stationary
 solvers compute.
 
-Fixed point (Section 4):  u_{k+1} = u_k + omega C (f - M u_k), C in
+Fixed point (Section 3):  u_{k+1} = u_k + omega C (f - M u_k), C in
 {diag(M)^-1, M_bras^-1}.  Weights used in the paper:
     omega_diag = 1 / lambda_max(C M),
     omega_bras = 2 / (1 + lambda_max(C M))   (lambda_min >= 1, Cor. bras_lambda_min).

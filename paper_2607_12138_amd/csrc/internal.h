@@ -46,7 +46,7 @@ struct Ctx {
   int nl = 0;
   int form = 0, nsym = 0, prec = 0, max_rhs = 1;
   int variant = -1;          // element-pass scheduling variant (-1: built-in choice)
-  int graph_iters = 8;
+  int graph_iters = 32;      // most CG / stationary iterations launched between two host checks
   int max_restart = 8;
   int small_cg = 1;          // solve eligible small problems in one work-group (pcg_small.hip)
   int last_path = 0;         // path of the last pcg_solve: 0 multi-pass, 1 one work-group

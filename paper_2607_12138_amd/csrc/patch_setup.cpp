@@ -1,0 +1,214 @@
+// Host set-up of the patch form of the operator passes (patch.hip).
+//
+// Elements are grouped into patches of at most P elements (one work-group
+// each) by greedy graph growing over the element graph of the local-to-global
+// map (two elements are neighbours when they share a DOF): a patch starts at
+// the lowest-numbered unassigned element and repeatedly takes the unassigned
+// neighbour with the most DOF copies already in the patch, which keeps
+// patches compact, so that most of their DOFs have every broken copy inside.
+// The library then numbers elements patch by patch (all element-indexed data
+// follow that internal order).
+//
+// For each patch the plan lists its DOFs (those whose copies all lie in the
+// patch first, then the shared ones, each group in increasing DOF order) and,
+// for each broken copy (K, l), a code = j | rank << lbits: j the copy's DOF in
+// the patch list and rank its position among that DOF's copies of the patch,
+// counted in element order.  The element pass adds copies of rank 0, 1, ...
+// in turn, so each DOF's copies are summed in one fixed order without float
+// atomics.  A shared DOF gets one partial sum per patch; the partials are
+// summed in patch order by a second pass over the shared DOFs.
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "patch.h"
+
+namespace bras {
+
+namespace {
+
+// Max-gain bucket queue with lazy deletion; within a bucket the most
+// recently pushed entry is taken first (a fixed, data-dependent order).
+struct BucketQueue {
+  std::vector<std::vector<int32_t>> b;
+  int top = -1;
+  void push(int g, int32_t k) {
+    if (g >= (int)b.size()) b.resize(g + 1);
+    b[g].push_back(k);
+    if (g > top) top = g;
+  }
+  void clear() {
+    for (auto& v : b) v.clear();
+    top = -1;
+  }
+};
+
+}  // namespace
+
+int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int32_t* mult, int P, int Dmax,
+                     PatchPlan* plan) {
+  if (P < 1 || Dmax < nl) return 1;
+  // DOF -> elements (CSR)
+  std::vector<int64_t> drp(n + 1, 0);
+  for (int64_t q = 0; q < E * nl; ++q) ++drp[l2g[q] + 1];
+  for (int64_t i = 0; i < n; ++i) drp[i + 1] += drp[i];
+  std::vector<int32_t> del(E * nl);
+  {
+    std::vector<int64_t> fill(drp.begin(), drp.end() - 1);
+    for (int64_t K = 0; K < E; ++K)
+      for (int l = 0; l < nl; ++l) del[fill[l2g[K * nl + l]]++] = (int32_t)K;
+  }
+  std::vector<int32_t> part(E, -1);
+  std::vector<int32_t> gain(E, 0);
+  std::vector<int32_t> stamp(n, -1);
+  std::vector<int32_t> touched;
+  BucketQueue bq;
+  plan->perm.clear();
+  plan->perm.reserve(E);
+  plan->pe.assign(1, 0);
+  int64_t next = 0;
+  int32_t np = 0;
+  while (true) {
+    while (next < E && part[next] >= 0) ++next;
+    if (next >= E) break;
+    bq.clear();
+    touched.clear();
+    bq.push(0, (int32_t)next);
+    int cnt = 0, ndof = 0;
+    while (cnt < P) {
+      int32_t K = -1;
+      while (bq.top >= 0 && K < 0) {
+        auto& v = bq.b[bq.top];
+        if (v.empty()) {
+          --bq.top;
+          continue;
+        }
+        const int32_t k = v.back();
+        v.pop_back();
+        if (part[k] < 0 && gain[k] == bq.top) K = k;
+      }
+      if (K < 0) break;   // frontier exhausted: the patch ends small
+      int add = 0;
+      for (int l = 0; l < nl; ++l) add += stamp[l2g[(int64_t)K * nl + l]] != np;
+      if (ndof + add > Dmax) break;
+      part[K] = np;
+      plan->perm.push_back(K);
+      ++cnt;
+      ndof += add;
+      for (int l = 0; l < nl; ++l) {
+        const int32_t g = l2g[(int64_t)K * nl + l];
+        stamp[g] = np;
+        for (int64_t a = drp[g]; a < drp[g + 1]; ++a) {
+          const int32_t K2 = del[a];
+          if (part[K2] >= 0) continue;
+          if (gain[K2] == 0) touched.push_back(K2);
+          ++gain[K2];
+          bq.push(gain[K2], K2);
+        }
+      }
+    }
+    for (int32_t k : touched) gain[k] = 0;
+    plan->pe.push_back((int32_t)plan->perm.size());
+    ++np;
+  }
+  const int64_t npatch = np;
+  plan->npatch = npatch;
+  // per-patch DOF lists and copy codes
+  plan->pd.assign(1, 0);
+  plan->pnl.assign(npatch, 0);
+  plan->pdof.clear();
+  plan->code.assign(E * nl, 0);
+  plan->sbase.assign(npatch + 1, 0);
+  std::vector<int32_t> lj(n, -1);       // DOF -> index in the current patch's first-seen list
+  std::vector<int32_t> seen, cnt_in;    // first-seen DOF list and copy counts
+  std::vector<int32_t> order, jof;
+  int maxd = 0, maxr = 0;
+  std::vector<int64_t> shared_cnt(n, 0);
+  for (int64_t p = 0; p < npatch; ++p) {
+    const int32_t e0 = plan->pe[p], e1 = plan->pe[p + 1], ne = e1 - e0;
+    seen.clear();
+    cnt_in.clear();
+    for (int32_t e = e0; e < e1; ++e) {
+      const int64_t K = plan->perm[e];
+      for (int l = 0; l < nl; ++l) {
+        const int32_t g = l2g[K * nl + l];
+        if (lj[g] < 0) {
+          lj[g] = (int32_t)seen.size();
+          seen.push_back(g);
+          cnt_in.push_back(0);
+        }
+        ++cnt_in[lj[g]];
+      }
+    }
+    const int nd = (int)seen.size();
+    // order: local DOFs (every copy in the patch) by DOF, then shared by DOF
+    order.resize(nd);
+    for (int k = 0; k < nd; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      const bool la = cnt_in[a] == mult[seen[a]], lb = cnt_in[b] == mult[seen[b]];
+      if (la != lb) return la;
+      return seen[a] < seen[b];
+    });
+    jof.assign(nd, 0);
+    int nloc = 0;
+    for (int k = 0; k < nd; ++k) {
+      jof[order[k]] = k;
+      const int32_t g = seen[order[k]];
+      plan->pdof.push_back(g);
+      if (cnt_in[order[k]] == mult[g]) ++nloc;
+      else ++shared_cnt[g];
+    }
+    plan->pnl[p] = nloc;
+    plan->pd.push_back((int32_t)plan->pdof.size());
+    plan->sbase[p + 1] = plan->sbase[p] + (nd - nloc);
+    maxd = std::max(maxd, nd);
+    // ranks in element order
+    std::vector<int32_t> rk(nd, 0);
+    for (int32_t e = e0; e < e1; ++e) {
+      const int64_t K = plan->perm[e];
+      for (int l = 0; l < nl; ++l) {
+        const int32_t g = l2g[K * nl + l];
+        const int32_t j = jof[lj[g]];
+        const int32_t r = rk[j]++;
+        maxr = std::max(maxr, r);
+        // j and r packed once lbits is known: keep (j, r) for now
+        plan->code[(int64_t)e0 * nl + (int64_t)l * ne + (e - e0)] = (uint32_t)j | ((uint32_t)r << 16);
+      }
+    }
+    for (int k = 0; k < nd; ++k) lj[seen[k]] = -1;
+  }
+  // code packing: lbits for j, the rest for the rank
+  int lbits = 1;
+  while ((1 << lbits) < maxd) ++lbits;
+  int rbits = 1;
+  while ((1 << rbits) <= maxr) ++rbits;
+  plan->lbits = lbits;
+  plan->rbits = rbits;
+  plan->maxrank = maxr;
+  plan->maxdofs = maxd;
+  for (auto& cd : plan->code) cd = (cd & 0xFFFFu) | ((cd >> 16) << lbits);
+  // second pass: the shared DOFs in increasing order, each with its partials in patch order
+  plan->srp.assign(1, 0);
+  plan->sdof.clear();
+  std::vector<int64_t> sfirst(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) sfirst[i + 1] = sfirst[i] + shared_cnt[i];
+  plan->spos.assign(sfirst[n], 0);
+  {
+    std::vector<int64_t> fill(sfirst.begin(), sfirst.end() - 1);
+    for (int64_t p = 0; p < npatch; ++p) {
+      const int32_t d0 = plan->pd[p], d1 = plan->pd[p + 1], nloc = plan->pnl[p];
+      for (int32_t j = d0 + nloc; j < d1; ++j) {
+        const int32_t g = plan->pdof[j];
+        plan->spos[fill[g]++] = plan->sbase[p] + (j - d0 - nloc);
+      }
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (shared_cnt[i] > 0) {
+      plan->sdof.push_back((int32_t)i);
+      plan->srp.push_back((int32_t)sfirst[i + 1]);
+    }
+  return 0;
+}
+
+}  // namespace bras

@@ -369,7 +369,7 @@ static int launch_chunk(std::vector<hipGraphExec_t>& graphs, int chunk, hipStrea
 
 // Iterations to launch before the host looks at the flags again: enough to
 // reach the target at the slowest running column's observed rate (1..32).
-static int predict_chunk(CgState* g, int R, int maxit) {
+static int predict_chunk(CgState* g, int R, int maxit, int cap) {
   int any = 0, max_it = 0;
   double worst = 0.0;
   for (int col = 0; col < R; ++col) {
@@ -390,7 +390,7 @@ static int predict_chunk(CgState* g, int R, int maxit) {
   if (!any) return 0;
   int chunk = (int)std::ceil(worst);
   if (chunk < 1) chunk = 1;
-  if (chunk > 32) chunk = 32;
+  if (chunk > cap) chunk = cap;
   if (chunk > maxit - max_it + 1) chunk = maxit - max_it + 1;
   return chunk < 1 ? 1 : chunk;
 }
@@ -445,7 +445,7 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
     if ((st = read_state(c, s))) break;
     // iterate: predict the remaining iterations from the observed rate
     while (true) {
-      const int chunk = predict_chunk(g, R, maxit);
+      const int chunk = predict_chunk(g, R, maxit, c->graph_iters);
       if (chunk == 0) break;
       if ((st = launch_chunk(*graphs, chunk, s))) break;
       if ((st = read_state(c, s))) break;
@@ -461,7 +461,7 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
       if (g->ic_host[I_STATUS * R + col] == ST_OK && g->sc_host[S_RELRES * R + col] > rtol &&
           g->ic_host[I_ITERS * R + col] < maxit)
         again = true;
-    if (!again || !flexible || restarts >= c->max_restart) break;
+    if (!again || restarts >= c->max_restart) break;
     ++restarts;
     restart_mode = 1;
   }
@@ -483,22 +483,28 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
 static int report(Ctx* c, int R, double rtol, int maxit, int* iters_h, double* relres_h, bool cg) {
   CgState* g = c->cg;
   int result = BRAS_OK;
+  int true_miss = -1;
   for (int col = 0; col < R; ++col) {
     if (iters_h) iters_h[col] = g->ic_host[I_ITERS * R + col];
-    if (relres_h) relres_h[col] = g->sc_host[S_RELRES * R + col];
+    const double rel = g->sc_host[S_RELRES * R + col];
+    if (relres_h) relres_h[col] = rel;
     const int cs = g->ic_host[I_STATUS * R + col];
     if (cs == ST_BREAK) result = BRAS_EBREAKDOWN;
     else if (cs == ST_NOCONV && result == BRAS_OK) result = BRAS_ENOCONV;
+    else if (cs == ST_OK && !(rel <= rtol) && true_miss < 0) true_miss = col;
   }
   if (result == BRAS_EBREAKDOWN)
     return fail(result, cg ? "PCG breakdown (p.q <= 0, r.z <= 0 or non-finite values)" : "non-finite residual");
   if (result == BRAS_ENOCONV)
     return fail(result, "%sdid not reach rtol=%g within maxit=%d", cg ? "PCG " : "", rtol, maxit);
+  if (true_miss >= 0)
+    return fail(BRAS_ENOCONV, "column %d: true relative residual %.3e above rtol=%g after %lld restart(s)", true_miss,
+                g->sc_host[S_RELRES * R + true_miss], rtol, (long long)c->last_restarts);
   return BRAS_OK;
 }
 
 // ===========================================================================
-// Stationary iterations with the same operators (Section 4): the damped
+// Stationary iterations with the same operators (Section 3): the damped
 // fixed point u_{k+1} = u_k + omega C (f - M u_k) and the Chebyshev
 // semi-iteration on a spectral interval [lmin, lmax] of C M, both written as
 //     r_k = f - M u_k;  stop if ||r_k|| <= rtol ||r_0||;
@@ -654,7 +660,7 @@ static int stationary(Ctx* c, int pc, const std::vector<double>& ca, const std::
     st = read_state(c, s);
   }
   while (st == BRAS_OK) {
-    const int chunk = predict_chunk(g, R, maxit);
+    const int chunk = predict_chunk(g, R, maxit, c->graph_iters);
     if (chunk == 0) break;
     if ((st = launch_chunk(*graphs, chunk, s))) break;
     st = read_state(c, s);

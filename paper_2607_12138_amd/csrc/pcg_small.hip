@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_cg_small(SmallOp o, int pc, c
   }
 }
 
-// Stationary iteration (Section 4) in one work-group, the iteration of the
+// Stationary iteration (Section 3) in one work-group, the iteration of the
 // multi-pass stationary driver:
 //   r_0 = b - M x_0;  stop if ||r_k|| <= rtol ||r_0||;
 //   d_k = a_k d_{k-1} + c_k C r_k;  x_{k+1} = x_k + d_k;  r_{k+1} = b - M x_{k+1}

@@ -257,7 +257,7 @@ __device__ inline double cast_out<double>(double v) { return v; }
 template <>
 __device__ inline float cast_out<float>(double v) { return (float)v; }
 template <>
-__device__ inline __bf16 cast_out<__bf16>(double v) { return (__bf16)(float)v; }   // RNE twice, as the oracle emulates
+__device__ inline __bf16 cast_out<__bf16>(double v) { return (__bf16)(float)v; }   // float64 -> float32 -> bfloat16, each to nearest even
 
 __device__ inline void unpack_lower(int q, int& i, int& j) {
   int r = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
@@ -481,11 +481,18 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
     mode = 1;
   }
   double* mpack = c->mpack;   // non-null when the mass pass reads packed M_K
-  double* diagb = nullptr;
-  BRAS_HIP(hipMalloc((void**)&diagb, sizeof(double) * c->nbr));
   size_t lds = sizeof(double) * (npack_of(nl) + 8 + nl);
   const int gram = c->prec == BRAS_BF16 ? 1 : 0;
   if (lds > 64 * 1024) return fail(BRAS_EINVAL, "n_loc %d too large for the element factorisation", nl);
+  // broken diagonal of M_K, freed on every path below
+  struct Scratch {
+    double* p = nullptr;
+    ~Scratch() {
+      if (p) (void)hipFree(p);
+    }
+  } diag_scratch;
+  BRAS_HIP(hipMalloc((void**)&diag_scratch.p, sizeof(double) * c->nbr));
+  double* diagb = diag_scratch.p;
   if (c->prec == BRAS_FP64)
     k_elem_factor<double><<<(unsigned)E, 64, lds, s>>>(mode, E, nl, c->nsym, c->ref, G, Mexp, c->l2g, c->invd, diagb,
                                                         mpack, c->mgroup, (double*)c->ainv, c->agroup, 0, c->flag);
@@ -500,8 +507,7 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
   k_diag_broken<<<blocks_for(c->n, 256), 256, 0, s>>>(c->rowptr, c->slot, c->n, diagb, c->diag, c->invdiag);
   BRAS_HIP(hipGetLastError());
   int f;
-  st = read_flag(c, s, &f);
-  (void)hipFree(diagb);
+  st = read_flag(c, s, &f);   // synchronises s, so the scratch can be freed on return
   if (st) return st;
   if (f != 0x7fffffff) return fail(BRAS_ENOTSPD, "element %d: mass matrix is not symmetric positive definite", f);
   return BRAS_OK;

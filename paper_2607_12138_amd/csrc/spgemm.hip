@@ -1,4 +1,4 @@
-// Sparse products for the Schur-complement approximations of Section 5:
+// Sparse products for the Schur-complement approximations of Section 4:
 // -St = C + G Mt^-1 G^T (eq. approx_positive_schur_general) is sparse when
 // Mt^-1 is (M_bras^-1 has the sparsity of M), and is formed from the
 // assembled operator as two products, (G Mt^-1) G^T, with the transpose of G.

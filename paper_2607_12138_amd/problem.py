@@ -83,7 +83,7 @@ class MassProblem:
         st, its, rel = L.pcg_solve(self.h, pcode, b, x, rtol, maxit)
         return x, st, its, rel
 
-    # -- stationary iterations (Section 4) ------------------------------------
+    # -- stationary iterations (Section 3) ------------------------------------
     def lambda_max(self, pc="bras", v0=None, iters=50):
         """Power-iteration estimate of lambda_max(C M)."""
         import torch
@@ -159,7 +159,7 @@ class MassProblem:
         return out
 
     def schur(self, G, op=None, C=None):
-        """-St = C + G Mt^-1 G^T (Section 5, eq. approx_positive_schur_general)
+        """-St = C + G Mt^-1 G^T (Section 4, eq. approx_positive_schur_general)
         for a CSR coupling G = (rowptr, col, val) of shape m x n on the device,
         Mt^-1 the assembled operator op (default L.OP_BRAS) and an optional
         CSR C (m x m): the sparse products (G Mt^-1) G^T, then the sum with C.

@@ -1,4 +1,4 @@
-"""The rotated-stretch study of Section 4 (eq. rot_stretch_map, Cor.
+"""The rotated-stretch study of Section 3 (eq. rot_stretch_map, Cor.
 bras_piola_metric_contrast) run through libbras on one GPU.
 
 2D BDM_p on the unit-square Kuhn mesh mapped by x -> c + R S R^T (x - c)

@@ -1,4 +1,4 @@
-"""The paper's mass-solve experiments (Section 4; Tables h1_mass_solve,
+"""The paper's mass-solve experiments (Section 3; Tables h1_mass_solve,
 hcurl_mass_solve, hdiv_mass_solve; all six element families) run through
 libbras on one GPU.
 

@@ -1,5 +1,5 @@
 """Sparse products on the GPU for the Schur-complement approximations of
-Section 5 (eq. approx_positive_schur_general, C = 0): the CSR product and
+Section 4 (eq. approx_positive_schur_general, C = 0): the CSR product and
 transpose against SciPy on seeded matrices with ragged and empty rows, the
 assembled -St = G M_bras^-1 G^T against the oracle's plain products, the
 spectral bound of Lemma schur_condition_number_from_mass on the GPU's St,
@@ -198,7 +198,7 @@ def test_schur_with_c_term_matches_oracle():
 @pytest.mark.parametrize("case", SCHUR[:3], ids=lambda c: "%s%d-%dd-N%d" % (c[0], c[2], c[1], c[3]))
 def test_diagonal_schur_and_bras_comparison(case):
     """-St with diag(M)^-1 (the approximation BRAS is compared with in
-    Section 5) against the oracle, and the BRAS St closer to S: its
+    Section 4) against the oracle, and the BRAS St closer to S: its
     beta_0 / alpha_0 below the diagonal one, both from the GPU's products."""
     from paper_2607_12138_amd import _lib as L
     from paper_2607_12138_amd.problem import MassProblem

@@ -177,7 +177,7 @@ def stationary(gpu, kind, b, pc, small, **kw):
 @pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[4], CASES[6]], ids=ids)
 def test_small_stationary_matches_oracle_and_multipass(case):
     """Damped fixed point (BRAS and Jacobi weights from the power iteration)
-    and Chebyshev with BRAS on [1, 1.02 lambda_max] (Section 4)."""
+    and Chebyshev with BRAS on [1, 1.02 lambda_max] (Section 3)."""
     import torch
     from oracle import stationary as ost
     from paper_2607_12138_amd import _lib as L

@@ -1,4 +1,4 @@
-"""GPU parity of the stationary iterations (Section 4): power-iteration
+"""GPU parity of the stationary iterations (Section 3): power-iteration
 estimates of lambda_max(C M), the damped fixed point and the Chebyshev
 semi-iteration, against the oracle on the same seeded inputs."""
 import sys

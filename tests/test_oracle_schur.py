@@ -1,4 +1,4 @@
-"""Oracle pins for the Schur-complement approximations of Section 5: the
+"""Oracle pins for the Schur-complement approximations of Section 4: the
 spectral bounds of Lemma schur_condition_number_from_mass hold for the BRAS
 and the diagonal mass inverses, the exact inverse reproduces the exact Schur
 complement, and the approximations are symmetric positive definite."""

@@ -1,4 +1,4 @@
-"""Pins for the oracle's fixed-point, Chebyshev and power iterations (Section 4)
+"""Pins for the oracle's fixed-point, Chebyshev and power iterations (Section 3)
 against dense eigen-decompositions, the classical contraction bounds the
 paper quotes, the Chebyshev polynomial in closed form, and the paper's
 printed fixed-point iteration counts."""
@@ -58,7 +58,7 @@ def test_power_iteration_against_eigendecomposition(case, which):
 @pytest.mark.parametrize("case", CASES)
 def test_fixed_point_contracts_at_the_optimal_rate(case):
     """With omega = 2/(lmin + lmax) the energy-norm error shrinks by at least
-    (kappa - 1)/(kappa + 1) per update (Section 4's omega_opt)."""
+    (kappa - 1)/(kappa + 1) per update (Section 3's omega_opt)."""
     pr = problem(*case)
     ev, Cm = dense_spectrum(pr, "bras")
     lmin, lmax = ev[0], ev[-1]

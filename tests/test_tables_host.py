@@ -1,6 +1,6 @@
 """Host-side checks of the mass-solve sweep: the closed-form DOF counts of the
 Kuhn meshes agree with the library's DOF numbering, and the chosen meshes have
-about 1e6 DOFs (Section 4's solve size)."""
+about 1e6 DOFs (Section 3's solve size)."""
 import pytest
 
 from paper_2607_12138_amd import _lib as L
