@@ -28,6 +28,7 @@
 #ifndef BRAS_H
 #define BRAS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -174,6 +175,21 @@ int bras_destroy(bras_handle h);
  * Deterministic (no floating-point atomics); asynchronous on stream; no
  * allocation. */
 int bras_apply(bras_handle h, const double* x_d, double* y_d, int nrhs, void* stream);
+
+/* bras_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and result (bit for bit) as bras_apply; the broken-vector
+ * workspace is a fixed device array of BRAS_NOALLOC_SCRATCH_BYTES per device
+ * (taken when the first handle is set up on that device and held until the
+ * process ends) instead of the handle's own buffer, and the call makes no
+ * allocation of any kind.  EINVAL when the workspace of the call (8 bytes per
+ * broken DOF and column for float64 inverses or the scaled H1 form, 4 for
+ * float32 / bfloat16 ones) exceeds that size, or when the handle's device is
+ * not the current one.  All calls on one device share the array: calls that
+ * overlap in time on one device (unordered streams) race and must not be
+ * issued; calls ordered on one stream are safe.  Asynchronous on stream. */
+#define BRAS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int bras_apply_noalloc(bras_handle h, const double* x_d, double* y_d, int nrhs, void* stream);
 
 /* y = M x = sum_K P_K^T M_K P_K x (eq. M_PMbrP), float64 throughout.
  * Same argument rules as bras_apply. */

@@ -26,6 +26,7 @@ INFO = {"n": 0, "E": 1, "nloc": 2, "nbr": 3, "prec": 4, "form": 5, "maxrhs": 6, 
         "solve_path": 9}
 EXPORT_MULT, EXPORT_ROWPTR, EXPORT_SLOT, EXPORT_DIAG = 0, 1, 2, 3
 OPT_GRAPH_ITERS, OPT_MAX_RESTART, OPT_VARIANT, OPT_SMALL_CG = 0, 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 32 << 20   # BRAS_NOALLOC_SCRATCH_BYTES
 FAMILY = {"P": H1, "N1curl": HCURL, "RT": HDIV, "B": H1_BERNSTEIN, "N2curl": HCURL2, "BDM": HDIV2}
 
 
@@ -61,6 +62,7 @@ _SIGS = {
     "bras_update": [vp, vp, vp],
     "bras_destroy": [vp],
     "bras_apply": [vp, vp, vp, i32, vp],
+    "bras_apply_noalloc": [vp, vp, vp, i32, vp],
     "mass_apply": [vp, vp, vp, i32, vp],
     "jacobi_apply": [vp, vp, vp, i32, vp],
     "pcg_solve": [vp, i32, vp, vp, i32, dbl, i32, C.POINTER(C.c_int), P_dbl, vp],
@@ -213,6 +215,10 @@ def _nrhs(x):
 
 def bras_apply(h, x_d, y_d, stream=None):
     check(lib().bras_apply(h, _dev(x_d), _dev(y_d), _nrhs(x_d), _stream(stream)))
+
+
+def bras_apply_noalloc(h, x_d, y_d, stream=None):
+    check(lib().bras_apply_noalloc(h, _dev(x_d), _dev(y_d), _nrhs(x_d), _stream(stream)))
 
 
 def mass_apply(h, x_d, y_d, stream=None):

@@ -32,6 +32,7 @@ SOURCES = [
     ("pcg.hip", []),
     ("pcg_small.hip", []),
     ("bf16.hip", []),
+    ("noalloc.hip", []),
 ]
 
 COMMON = [

@@ -639,19 +639,21 @@ static int mass_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
   }
 }
 
-// element pass of the BRAS operator; reports whether the broken vector is float32
-static int bras_elem(Ctx* c, const InArgs& in, int R, hipStream_t s, bool* zb_float) {
+// element pass of the BRAS operator into the broken vector zb (the handle's
+// own, or a caller-provided workspace of the same size); reports whether the
+// broken vector is float32
+static int bras_elem(Ctx* c, const InArgs& in, int R, hipStream_t s, bool* zb_float, void* zb) {
   *zb_float = false;
   if (c->form == BRAS_ELEM_SCALED_REF)
-    return scaled_dispatch(c, R, in, c->invd, c->refinv, c->icoef, (double*)c->zb, s);
+    return scaled_dispatch(c, R, in, c->invd, c->refinv, c->icoef, (double*)zb, s);
   const bool lane = c->nl <= kLaneMaxNL;
   if (c->prec == BRAS_FP64) {
-    if (lane) return lane_packed_f64(c, R, in, (const double*)c->ainv, (double*)c->zb, s);
-    return mfma_elem_f64(c, R, in, (const double*)c->ainv, (double*)c->zb, s);
+    if (lane) return lane_packed_f64(c, R, in, (const double*)c->ainv, (double*)zb, s);
+    return mfma_elem_f64(c, R, in, (const double*)c->ainv, (double*)zb, s);
   }
   *zb_float = true;
-  if (lane) return lane_packed_f32(c, R, in, (const float*)c->ainv, (float*)c->zb, s);
-  return mfma_elem_f32(c, R, in, (const float*)c->ainv, (float*)c->zb, s);
+  if (lane) return lane_packed_f32(c, R, in, (const float*)c->ainv, (float*)zb, s);
+  return mfma_elem_f32(c, R, in, (const float*)c->ainv, (float*)zb, s);
 }
 
 template <typename ZT, int OUT>
@@ -694,18 +696,24 @@ int launch_mass(Ctx* c, const double* x, double* y, int R, hipStream_t s, const 
   return reduce_launch<double, OUT_PLAIN>(c, (const double*)c->zb, nullptr, y, R, s, dotv, dotpart, CgArgs());
 }
 
+size_t broken_bytes(const Ctx* c, int R) {
+  const size_t esz = (c->form != BRAS_ELEM_SCALED_REF && c->prec != BRAS_FP64) ? sizeof(float) : sizeof(double);
+  return esz * (size_t)c->nbr * (size_t)R;
+}
+
 int launch_bras(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
-                const int* active) {
-  if (c->prec == BRAS_BF16) return launch_bras_bf16(c, x, y, R, s, dotv, dotpart, active);
+                const int* active, void* ws) {
+  void* zb = ws ? ws : c->zb;
+  if (c->prec == BRAS_BF16) return launch_bras_bf16(c, x, y, R, s, dotv, dotpart, active, zb);
   InArgs in;
   in.x = x;
   in.active = active;
   bool zf;
-  int st = bras_elem(c, in, R, s, &zf);
+  int st = bras_elem(c, in, R, s, &zf, zb);
   if (st) return st;
   const double* scale = c->form == BRAS_ELEM_SCALED_REF ? c->invd : nullptr;
-  if (zf) return reduce_launch<float, OUT_PLAIN>(c, (const float*)c->zb, scale, y, R, s, dotv, dotpart, CgArgs());
-  return reduce_launch<double, OUT_PLAIN>(c, (const double*)c->zb, scale, y, R, s, dotv, dotpart, CgArgs());
+  if (zf) return reduce_launch<float, OUT_PLAIN>(c, (const float*)zb, scale, y, R, s, dotv, dotpart, CgArgs());
+  return reduce_launch<double, OUT_PLAIN>(c, (const double*)zb, scale, y, R, s, dotv, dotpart, CgArgs());
 }
 
 int launch_jacobi(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
@@ -760,7 +768,7 @@ int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
   if (pc == BRAS_PC_BRAS && c->prec != BRAS_BF16) {
     InArgs in = precond_input(cg, R);
     bool zf;
-    int st = bras_elem(c, in, R, s, &zf);
+    int st = bras_elem(c, in, R, s, &zf, c->zb);
     if (st) return st;
     const double* scale = c->form == BRAS_ELEM_SCALED_REF ? c->invd : nullptr;
     if (zf)
@@ -799,7 +807,7 @@ int st_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
     return reduce_launch<float, OUT_STAT>(c, (const float*)c->zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
   }
   bool zf;
-  int st = bras_elem(c, in, R, s, &zf);
+  int st = bras_elem(c, in, R, s, &zf, c->zb);
   if (st) return st;
   const double* scale = c->form == BRAS_ELEM_SCALED_REF ? c->invd : nullptr;
   if (zf) return reduce_launch<float, OUT_STAT>(c, (const float*)c->zb, scale, nullptr, R, s, nullptr, nullptr, cg);

@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kB16) k_bras_bf16(int64_t E, int R, const int3
 #define BF16_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(24) X(35) X(36) X(45) X(56) X(70) X(84)
 
 template <int NL>
-static int bf16_launch(Ctx* c, const InArgs& in, int R, hipStream_t s) {
+static int bf16_launch(Ctx* c, const InArgs& in, int R, hipStream_t s, float* zb) {
   static int per_cu = 0;   // resident work-groups per compute unit
   if (per_cu == 0) {
     int v = 0;
@@ -231,14 +231,14 @@ static int bf16_launch(Ctx* c, const InArgs& in, int R, hipStream_t s) {
   }
   const int64_t want = (int64_t)per_cu * c->ncu;
   const unsigned nb = (unsigned)(c->E < want ? c->E : want);
-  k_bras_bf16<NL><<<nb, kB16, 0, s>>>(c->E, R, c->l2g, in, (const __bf16*)c->ainv, (float*)c->zb);
+  k_bras_bf16<NL><<<nb, kB16, 0, s>>>(c->E, R, c->l2g, in, (const __bf16*)c->ainv, zb);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
 
-static int bf16_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
+static int bf16_elem(Ctx* c, const InArgs& in, int R, hipStream_t s, float* zb) {
 #define CASE(N) \
-  case N: return bf16_launch<N>(c, in, R, s);
+  case N: return bf16_launch<N>(c, in, R, s, zb);
   switch (c->nl) {
     BF16_CASES(CASE)
     default: return fail(BRAS_EINVAL, "n_loc %d has no BF16 element kernel", c->nl);
@@ -246,21 +246,21 @@ static int bf16_elem(Ctx* c, const InArgs& in, int R, hipStream_t s) {
 #undef CASE
 }
 
-int bf16_elem_pass(Ctx* c, const InArgs& in, int R, hipStream_t s) { return bf16_elem(c, in, R, s); }
+int bf16_elem_pass(Ctx* c, const InArgs& in, int R, hipStream_t s) { return bf16_elem(c, in, R, s, (float*)c->zb); }
 
 int launch_bras_bf16(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
-                     const int* active) {
+                     const int* active, void* zb) {
   InArgs in;
   in.x = x;
   in.active = active;
-  int st = bf16_elem(c, in, R, s);
+  int st = bf16_elem(c, in, R, s, (float*)zb);
   if (st) return st;
-  return reduce_float_plain(c, (const float*)c->zb, y, R, s, dotv, dotpart);
+  return reduce_float_plain(c, (const float*)zb, y, R, s, dotv, dotpart);
 }
 
 int cg_bras_bf16_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
   InArgs in = precond_input(cg, R);
-  int st = bf16_elem(c, in, R, s);
+  int st = bf16_elem(c, in, R, s, (float*)c->zb);
   if (st) return st;
   return reduce_float_cg(c, (const float*)c->zb, R, s, cg);
 }

@@ -109,14 +109,18 @@ inline int sym_stride(int nsym) { return nsym <= 3 ? 3 : 6; }
 // Launch helpers (apply.hip).  dotv/dotpart (optional): accumulate y . dotv
 // into per-block partial sums [blocks][nrhs]; active (optional): per-column
 // flags, columns with active[r] == 0 are skipped.
+// ws (optional): broken-vector workspace of at least broken_bytes(c, nrhs)
+// bytes to use instead of the handle's own
 int launch_bras(Ctx* c, const double* x, double* y, int nrhs, hipStream_t s, const double* dotv, double* dotpart,
-                const int* active);
+                const int* active, void* ws = nullptr);
 int launch_mass(Ctx* c, const double* x, double* y, int nrhs, hipStream_t s, const double* dotv, double* dotpart,
                 const int* active);
 int launch_jacobi(Ctx* c, const double* x, double* y, int nrhs, hipStream_t s, const double* dotv, double* dotpart,
                   const int* active);
 int launch_bras_bf16(Ctx* c, const double* x, double* y, int nrhs, hipStream_t s, const double* dotv,
-                     double* dotpart, const int* active);
+                     double* dotpart, const int* active, void* zb);
+// bytes of broken-vector workspace one BRAS apply of nrhs columns uses
+size_t broken_bytes(const Ctx* c, int nrhs);
 int reduce_blocks(Ctx* c, int nrhs);   // blocks (= partials per column) of a reduce pass
 int vector_blocks(Ctx* c, int nrhs);   // blocks of a grid-stride vector pass (grid * 256 % nrhs == 0)
 void cg_free(Ctx* c);
@@ -152,6 +156,10 @@ int launch_small_cg(Ctx* c, int pc, const double* b, double* x, double rtol, int
 // damped fixed point / Chebyshev with the coefficient table coef [2][cap]
 int launch_small_stationary(Ctx* c, int pc, const double* b, double* x, double rtol, int maxit, const double* coef,
                             int cap, double* sc, int* ic, hipStream_t s);
+
+// fixed workspace of bras_apply_noalloc (noalloc.hip): its device address on
+// dev (current), looked up once per device
+int scratch_init(int dev, void** out);
 
 // setup internals (setup.hip)
 int element_setup(Ctx* c, const double* elem_d, hipStream_t s);

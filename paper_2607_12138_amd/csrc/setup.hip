@@ -599,6 +599,8 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     delete c;
     return fail(BRAS_EHIP, "hipStreamCreateWithFlags failed");
   }
+  // device address of the fixed workspace of bras_apply_noalloc, once per device
+  TRY(scratch_init(c->device, nullptr));
   TRY(dalloc(&c->l2g, c->nbr));
   TRY(dalloc(&c->mult, n));
   TRY(dalloc(&c->invd, n));
