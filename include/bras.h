@@ -247,6 +247,8 @@ int bras_rho_grad(bras_handle h, const double* x_d, const double* lam_d,
 #define BRAS_INFO_VARIANT  8   /* element-pass scheduling variant (-1: built-in) */
 #define BRAS_INFO_SOLVE_PATH 9 /* last pcg_solve / fixed_point_solve /
                                   chebyshev_solve: 0 multi-pass, 1 one work-group */
+#define BRAS_INFO_PATCHES  10  /* patches of the one-column operator passes
+                                  (0: element / reduce form only)             */
 int bras_info(bras_handle h, int what, int64_t* value_h);
 
 /* Copy derived setup data to device buffers for inspection:
@@ -344,6 +346,10 @@ int bras_csr_add_fill(int64_t m, const int64_t* a_rowptr_d, const int32_t* a_col
 #define BRAS_OPT_SMALL_CG    3  /* 1 (default): single work-group pcg_solve,
                                    fixed_point_solve and chebyshev_solve for
                                    small problems; 0: always multi-pass      */
+#define BRAS_OPT_PATCH       4  /* 1 (default): one-column BRAS / mass passes
+                                   in patch form when the handle has patches
+                                   (BRAS_INFO_PATCHES > 0); 0: element pass
+                                   plus transpose-map reduce               */
 int bras_set_option(bras_handle h, int opt, double value);
 
 /* ======================================================================== *

@@ -33,6 +33,13 @@ SOURCES = [
     ("pcg_small.hip", []),
     ("bf16.hip", []),
     ("noalloc.hip", []),
+    ("patch_setup.cpp", []),
+    ("patch.hip", []),
+    ("patch_scaled.hip", []),
+    ("patch_packed_f32.hip", []),
+    ("patch_packed_f64.hip", []),
+    ("patch_metric3.hip", []),
+    ("patch_metric6.hip", []),
 ]
 
 COMMON = [
@@ -60,14 +67,36 @@ def compile_one(src, extra):
     return obj, warn
 
 
-def build(jobs=8, verbose=False):
+def _up_to_date(src):
+    """The object of src is newer than src and every header it may include."""
+    obj = os.path.join(BUILD, src + ".o")
+    if not os.path.exists(obj):
+        return False
+    deps = [os.path.join(CSRC, src), os.path.join(os.path.dirname(HERE), "include", "bras.h")]
+    deps += [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    t = os.path.getmtime(obj)
+    return all(os.path.getmtime(d) < t for d in deps)
+
+
+def build(jobs=8, verbose=False, incremental=False):
+    """Compile every source (incremental: only those whose object is out of
+    date) and link libbras.so."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = [ex.submit(compile_one, s, e) for s, e in SOURCES]
-        for f in futs:
+        futs = []
+        for s, e in SOURCES:
+            if incremental and _up_to_date(s):
+                futs.append(None)
+                objs.append(os.path.join(BUILD, s + ".o"))
+            else:
+                futs.append(ex.submit(compile_one, s, e))
+                objs.append(None)
+        for k, f in enumerate(futs):
+            if f is None:
+                continue
             obj, warn = f.result()
-            objs.append(obj)
+            objs[k] = obj
             if verbose and warn:
                 print(warn, file=sys.stderr)
     tmp = LIB + ".tmp"
@@ -83,5 +112,6 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("-v", "--verbose", action="store_true")
+    ap.add_argument("--incremental", action="store_true", help="recompile only out-of-date objects")
     a = ap.parse_args()
-    print(build(a.jobs, a.verbose))
+    print(build(a.jobs, a.verbose, a.incremental))

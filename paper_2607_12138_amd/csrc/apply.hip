@@ -32,7 +32,6 @@ constexpr int kBS = 256;                  // reduce / vector pass block size
 constexpr int kEB = 256;                  // element pass block size
 constexpr int kMaxVectorBlocks = 512;
 
-enum { OUT_PLAIN = 0, OUT_MASS_CG = 1, OUT_BRAS_CG = 2, OUT_RES = 3, OUT_STAT = 4 };
 
 // ---------------------------------------------------------------------------
 // element pass, affine H1 (a shared reference matrix times one coefficient per
@@ -537,7 +536,7 @@ template <int NL>
 __global__ void __launch_bounds__(kEB) k_rho_grad(int64_t E, int R, const int32_t* __restrict__ l2g,
                                                   const double* __restrict__ x, const double* __restrict__ lam,
                                                   const double* __restrict__ Mhat, const double* __restrict__ dcoef,
-                                                  double* __restrict__ g) {
+                                                  const int32_t* __restrict__ perm, double* __restrict__ g) {
   constexpr int EPB = kEB / NL;
   __shared__ double w[kEB];
   __shared__ double part[kEB];
@@ -570,7 +569,8 @@ __global__ void __launch_bounds__(kEB) k_rho_grad(int64_t E, int R, const int32_
     if (on && l == 0) {
       double s = 0.0;
       for (int j = 0; j < NL; ++j) s += part[e * NL + j];
-      g[K] = -dcoef[K] * s;
+      const int64_t Ku = perm ? perm[K] : K;   // the caller's element number
+      g[Ku] = -dcoef[Ku] * s;
     }
     __syncthreads();
   }
@@ -671,6 +671,7 @@ static int reduce_launch(Ctx* c, const ZT* zb, const double* scale, double* y, i
 }
 
 int reduce_blocks(Ctx* c, int R) {
+  if (patch_active(c, R)) return patch_blocks(c);   // patch pass: one partial per work-group of its two kernels
   // one column: one work-group per chunk up to a large cap (latency hiding);
   // several columns: fewer, longer-lived work-groups and fewer partials
   const int64_t cap = R == 1 ? kMaxReduceBlocks1 : kMaxReduceBlocks;
@@ -691,12 +692,14 @@ int launch_mass(Ctx* c, const double* x, double* y, int R, hipStream_t s, const 
   InArgs in;
   in.x = x;
   in.active = active;
+  if (patch_active(c, R)) return patch_pass(c, 0, OUT_PLAIN, in, y, dotv, dotpart, CgArgs(), s);
   int st = mass_elem(c, in, R, s);
   if (st) return st;
   return reduce_launch<double, OUT_PLAIN>(c, (const double*)c->zb, nullptr, y, R, s, dotv, dotpart, CgArgs());
 }
 
 size_t broken_bytes(const Ctx* c, int R) {
+  if (patch_active(c, R)) return patch_workspace_bytes(c);
   const size_t esz = (c->form != BRAS_ELEM_SCALED_REF && c->prec != BRAS_FP64) ? sizeof(float) : sizeof(double);
   return esz * (size_t)c->nbr * (size_t)R;
 }
@@ -708,6 +711,7 @@ int launch_bras(Ctx* c, const double* x, double* y, int R, hipStream_t s, const 
   InArgs in;
   in.x = x;
   in.active = active;
+  if (patch_active(c, R)) return patch_pass(c, 1, OUT_PLAIN, in, y, dotv, dotpart, CgArgs(), s, (double*)ws);
   bool zf;
   int st = bras_elem(c, in, R, s, &zf, zb);
   if (st) return st;
@@ -746,6 +750,7 @@ InArgs precond_input(const CgArgs& cg, int R) {
 // Work-groups of the pass that consumes alpha (each one would sum the p.q
 // partials in its prologue).
 int precond_consumer_blocks(Ctx* c, int pc, int R) {
+  if (pc == BRAS_PC_BRAS && patch_active(c, R)) return (int)c->pt.npatch;
   if (pc == BRAS_PC_BRAS) return c->prec == BRAS_BF16 ? (int)c->E : (int)((c->E + kEPB - 1) / kEPB);
   return vector_blocks(c, R);
 }
@@ -758,6 +763,7 @@ int cg_mass_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
   in.cvec = cg.sc + S_BETA * R;
   in.sign = 1.0;
   in.active = cg.ic + I_ACTIVE * R;
+  if (patch_active(c, R)) return patch_pass(c, 0, OUT_MASS_CG, in, nullptr, nullptr, nullptr, cg, s);
   int st = mass_elem(c, in, R, s);
   if (st) return st;
   return reduce_launch<double, OUT_MASS_CG>(c, (const double*)c->zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
@@ -767,6 +773,7 @@ int cg_mass_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
 int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
   if (pc == BRAS_PC_BRAS && c->prec != BRAS_BF16) {
     InArgs in = precond_input(cg, R);
+    if (patch_active(c, R)) return patch_pass(c, 1, OUT_BRAS_CG, in, nullptr, nullptr, nullptr, cg, s);
     bool zf;
     int st = bras_elem(c, in, R, s, &zf, c->zb);
     if (st) return st;
@@ -786,6 +793,7 @@ int st_mass_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
   InArgs in;
   in.x = cg.x;
   in.active = cg.ic + I_ACTIVE * R;
+  if (patch_active(c, R)) return patch_pass(c, 0, OUT_RES, in, nullptr, nullptr, nullptr, cg, s);
   int st = mass_elem(c, in, R, s);
   if (st) return st;
   return reduce_launch<double, OUT_RES>(c, (const double*)c->zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
@@ -806,6 +814,7 @@ int st_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
     if (st) return st;
     return reduce_launch<float, OUT_STAT>(c, (const float*)c->zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
   }
+  if (patch_active(c, R)) return patch_pass(c, 1, OUT_STAT, in, nullptr, nullptr, nullptr, cg, s);
   bool zf;
   int st = bras_elem(c, in, R, s, &zf, c->zb);
   if (st) return st;
@@ -861,7 +870,7 @@ extern "C" int bras_rho_grad(bras_handle h, const double* x_d, const double* lam
     constexpr int EPB = kEB / N;                                                                         \
     const int64_t groups = (c->E + EPB - 1) / EPB;                                                      \
     const unsigned nb = (unsigned)(groups < 65536 ? groups : 65536);                                     \
-    k_rho_grad<N><<<nb, kEB, 0, s>>>(c->E, nrhs, c->l2g, x_d, lam_d, c->ref, dcoef_d, g_d);              \
+    k_rho_grad<N><<<nb, kEB, 0, s>>>(c->E, nrhs, c->l2g, x_d, lam_d, c->ref, dcoef_d, c->pt.perm, g_d); \
     break;                                                                                               \
   }
   switch (c->nl) {

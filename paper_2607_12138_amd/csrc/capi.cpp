@@ -1,4 +1,5 @@
 // Error reporting, introspection, options and the kernel-variant autotuner.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -41,6 +42,7 @@ extern "C" int bras_info(bras_handle h, int what, int64_t* value_h) {
     case BRAS_INFO_RESTARTS: *value_h = c->last_restarts; break;
     case BRAS_INFO_VARIANT: *value_h = c->variant; break;
     case BRAS_INFO_SOLVE_PATH: *value_h = c->last_path; break;
+    case BRAS_INFO_PATCHES: *value_h = c->pt.npatch; break;
     default: return fail(BRAS_EINVAL, "unknown info key %d", what);
   }
   return BRAS_OK;
@@ -68,6 +70,11 @@ extern "C" int bras_set_option(bras_handle h, int opt, double value) {
       BRAS_CHECK(value == 0 || value == 1, "small-problem solver switch must be 0 or 1");
       c->small_cg = (int)value;
       break;
+    case BRAS_OPT_PATCH:
+      BRAS_CHECK(value == 0 || value == 1, "patch-form switch must be 0 or 1");
+      c->use_patch = (int)value;
+      cg_free(c);   // captured CG graphs and partial buffers follow the operator form
+      break;
     default: return fail(BRAS_EINVAL, "unknown option %d", opt);
   }
   return BRAS_OK;
@@ -89,15 +96,23 @@ extern "C" int bras_export(bras_handle h, int what, void* dst_d, void* stream) {
       BRAS_HIP(hipMemcpyAsync(dst_d, c->diag, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
       break;
     case BRAS_EXPORT_SLOT: {
-      // internal l*E + K -> canonical K*n_loc + l, on the host
-      std::vector<int32_t> in(c->nbr);
+      // internal l*E + K -> the caller's K*n_loc + l, on the host, each row in
+      // increasing order (the handle's element order may be patch-major)
+      std::vector<int32_t> in(c->nbr), rp(c->n + 1), perm;
       std::vector<int64_t> out(c->nbr);
       BRAS_HIP(hipMemcpyAsync(in.data(), c->slot, sizeof(int32_t) * c->nbr, hipMemcpyDeviceToHost, s));
+      BRAS_HIP(hipMemcpyAsync(rp.data(), c->rowptr, sizeof(int32_t) * (c->n + 1), hipMemcpyDeviceToHost, s));
+      if (c->pt.perm) {
+        perm.resize(c->E);
+        BRAS_HIP(hipMemcpyAsync(perm.data(), c->pt.perm, sizeof(int32_t) * c->E, hipMemcpyDeviceToHost, s));
+      }
       BRAS_HIP(hipStreamSynchronize(s));
       for (int64_t p = 0; p < c->nbr; ++p) {
         const int64_t l = in[p] / c->E, K = in[p] - l * c->E;
-        out[p] = K * c->nl + l;
+        out[p] = (perm.empty() ? K : (int64_t)perm[K]) * c->nl + l;
       }
+      if (!perm.empty())
+        for (int64_t i = 0; i < c->n; ++i) std::sort(out.begin() + rp[i], out.begin() + rp[i + 1]);
       BRAS_HIP(hipMemcpyAsync(dst_d, out.data(), sizeof(int64_t) * c->nbr, hipMemcpyHostToDevice, s));
       BRAS_HIP(hipStreamSynchronize(s));
       break;

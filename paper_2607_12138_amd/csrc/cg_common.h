@@ -15,6 +15,15 @@ enum { S_RZ = 0, S_R0, S_TARGET, S_ALPHA, S_BETA, S_RZOLD, S_RELRES, S_RR, S_NSC
 enum { I_ACTIVE = 0, I_ITERS, I_STATUS, I_NIC };
 enum { ST_RUN = 0, ST_OK = 1, ST_NOCONV = 2, ST_BREAK = 3 };
 
+// What a reduce (or patch) pass does with each conforming sum acc_i:
+//   OUT_PLAIN    y_i = acc_i (optional partials of y . dotv)
+//   OUT_MASS_CG  p_new = z + beta p, q = acc, partials p_new . q
+//   OUT_BRAS_CG  r_new = r - alpha q, x += alpha p, z = acc, partials r_new . r_new,
+//                r_new . z and (flexible) r_new . z_old
+//   OUT_RES      r = b - acc, partials r . r             (stationary iterations)
+//   OUT_STAT     d = a d + c acc, x += d                 (a = sc[S_ALPHA], c = sc[S_BETA])
+enum { OUT_PLAIN = 0, OUT_MASS_CG = 1, OUT_BRAS_CG = 2, OUT_RES = 3, OUT_STAT = 4 };
+
 // Input of an element pass: w = x + sign * c_r * x2 (x2 optional), where c_r
 // is cvec[r], or, when apart is set, alpha_r = rho_r / (sum of the p.q
 // partials apart[anb][R]) computed in the pass's own prologue (block 0 stores

@@ -75,6 +75,103 @@ __device__ __forceinline__ void touch_all(T (&z)[N]) {
   for (int i = 0; i < N; ++i) __asm__ volatile("" : "+v"(z[i]));
 }
 
+// Product z = M_K w of one element in one lane, over the stored lower
+// triangle (each entry used for both z_i and z_j): FORM_PACKED reads the
+// element's packed matrix from ap (16-byte groups, layout of packed_at with
+// element index K0 + lt), FORM_METRIC rebuilds each entry from the pair
+// tables symtab [q][NSYM] and the element's coefficients g.  z must be zero
+// on entry.  VAR: scheduling variant (see k_elem_lane).
+template <int NL, int FORM, int NSYM, typename T, int VAR>
+__device__ __forceinline__ void lane_product(const T (&wr)[NL], T (&z)[NL], int64_t K0, int lt, int64_t E,
+                                             const T* __restrict__ ap, const double* __restrict__ symtab,
+                                             const double (&g)[NSYM > 0 ? NSYM : 1]) {
+  constexpr int NPK = NL * (NL + 1) / 2;
+  constexpr int V = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  // one stored entry q = i(i+1)/2 + j applied symmetrically
+  auto use = [&](auto qc, T m) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int i = tri_row(q), j = q - i * (i + 1) / 2;
+    z[i] = fma(m, wr[j], z[i]);
+    if constexpr (j < i) z[j] = fma(m, wr[i], z[j]);
+  };
+  if constexpr (FORM == FORM_METRIC) {
+    // table entries are wave-uniform scalar loads (SGPR operands, no LDS
+    // traffic), in batches of CQ entries, the next batch in flight.
+    // Visiting order: row by row, or diagonal by diagonal (entries (i, i-d)
+    // for i = d..NL-1), where consecutive entries update different
+    // accumulators.
+    constexpr int CQS = (VAR >> 2) & 3;
+    constexpr int CQ = (VAR & 64) ? ((VAR & 128) ? 16 : 12) : (CQS == 0 ? 2 : (CQS == 1 ? 4 : (CQS == 2 ? 1 : 8)));
+    constexpr bool DIAG = (VAR & 1) != 0;
+    constexpr bool PIN_M = (VAR & 2) != 0;
+    constexpr int NBQ = (NPK + CQ - 1) / CQ;
+    double tb[2][CQ * NSYM];
+    double mlast = wr[0];
+    auto tload = [&](auto bc, int64_t o) {
+      constexpr int b = decltype(bc)::value;
+      const double* src = symtab + o;
+      static_for<CQ>([&](auto ec) {
+        constexpr int t = b * CQ + decltype(ec)::value;
+        if constexpr (t < NPK) {
+          constexpr int q = DIAG ? diag_q<NL>(t) : t;
+#pragma unroll
+          for (int p = 0; p < NSYM; ++p) tb[b & 1][decltype(ec)::value * NSYM + p] = src[q * NSYM + p];
+        }
+      });
+    };
+    tload(std::integral_constant<int, 0>{}, pin_s((int64_t)0, wr[0]));
+    static_for<NBQ>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      if constexpr (b + 1 < NBQ) tload(std::integral_constant<int, b + 1>{}, pin_s((int64_t)0, mlast));
+      static_for<CQ>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        constexpr int t = b * CQ + e;
+        if constexpr (t < NPK) {
+          constexpr int q = DIAG ? diag_q<NL>(t) : t;
+          double acc = 0.0;
+#pragma unroll
+          for (int p = 0; p < NSYM; ++p) acc = fma(g[p], tb[b & 1][e * NSYM + p], acc);
+          use(std::integral_constant<int, q>{}, (T)acc);
+          if (PIN_M) mlast = acc;
+        }
+      });
+      if constexpr (!PIN_M) touch_all(z);
+    });
+  } else {
+    constexpr int NQ = (NPK + V - 1) / V;   // 16-byte groups
+    constexpr int CV = ((VAR >> 4) & 3) == 0 ? 6 : (((VAR >> 4) & 3) == 1 ? 3 : (((VAR >> 4) & 3) == 2 ? 10 : 14));
+    constexpr int NB = (NQ + CV - 1) / CV;
+    // uniform base + per-lane offset (lanes past the last element read its data)
+    const vec_t* sbase = reinterpret_cast<const vec_t*>(ap) + K0;
+    vec_t buf[2][CV];
+    auto load = [&](auto bc, int64_t boff) {
+      constexpr int b = decltype(bc)::value;
+      const vec_t* src = sbase + boff;
+#pragma unroll
+      for (int v = 0; v < CV; ++v)
+        if (b * CV + v < NQ) {
+          // VAR bit 8: the matrix stream is read with the non-temporal hint
+          if constexpr ((VAR & 256) != 0)
+            buf[b & 1][v] = __builtin_nontemporal_load(&src[(int64_t)v * E + lt]);
+          else
+            buf[b & 1][v] = src[(int64_t)v * E + lt];
+        }
+    };
+    load(std::integral_constant<int, 0>{}, pin_s((int64_t)0, wr[0]));
+    static_for<NB>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      // batch b+1 goes out once batch b-1 has been used: two batches in flight
+      if constexpr (b + 1 < NB) load(std::integral_constant<int, b + 1>{}, pin_s((int64_t)((b + 1) * CV) * E, wr[0]));
+      static_for<CV * V>([&](auto ec) {
+        constexpr int q = b * CV * V + decltype(ec)::value;
+        if constexpr (q < NPK) use(std::integral_constant<int, q>{}, buf[b & 1][(q / V) % CV][q % V]);
+      });
+      touch_all(z);
+    });
+  }
+}
+
 // VAR selects scheduling variants: metric form bit 0 diagonal order, bit 1
 // pinning on the entry values, bits 2-3 and 6-7 the batch size; packed form
 // bits 4-5 the batch size, bit 8 non-temporal loads of the matrix stream
@@ -177,89 +274,7 @@ __global__ void __launch_bounds__(EPB) k_elem_lane(int64_t E, int R, const int32
       wr[j] = w[j * WSL + tid];
       z[j] = (T)0;
     }
-    // one stored entry q = i(i+1)/2 + j applied symmetrically
-    auto use = [&](auto qc, T m) {
-      constexpr int q = decltype(qc)::value;
-      constexpr int i = tri_row(q), j = q - i * (i + 1) / 2;
-      z[i] = fma(m, wr[j], z[i]);
-      if constexpr (j < i) z[j] = fma(m, wr[i], z[j]);
-    };
-    if constexpr (FORM == FORM_METRIC) {
-      // table entries are wave-uniform scalar loads (SGPR operands, no LDS
-      // traffic), in batches of CQ entries, the next batch in flight.
-      // Visiting order: row by row, or diagonal by diagonal (entries (i, i-d)
-      // for i = d..NL-1), where consecutive entries update different
-      // accumulators.
-      constexpr int CQS = (VAR >> 2) & 3;
-      constexpr int CQ = (VAR & 64) ? ((VAR & 128) ? 16 : 12) : (CQS == 0 ? 2 : (CQS == 1 ? 4 : (CQS == 2 ? 1 : 8)));
-      constexpr bool DIAG = (VAR & 1) != 0;
-      constexpr bool PIN_M = (VAR & 2) != 0;
-      constexpr int NBQ = (NPK + CQ - 1) / CQ;
-      double tb[2][CQ * NSYM];
-      double mlast = wr[0];
-      auto tload = [&](auto bc, int64_t o) {
-        constexpr int b = decltype(bc)::value;
-        const double* src = symtab + o;
-        static_for<CQ>([&](auto ec) {
-          constexpr int t = b * CQ + decltype(ec)::value;
-          if constexpr (t < NPK) {
-            constexpr int q = DIAG ? diag_q<NL>(t) : t;
-#pragma unroll
-            for (int p = 0; p < NSYM; ++p) tb[b & 1][decltype(ec)::value * NSYM + p] = src[q * NSYM + p];
-          }
-        });
-      };
-      tload(std::integral_constant<int, 0>{}, pin_s((int64_t)0, wr[0]));
-      static_for<NBQ>([&](auto bc) {
-        constexpr int b = decltype(bc)::value;
-        if constexpr (b + 1 < NBQ) tload(std::integral_constant<int, b + 1>{}, pin_s((int64_t)0, mlast));
-        static_for<CQ>([&](auto ec) {
-          constexpr int e = decltype(ec)::value;
-          constexpr int t = b * CQ + e;
-          if constexpr (t < NPK) {
-            constexpr int q = DIAG ? diag_q<NL>(t) : t;
-            double acc = 0.0;
-#pragma unroll
-            for (int p = 0; p < NSYM; ++p) acc = fma(g[p], tb[b & 1][e * NSYM + p], acc);
-            use(std::integral_constant<int, q>{}, (T)acc);
-            if (PIN_M) mlast = acc;
-          }
-        });
-        if constexpr (!PIN_M) touch_all(z);
-      });
-    } else {
-      constexpr int NQ = (NPK + V - 1) / V;   // 16-byte groups
-      constexpr int CV = ((VAR >> 4) & 3) == 0 ? 6 : (((VAR >> 4) & 3) == 1 ? 3 : (((VAR >> 4) & 3) == 2 ? 10 : 14));
-      constexpr int NB = (NQ + CV - 1) / CV;
-      // uniform base + per-lane offset (lanes past the last element read its data)
-      const vec_t* sbase = reinterpret_cast<const vec_t*>(ap) + K0;
-      const int lt = on ? tid : 0;
-      vec_t buf[2][CV];
-      auto load = [&](auto bc, int64_t boff) {
-        constexpr int b = decltype(bc)::value;
-        const vec_t* src = sbase + boff;
-#pragma unroll
-        for (int v = 0; v < CV; ++v)
-          if (b * CV + v < NQ) {
-            // VAR bit 8: the matrix stream is read with the non-temporal hint
-            if constexpr ((VAR & 256) != 0)
-              buf[b & 1][v] = __builtin_nontemporal_load(&src[(int64_t)v * E + lt]);
-            else
-              buf[b & 1][v] = src[(int64_t)v * E + lt];
-          }
-      };
-      load(std::integral_constant<int, 0>{}, pin_s((int64_t)0, wr[0]));
-      static_for<NB>([&](auto bc) {
-        constexpr int b = decltype(bc)::value;
-        // batch b+1 goes out once batch b-1 has been used: two batches in flight
-        if constexpr (b + 1 < NB) load(std::integral_constant<int, b + 1>{}, pin_s((int64_t)((b + 1) * CV) * E, wr[0]));
-        static_for<CV * V>([&](auto ec) {
-          constexpr int q = b * CV * V + decltype(ec)::value;
-          if constexpr (q < NPK) use(std::integral_constant<int, q>{}, buf[b & 1][(q / V) % CV][q % V]);
-        });
-        touch_all(z);
-      });
-    }
+    lane_product<NL, FORM, NSYM, T, VAR>(wr, z, K0, on ? tid : 0, E, ap, symtab, g);
     if (on) {
 #pragma unroll
       for (int i = 0; i < NL; ++i) zb[((int64_t)i * E + K) * R + col] = (ZT)z[i];

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/bras.h"
+#include "patch.h"
 
 namespace bras {
 
@@ -49,6 +50,7 @@ struct Ctx {
   int graph_iters = 32;      // most CG / stationary iterations launched between two host checks
   int max_restart = 8;
   int small_cg = 1;          // solve eligible small problems in one work-group (pcg_small.hip)
+  int use_patch = 1;         // one-column operator passes in patch form when the handle has a plan (patch.hip)
   int last_path = 0;         // path of the last pcg_solve: 0 multi-pass, 1 one work-group
   int64_t last_restarts = 0;
 
@@ -74,6 +76,9 @@ struct Ctx {
   double* symtab = nullptr;  // METRIC_REF, n_loc <= kLaneMaxNL: pair tables packed [npack][sym_stride(nsym)]
   double* mpack = nullptr;   // packed float64 M_K [npack][E] for the mass pass (EXPLICIT, or METRIC with
                              // n_loc > kLaneMaxNL)
+  double* ref_pk = nullptr;    // SCALED_REF with a patch plan: Mhat, packed lower [npack]
+  double* refinv_pk = nullptr; // SCALED_REF with a patch plan: Mhat^-1, packed lower [npack]
+  PatchDev pt;               // patch plan (npatch == 0: none); element order is then patch-major
   double* diag = nullptr;    // diag(M) [n]
   double* invdiag = nullptr; // [n]
 
@@ -160,6 +165,17 @@ int launch_small_stationary(Ctx* c, int pc, const double* b, double* x, double r
 // fixed workspace of bras_apply_noalloc (noalloc.hip): its device address on
 // dev (current), looked up once per device
 int scratch_init(int dev, void** out);
+
+// Patch form of the one-column operator passes (patch.hip): op 0 mass, 1
+// BRAS; out one of OUT_* (cg_common.h); ws (optional) replaces the handle's
+// buffer of shared-DOF partial sums (patch_workspace_bytes).  Dot partials:
+// patch_blocks per column.
+bool patch_supported(int form, int prec, int nl);
+bool patch_active(const Ctx* c, int nrhs);
+int patch_blocks(const Ctx* c);
+size_t patch_workspace_bytes(const Ctx* c);
+int patch_pass(Ctx* c, int op, int out, const InArgs& in, double* y, const double* dotv, double* dotpart,
+               const CgArgs& cg, hipStream_t s, double* ws = nullptr);
 
 // setup internals (setup.hip)
 int element_setup(Ctx* c, const double* elem_d, hipStream_t s);

@@ -1,0 +1,274 @@
+// Patch form of the BRAS and mass operators (eqs. mhatinvbras_def,
+// mass_and_bras_element_sums, M_PMbrP): one work-group per patch of up to 256
+// elements (patch_setup.cpp); gather, element products and most of the
+// scatter-sum in one kernel, without the broken vector in device memory.
+//
+//   1. the patch's DOF values w_j = x[g_j] (or an axpy of two vectors, times
+//      D^-1 for the scaled H1 form) go to LDS, one float64 per DOF, read in
+//      increasing DOF order;
+//   2. each lane takes one element, reads its n_loc inputs from LDS through
+//      the copy codes and forms z = M_K w (the per-lane product of
+//      elem_lane.h: packed matrices, metric pair tables, or the shared
+//      reference matrix times the element's coefficient); the LDS array then
+//      collects the sums: the copies of rank 0 are added, then those of rank
+//      1, ... (a barrier between ranks), so every DOF's copies are summed in
+//      element order and no two lanes add to one entry at once (no atomics);
+//   3. each DOF whose copies all lie in the patch gets its final value (times
+//      D^-1 for the scaled H1 form) and the CG / stationary epilogue; each
+//      shared DOF writes its patch's partial sum.
+// A second kernel sums each shared DOF's partials in patch order and runs the
+// same epilogue.  Dot-product partials: one per work-group of either kernel,
+// patches first, summed in that fixed order by the consumer.
+//
+// One column only (R = 1); several columns use the element / reduce passes.
+#pragma once
+
+#include "internal.h"
+#include "cg_common.h"
+#include "elem_lane.h"
+#include "patch.h"
+
+namespace bras {
+
+struct PatchArgs {
+  const int32_t* pe;
+  const int32_t* pd;
+  const int32_t* pnl;
+  const int32_t* pdof;
+  const uint16_t* code;
+  const int32_t* sbase;
+  int64_t E;
+  int lbits, maxrank;
+};
+
+// One call of the patch form of an operator (op 0 mass, 1 BRAS).
+struct PatchCall {
+  int op = 0;
+  int out = 0;
+  InArgs in;
+  double* y = nullptr;
+  const double* dotv = nullptr;
+  double* dotpart = nullptr;
+  CgArgs cg;
+  double* spart = nullptr;   // partial sums of shared DOFs
+};
+
+template <int OUT>
+__device__ __forceinline__ void patch_epilogue(int32_t g, double acc, double coef, double coef2, const CgArgs& cg,
+                                               double* y, const double* dotv, double& d0, double& d1, double& d2) {
+  if (OUT == OUT_PLAIN) {
+    y[g] = acc;
+    if (dotv) d0 = fma(acc, dotv[g], d0);
+  } else if (OUT == OUT_MASS_CG) {
+    const double pn = fma(coef, cg.p[g], cg.z[g]);
+    cg.p[g] = pn;
+    cg.q[g] = acc;
+    d0 = fma(pn, acc, d0);
+  } else if (OUT == OUT_BRAS_CG) {
+    const double rn = fma(-coef, cg.q[g], cg.r[g]);
+    cg.x[g] = fma(coef, cg.p[g], cg.x[g]);
+    if (cg.flexible) d2 = fma(rn, cg.z[g], d2);
+    cg.z[g] = acc;
+    cg.r[g] = rn;
+    d0 = fma(rn, rn, d0);
+    d1 = fma(rn, acc, d1);
+  } else if (OUT == OUT_RES) {
+    const double rv = cg.b[g] - acc;
+    cg.r[g] = rv;
+    d0 = fma(rv, rv, d0);
+  } else {
+    const double dn = fma(coef, cg.p[g], coef2 * acc);
+    cg.p[g] = dn;
+    cg.x[g] += dn;
+  }
+}
+
+// Work-group sums of the epilogue's dot-product terms (fixed tree order) into
+// slot b of the partial arrays; sh: 3 * kPatchBlock doubles of LDS, free.
+template <int OUT>
+__device__ __forceinline__ void patch_dots(double d0, double d1, double d2, int64_t b, double* out0,
+                                           const CgArgs& cg, double* sh) {
+  if (OUT == OUT_STAT) return;
+  if (OUT == OUT_PLAIN && !out0) return;
+  double* sh0 = sh;
+  double* sh1 = sh + kPatchBlock;
+  double* sh2 = sh + 2 * kPatchBlock;
+  const int tid = threadIdx.x;
+  sh0[tid] = d0;
+  if (OUT == OUT_BRAS_CG) {
+    sh1[tid] = d1;
+    sh2[tid] = d2;
+  }
+  __syncthreads();
+  for (int off = kPatchBlock / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      sh0[tid] += sh0[tid + off];
+      if (OUT == OUT_BRAS_CG) {
+        sh1[tid] += sh1[tid + off];
+        sh2[tid] += sh2[tid + off];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out0[b] = sh0[0];
+    if (OUT == OUT_BRAS_CG) {
+      cg.part1[b] = sh1[0];
+      if (cg.flexible) cg.part2[b] = sh2[0];
+    }
+  }
+}
+
+// FORM_PACKED: M_K (or the folded inverse) from ap; FORM_METRIC with NSYM > 1:
+// pair tables symtab [q][NSYM] and coefficients coefK [nsym][E]; FORM_METRIC
+// with NSYM = 1: the scaled H1 form, symtab = the shared reference matrix as
+// a packed lower triangle, coefK [E] the element's factor.  Dynamic LDS:
+// max(maxdofs, 3 * kPatchBlock) doubles.
+template <int NL, int FORM, int NSYM, typename T, int OUT, bool DS, int VAR>
+__global__ void __launch_bounds__(kPatchBlock) k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
+                                                       const double* __restrict__ symtab,
+                                                       const double* __restrict__ coefK, int nsym,
+                                                       const double* __restrict__ dscale, double* __restrict__ y,
+                                                       const double* __restrict__ dotv, double* __restrict__ dotpart,
+                                                       CgArgs cg, double* __restrict__ spart) {
+  extern __shared__ double wsh[];   // inputs, then sums, then dot partials
+  __shared__ double coef_s[1];
+  __shared__ int act_s[1];
+  const int tid = threadIdx.x;
+  if (in.apart) {
+    alpha_prologue(in.apart, in.anb, 1, in.sc, in.ic, coef_s, act_s, wsh);
+  } else {
+    if (tid == 0) {
+      act_s[0] = in.active ? in.active[0] : 1;
+      coef_s[0] = in.cvec ? in.cvec[0] : 0.0;
+    }
+    __syncthreads();
+  }
+  if (!act_s[0]) return;   // uniform across the grid
+  const double cf = coef_s[0];                    // alpha (BRAS_CG) or beta (MASS_CG)
+  const double c2 = in.x2 ? in.sign * cf : 0.0;   // weight of the second input vector
+  const int64_t p = blockIdx.x;
+  const int32_t e0 = pa.pe[p], ne = pa.pe[p + 1] - e0;
+  const int32_t d0 = pa.pd[p], nd = pa.pd[p + 1] - d0, nloc = pa.pnl[p];
+  __syncthreads();   // the prologue's use of wsh is over
+  // 1. patch DOF values
+  for (int j = tid; j < nd; j += kPatchBlock) {
+    const int32_t g = pa.pdof[d0 + j];
+    double v = in.x[g];
+    if (in.x2) v = fma(c2, in.x2[g], v);
+    if (DS) v *= dscale[g];
+    wsh[j] = v;
+  }
+  __syncthreads();
+  // 2. one element per lane (idle lanes repeat element 0 and add nothing)
+  const bool on = tid < ne;
+  const int e = on ? tid : 0;
+  const uint32_t lmask = (1u << pa.lbits) - 1u;
+  const uint16_t* cdp = pa.code + (int64_t)e0 * NL + e;
+  uint32_t cd[NL];
+  T wr[NL], z[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) cd[l] = cdp[(int64_t)l * ne];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    wr[l] = (T)wsh[cd[l] & lmask];
+    z[l] = (T)0;
+  }
+  __syncthreads();   // every input read: the array now collects the sums
+  for (int j = tid; j < nd; j += kPatchBlock) wsh[j] = 0.0;
+  double g[NSYM > 0 ? NSYM : 1];
+  if (FORM == FORM_METRIC) {
+#pragma unroll
+    for (int q = 0; q < NSYM; ++q)
+      g[q] = q < nsym ? __builtin_nontemporal_load(&coefK[(int64_t)q * pa.E + e0 + e]) : 0.0;
+  }
+  lane_product<NL, FORM, NSYM, T, VAR>(wr, z, e0, e, pa.E, ap, symtab, g);
+  __syncthreads();
+  const int lb = pa.lbits;
+  for (int r = 0; r <= pa.maxrank; ++r) {
+    if (on) {
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+        if ((int)(cd[l] >> lb) == r) wsh[cd[l] & lmask] += (double)z[l];
+    }
+    __syncthreads();
+  }
+  // 3. DOFs of the patch
+  const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
+  const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  const int32_t sb = pa.sbase[p];
+  for (int j = tid; j < nd; j += kPatchBlock) {
+    double acc = wsh[j];
+    if (j < nloc) {
+      const int32_t g2 = pa.pdof[d0 + j];
+      if (DS) acc *= dscale[g2];
+      patch_epilogue<OUT>(g2, acc, ep1, ep2, cg, y, dotv, a0, a1, a2);
+    } else {
+      spart[sb + (j - nloc)] = acc;
+    }
+  }
+  __syncthreads();   // wsh is free again
+  patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
+}
+
+// Shared DOFs: the patch partials summed in patch order, then the epilogue.
+template <int OUT, bool DS>
+__global__ void __launch_bounds__(kPatchBlock) k_patch_shared(int64_t ns, const int32_t* __restrict__ srp,
+                                                              const int32_t* __restrict__ spos,
+                                                              const int32_t* __restrict__ sdof,
+                                                              const double* __restrict__ spart,
+                                                              const double* __restrict__ dscale,
+                                                              double* __restrict__ y, const double* __restrict__ dotv,
+                                                              double* __restrict__ dotpart, int64_t pbase,
+                                                              const int* __restrict__ active, CgArgs cg) {
+  __shared__ double sh[3 * kPatchBlock];
+  if (OUT != OUT_PLAIN && !cg.ic[I_ACTIVE]) return;   // uniform across the grid
+  if (OUT == OUT_PLAIN && active && !active[0]) return;
+  const double c1 = OUT == OUT_MASS_CG ? cg.sc[S_BETA]
+                    : ((OUT == OUT_BRAS_CG || OUT == OUT_STAT) ? cg.sc[S_ALPHA] : 0.0);
+  const double c2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int64_t s = (int64_t)blockIdx.x * kPatchBlock + threadIdx.x; s < ns; s += (int64_t)gridDim.x * kPatchBlock) {
+    const int32_t k0 = srp[s], k1 = srp[s + 1];
+    double acc = 0.0;
+    for (int32_t k = k0; k < k1; ++k) acc += spart[spos[k]];
+    const int32_t g = sdof[s];
+    if (DS) acc *= dscale[g];
+    patch_epilogue<OUT>(g, acc, c1, c2, cg, y, dotv, a0, a1, a2);
+  }
+  patch_dots<OUT>(a0, a1, a2, pbase + blockIdx.x, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, sh);
+}
+
+// Both kernels of one patch-form operator pass.
+template <int NL, int FORM, int NSYM, typename T, int OUT, bool DS, int VAR>
+int patch_launch(Ctx* c, const PatchCall& pc, const T* ap, const double* symtab, const double* coefK, int nsym,
+                 const double* dscale, hipStream_t s) {
+  const PatchDev& pt = c->pt;
+  PatchArgs pa{pt.pe, pt.pd, pt.pnl, pt.pdof, pt.code, pt.sbase, c->E, pt.lbits, pt.maxrank};
+  const int words = pt.maxdofs > 3 * kPatchBlock ? pt.maxdofs : 3 * kPatchBlock;
+  k_patch<NL, FORM, NSYM, T, OUT, DS, VAR><<<(unsigned)pt.npatch, kPatchBlock, sizeof(double) * words, s>>>(
+      pa, pc.in, ap, symtab, coefK, nsym, dscale, pc.y, pc.dotv, pc.dotpart, pc.cg, pc.spart);
+  BRAS_HIP(hipGetLastError());
+  if (pt.ns > 0) {
+    k_patch_shared<OUT, DS><<<(unsigned)pt.nb2, kPatchBlock, 0, s>>>(pt.ns, pt.srp, pt.spos, pt.sdof, pc.spart,
+                                                                       dscale, pc.y, pc.dotv, pc.dotpart,
+                                                                       pt.npatch, pc.in.active, pc.cg);
+    BRAS_HIP(hipGetLastError());
+  }
+  return BRAS_OK;
+}
+
+// n_loc of the per-lane forms: scaled H1 (Lagrange / Bernstein degree 1-4),
+// the vector families up to n_loc 36
+#define PATCH_SCALED_NL(X) X(3) X(4) X(6) X(10) X(15) X(20) X(35)
+#define PATCH_VECTOR_NL(X) X(3) X(4) X(6) X(8) X(12) X(15) X(20) X(24) X(30) X(36)
+
+// Per-form dispatchers (one translation unit each, patch_*.hip).
+int patch_scaled(Ctx* c, const PatchCall& pc, hipStream_t s);
+int patch_packed_f32(Ctx* c, const PatchCall& pc, hipStream_t s);
+int patch_packed_f64(Ctx* c, const PatchCall& pc, hipStream_t s);
+int patch_metric3(Ctx* c, const PatchCall& pc, hipStream_t s);
+int patch_metric6(Ctx* c, const PatchCall& pc, hipStream_t s);
+
+}  // namespace bras

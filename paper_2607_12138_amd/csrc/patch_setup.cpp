@@ -47,7 +47,15 @@ struct BucketQueue {
 
 int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int32_t* mult, int P, int Dmax,
                      PatchPlan* plan) {
-  if (P < 1 || Dmax < nl) return 1;
+  if (P < 1) return 1;
+  // 16-bit codes: rank bits for the largest multiplicity, the rest for j
+  int maxmult = 1;
+  for (int64_t i = 0; i < n; ++i) maxmult = std::max(maxmult, (int)mult[i]);
+  int rbits = 0;
+  while ((1 << rbits) < maxmult) ++rbits;
+  if (rbits > 10) return 1;
+  Dmax = std::min(Dmax, 1 << (16 - rbits));
+  if (Dmax < nl) return 1;
   // DOF -> elements (CSR)
   std::vector<int64_t> drp(n + 1, 0);
   for (int64_t q = 0; q < E * nl; ++q) ++drp[l2g[q] + 1];
@@ -60,22 +68,42 @@ int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int
   }
   std::vector<int32_t> part(E, -1);
   std::vector<int32_t> gain(E, 0);
+  std::vector<int32_t> anc(E, 0);     // DOF incidences shared with already assigned elements
   std::vector<int32_t> stamp(n, -1);
   std::vector<int32_t> touched;
   BucketQueue bq;
+  BucketQueue seeds;                  // unassigned elements by anc: a new patch starts at the most
+                                      // enclosed one, so that no small pockets are left behind
   plan->perm.clear();
   plan->perm.reserve(E);
   plan->pe.assign(1, 0);
   int64_t next = 0;
   int32_t np = 0;
+  // patches grow to Pg < P elements; the room left takes in the small
+  // pockets greedy growth leaves between patches (merge step below)
+  const int Pg = P >= 16 ? P - P / 8 : P;
   while (true) {
-    while (next < E && part[next] >= 0) ++next;
-    if (next >= E) break;
+    int32_t seed = -1;
+    while (seeds.top > 0 && seed < 0) {
+      auto& v = seeds.b[seeds.top];
+      if (v.empty()) {
+        --seeds.top;
+        continue;
+      }
+      const int32_t k = v.back();
+      v.pop_back();
+      if (part[k] < 0 && anc[k] == seeds.top) seed = k;
+    }
+    if (seed < 0) {
+      while (next < E && part[next] >= 0) ++next;
+      if (next >= E) break;
+      seed = (int32_t)next;
+    }
     bq.clear();
     touched.clear();
-    bq.push(0, (int32_t)next);
+    bq.push(0, seed);
     int cnt = 0, ndof = 0;
-    while (cnt < P) {
+    while (cnt < Pg) {
       int32_t K = -1;
       while (bq.top >= 0 && K < 0) {
         auto& v = bq.b[bq.top];
@@ -104,20 +132,96 @@ int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int
           if (gain[K2] == 0) touched.push_back(K2);
           ++gain[K2];
           bq.push(gain[K2], K2);
+          ++anc[K2];
         }
       }
     }
-    for (int32_t k : touched) gain[k] = 0;
-    plan->pe.push_back((int32_t)plan->perm.size());
+    for (int32_t k : touched) {
+      gain[k] = 0;
+      if (part[k] < 0) seeds.push(anc[k], k);
+    }
     ++np;
   }
-  const int64_t npatch = np;
+  // merge: a patch of fewer than Pg / 4 elements joins the neighbouring patch
+  // it shares the most DOF copies with, when that one has room for its
+  // elements and DOFs
+  {
+    std::vector<int32_t> ecount(np, 0), dcount(np, 0);
+    for (int64_t K = 0; K < E; ++K) ++ecount[part[K]];
+    std::vector<int32_t> dstamp(n, -1);
+    for (int64_t K = 0; K < E; ++K)
+      for (int l = 0; l < nl; ++l) {
+        const int32_t g = l2g[K * nl + l];
+        if (dstamp[g] != part[K]) {
+          // a DOF is counted once per patch: its elements' patches are visited in element order
+          bool seen = false;
+          for (int64_t a = drp[g]; a < drp[g + 1] && del[a] < K; ++a) seen = seen || part[del[a]] == part[K];
+          if (!seen) ++dcount[part[K]];
+          dstamp[g] = part[K];
+        }
+      }
+    std::vector<std::vector<int32_t>> members(np);
+    for (int32_t K : plan->perm) members[part[K]].push_back(K);   // growth order
+    std::vector<int32_t> score(np, 0), cand;
+    for (int32_t q = 0; q < np; ++q) {
+      if (ecount[q] == 0 || ecount[q] >= Pg / 4) continue;
+      cand.clear();
+      for (int32_t K : members[q])
+        for (int l = 0; l < nl; ++l) {
+          const int32_t g = l2g[(int64_t)K * nl + l];
+          for (int64_t a = drp[g]; a < drp[g + 1]; ++a) {
+            const int32_t t = part[del[a]];
+            if (t == q) continue;
+            if (score[t] == 0) cand.push_back(t);
+            ++score[t];
+          }
+        }
+      int32_t best = -1;
+      for (int32_t t : cand) {
+        if (ecount[t] + ecount[q] > P) continue;
+        if (best < 0 || score[t] > score[best] || (score[t] == score[best] && t < best)) best = t;
+      }
+      for (int32_t t : cand) score[t] = 0;
+      if (best < 0) continue;
+      // DOFs the merged patch would hold
+      int add = 0;
+      for (int32_t K : members[q])
+        for (int l = 0; l < nl; ++l) {
+          const int32_t g = l2g[(int64_t)K * nl + l];
+          bool in_best = false, first = true;
+          for (int64_t a = drp[g]; a < drp[g + 1]; ++a) {
+            const int32_t t = part[del[a]];
+            in_best = in_best || t == best;
+            if (t == q && del[a] < K) first = false;
+          }
+          if (!in_best && first) ++add;
+        }
+      if (dcount[best] + add > Dmax) continue;
+      for (int32_t K : members[q]) {
+        part[K] = best;
+        members[best].push_back(K);
+      }
+      members[q].clear();
+      ecount[best] += ecount[q];
+      ecount[q] = 0;
+      dcount[best] += add;
+      dcount[q] = 0;
+    }
+    // patch-major element order, patches in creation order, elements in growth order
+    plan->perm.clear();
+    for (int32_t q = 0; q < np; ++q) {
+      if (members[q].empty()) continue;
+      for (int32_t K : members[q]) plan->perm.push_back(K);
+      plan->pe.push_back((int32_t)plan->perm.size());
+    }
+  }
+  const int64_t npatch = (int64_t)plan->pe.size() - 1;
   plan->npatch = npatch;
   // per-patch DOF lists and copy codes
   plan->pd.assign(1, 0);
   plan->pnl.assign(npatch, 0);
   plan->pdof.clear();
-  plan->code.assign(E * nl, 0);
+  std::vector<uint32_t> jr(E * nl, 0);   // (j, rank) per copy, packed below
   plan->sbase.assign(npatch + 1, 0);
   std::vector<int32_t> lj(n, -1);       // DOF -> index in the current patch's first-seen list
   std::vector<int32_t> seen, cnt_in;    // first-seen DOF list and copy counts
@@ -172,21 +276,21 @@ int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int
         const int32_t r = rk[j]++;
         maxr = std::max(maxr, r);
         // j and r packed once lbits is known: keep (j, r) for now
-        plan->code[(int64_t)e0 * nl + (int64_t)l * ne + (e - e0)] = (uint32_t)j | ((uint32_t)r << 16);
+        jr[(int64_t)e0 * nl + (int64_t)l * ne + (e - e0)] = (uint32_t)j | ((uint32_t)r << 16);
       }
     }
     for (int k = 0; k < nd; ++k) lj[seen[k]] = -1;
   }
-  // code packing: lbits for j, the rest for the rank
+  // code packing: lbits for j, the rank above (maxd <= Dmax <= 2^(16 - rbits), maxr < maxmult <= 2^rbits)
   int lbits = 1;
   while ((1 << lbits) < maxd) ++lbits;
-  int rbits = 1;
-  while ((1 << rbits) <= maxr) ++rbits;
+  if (lbits + rbits > 16) return 1;
   plan->lbits = lbits;
   plan->rbits = rbits;
   plan->maxrank = maxr;
   plan->maxdofs = maxd;
-  for (auto& cd : plan->code) cd = (cd & 0xFFFFu) | ((cd >> 16) << lbits);
+  plan->code.resize(E * nl);
+  for (int64_t q = 0; q < E * nl; ++q) plan->code[q] = (uint16_t)((jr[q] & 0xFFFFu) | ((jr[q] >> 16) << lbits));
   // second pass: the shared DOFs in increasing order, each with its partials in patch order
   plan->srp.assign(1, 0);
   plan->sdof.clear();

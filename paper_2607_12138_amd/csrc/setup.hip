@@ -9,6 +9,9 @@
 #include <cstring>
 #include <vector>
 
+#include <cstdlib>
+#include <type_traits>
+
 #include "internal.h"
 
 namespace bras {
@@ -218,6 +221,16 @@ __global__ void k_pack_sym(const double* __restrict__ S, int nl, int nsym, int s
   while ((i + 1) * (i + 2) / 2 <= q) ++i;
   const int j = q - i * (i + 1) / 2;
   out[t] = p < nsym ? S[(int64_t)p * nl * nl + i * nl + j] : 0.0;
+}
+
+// rows of per-element data into the internal (patch-major) element order:
+// out[K][i] = in[perm[K]][i]
+__global__ void k_permute_rows(const double* __restrict__ in, const int32_t* __restrict__ perm, int64_t E, int w,
+                               double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= E * w) return;
+  const int64_t K = t / w, i = t - K * w;
+  out[t] = in[(int64_t)perm[K] * w + i];
 }
 
 // AoS [E][nsym] -> SoA [nsym][E]
@@ -451,7 +464,37 @@ static int reset_flag(Ctx* c, hipStream_t s) {
   return BRAS_OK;
 }
 
+static int element_setup_ordered(Ctx* c, const double* elem_d, hipStream_t s);
+
+// The caller's number of internal element K (errors name the caller's element).
+static int caller_element(const Ctx* c, int K) {
+  if (!c->pt.perm || K < 0 || K >= c->E) return K;
+  int32_t u = K;
+  if (hipMemcpy(&u, c->pt.perm + K, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return K;
+  return u;
+}
+
+// Element data arrive in the caller's element order; with a patch plan the
+// handle's order is patch-major, so they are permuted first.
 int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
+  if (!c->pt.perm) return element_setup_ordered(c, elem_d, s);
+  const int w = c->form == BRAS_ELEM_SCALED_REF ? 1 : (c->form == BRAS_ELEM_METRIC_REF ? c->nsym : c->nl * c->nl);
+  struct Tmp {
+    double* p = nullptr;
+    ~Tmp() {
+      if (p) (void)hipFree(p);
+    }
+  } tmp;
+  if (hipMalloc((void**)&tmp.p, sizeof(double) * (size_t)c->E * w) != hipSuccess)
+    return fail(BRAS_ENOMEM, "element data permutation buffer allocation failed");
+  k_permute_rows<<<blocks_for(c->E * w, 256), 256, 0, s>>>(elem_d, c->pt.perm, c->E, w, tmp.p);
+  BRAS_HIP(hipGetLastError());
+  const int st = element_setup_ordered(c, tmp.p, s);
+  (void)hipStreamSynchronize(s);   // tmp is read by the kernels just queued
+  return st;
+}
+
+static int element_setup_ordered(Ctx* c, const double* elem_d, hipStream_t s) {
   const int64_t E = c->E;
   const int nl = c->nl;
   int st;
@@ -461,7 +504,8 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
     BRAS_HIP(hipGetLastError());
     int f;
     if ((st = read_flag(c, s, &f))) return st;
-    if (f != 0x7fffffff) return fail(BRAS_ENOTSPD, "element %d: coefficient c_K must be positive and finite", f);
+    if (f != 0x7fffffff)
+      return fail(BRAS_ENOTSPD, "element %d: coefficient c_K must be positive and finite", caller_element(c, f));
     k_diag_scaled<<<blocks_for(c->n, 256), 256, 0, s>>>(c->rowptr, c->slot, c->n, E, c->coef, c->ref, nl, c->diag,
                                                         c->invdiag);
     BRAS_HIP(hipGetLastError());
@@ -509,14 +553,17 @@ int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
   int f;
   st = read_flag(c, s, &f);   // synchronises s, so the scratch can be freed on return
   if (st) return st;
-  if (f != 0x7fffffff) return fail(BRAS_ENOTSPD, "element %d: mass matrix is not symmetric positive definite", f);
+  if (f != 0x7fffffff)
+    return fail(BRAS_ENOTSPD, "element %d: mass matrix is not symmetric positive definite", caller_element(c, f));
   return BRAS_OK;
 }
 
 static void free_ctx(Ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->l2g, c->mult, c->invd, c->rowptr, c->chunk, c->slot, c->ref, c->refinv, c->coef, c->icoef, c->ainv,
-                  c->symtab, c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag};
+                  c->symtab, c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag, c->ref_pk, c->refinv_pk,
+                  c->pt.perm, c->pt.pe, c->pt.pd, c->pt.pnl, c->pt.pdof, c->pt.code, c->pt.sbase, c->pt.srp,
+                  c->pt.spos, c->pt.sdof, c->pt.part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   cg_free(c);
@@ -535,6 +582,60 @@ static int dalloc(T** p, size_t count) {
 }  // namespace bras
 
 using namespace bras;
+
+// Patch plan of the handle (host partition of the validated map), the map in
+// patch-major element order, and the device copy of the plan.  Skipped for
+// element forms without a patch kernel, and when BRAS_PATCH=0 is set in the
+// environment; BRAS_PATCH_ELEMS / BRAS_PATCH_DOFS change the patch size and
+// DOF cap.
+static int patch_setup(Ctx* c, hipStream_t s) {
+  const char* env = getenv("BRAS_PATCH");
+  if (env && atoi(env) == 0) return BRAS_OK;
+  if (!patch_supported(c->form, c->prec, c->nl)) return BRAS_OK;
+  int P = kPatchElems, D = kPatchMaxDofs;
+  if (const char* e = getenv("BRAS_PATCH_ELEMS")) P = atoi(e);
+  if (const char* e = getenv("BRAS_PATCH_DOFS")) D = atoi(e);
+  if (P < 1 || P > kPatchBlock) return fail(BRAS_EINVAL, "BRAS_PATCH_ELEMS must be in 1..%d", kPatchBlock);
+  if (D < 1 || D > 65536) return fail(BRAS_EINVAL, "BRAS_PATCH_DOFS must be in 1..65536");
+  const int64_t n = c->n, E = c->E, nl = c->nl, nbr = c->nbr;
+  std::vector<int32_t> l2g(nbr), mult(n);
+  BRAS_HIP(hipMemcpyAsync(l2g.data(), c->l2g, sizeof(int32_t) * nbr, hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipMemcpyAsync(mult.data(), c->mult, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  BRAS_HIP(hipStreamSynchronize(s));
+  PatchPlan plan;
+  if (build_patch_plan(n, E, (int)nl, l2g.data(), mult.data(), P, D, &plan) != 0) return BRAS_OK;
+  std::vector<int32_t> il2g(nbr);
+  for (int64_t K = 0; K < E; ++K)
+    for (int l = 0; l < nl; ++l) il2g[K * nl + l] = l2g[(int64_t)plan.perm[K] * nl + l];
+  PatchDev& pt = c->pt;
+  auto up = [&](auto** dst, const auto& v) -> int {
+    typedef typename std::remove_reference<decltype(v[0])>::type T;
+    const size_t cnt = v.size() > 0 ? v.size() : 1;
+    if (hipMalloc((void**)dst, sizeof(T) * cnt) != hipSuccess)
+      return fail(BRAS_ENOMEM, "patch plan allocation failed");
+    if (!v.empty() && hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(BRAS_EHIP, "patch plan copy failed");
+    return BRAS_OK;
+  };
+  int st;
+  if ((st = up(&pt.perm, plan.perm)) || (st = up(&pt.pe, plan.pe)) || (st = up(&pt.pd, plan.pd)) ||
+      (st = up(&pt.pnl, plan.pnl)) || (st = up(&pt.pdof, plan.pdof)) || (st = up(&pt.code, plan.code)) ||
+      (st = up(&pt.sbase, plan.sbase)) || (st = up(&pt.srp, plan.srp)) || (st = up(&pt.spos, plan.spos)) ||
+      (st = up(&pt.sdof, plan.sdof)))
+    return st;
+  BRAS_HIP(hipMemcpy(c->l2g, il2g.data(), sizeof(int32_t) * nbr, hipMemcpyHostToDevice));
+  pt.ns = (int64_t)plan.sdof.size();
+  pt.nspart = (int64_t)plan.spos.size();
+  if (hipMalloc((void**)&pt.part, sizeof(double) * (size_t)(pt.nspart > 0 ? pt.nspart : 1)) != hipSuccess)
+    return fail(BRAS_ENOMEM, "patch partial-sum buffer allocation failed");
+  const int64_t nb2 = (pt.ns + kPatchBlock - 1) / kPatchBlock;
+  pt.nb2 = (int)(nb2 < kPatchSharedBlocks ? (nb2 > 0 ? nb2 : 1) : kPatchSharedBlocks);
+  pt.lbits = plan.lbits;
+  pt.maxrank = plan.maxrank;
+  pt.maxdofs = plan.maxdofs;
+  pt.npatch = plan.npatch;   // last: the plan is complete
+  return BRAS_OK;
+}
 
 extern "C" int bras_geometry(int family, int dim, int64_t nvert, const double* coords_d, int64_t ncell,
                              const int32_t* cells_d, const double* rho_d, double* elem_d, void* stream) {
@@ -627,6 +728,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     free_ctx(c);
     return fail(BRAS_EINVAL, "DOF %d has no broken copy (P must have full column rank)", f);
   }
+  TRY(patch_setup(c, s));
   {
     const int64_t per = (int64_t)kScanBlock * kScanItems;
     const int64_t nb = (n + per - 1) / per;
@@ -696,6 +798,15 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     (void)hipFree(work);
     if (st) { free_ctx(c); return st; }
     if (f != 0x7fffffff) { free_ctx(c); return fail(BRAS_ENOTSPD, "reference mass matrix is not SPD"); }
+    if (c->pt.npatch > 0) {
+      // the patch passes read the shared matrices as packed lower triangles
+      const int npk = npack_of(n_loc);
+      TRY(dalloc(&c->ref_pk, npk));
+      TRY(dalloc(&c->refinv_pk, npk));
+      k_pack_sym<<<blocks_for(npk, 256), 256, 0, s>>>(c->ref, n_loc, 1, 1, c->ref_pk);
+      k_pack_sym<<<blocks_for(npk, 256), 256, 0, s>>>(c->refinv, n_loc, 1, 1, c->refinv_pk);
+      if (hipGetLastError() != hipSuccess) { free_ctx(c); return fail(BRAS_EHIP, "reference table packing failed"); }
+    }
   } else {
     if (form == BRAS_ELEM_METRIC_REF) {
       TRY(dalloc(&c->ref, (size_t)c->nsym * nn));
