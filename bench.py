@@ -54,7 +54,7 @@ def algorithmic_bytes(w, n, E, n_loc, R, prec):
 # sources of the operator passes and their data layout (the kernels the
 # stored counter measurements describe)
 APPLY_SOURCES = ("apply.hip", "elem_lane.h", "lane_*.hip", "elem_mfma.hip", "bf16.hip", "cg_common.h",
-                 "block_reduce.h", "internal.h", "setup.hip")
+                 "block_reduce.h", "internal.h", "setup.hip", "patch*.hip", "patch*.h", "patch_setup.cpp")
 
 
 def source_digest():
@@ -288,9 +288,10 @@ def main():
     ap.add_argument("--no-assembled", action="store_true", help="skip the assembled (CSR) BRAS comparison and the Schur-complement products")
     ap.add_argument("--stationary-steps", type=int, default=2,
                     help="timed fixed-point / Chebyshev solves of each kind (0: skip)")
-    ap.add_argument("--mode", choices=["full", "apply", "mass", "copy"], default="full",
+    ap.add_argument("--mode", choices=["full", "apply", "mass", "copy", "solve"], default="full",
                     help="apply / mass: only back-to-back BRAS / mass applies (for counter runs); "
-                         "copy: a device copy of known size (counter calibration)")
+                         "copy: a device copy of known size (counter calibration); "
+                         "solve: only BRAS-PCG solves (for kernel traces of the solve)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on exactly one GPU: the method has no multi-GPU path in this library "
@@ -336,6 +337,14 @@ def main():
         print(json.dumps({"mode": "apply", "workload": w.name, "reps": a.apply_reps, "us_per_apply": round(us, 3),
                           "bytes_per_apply": int(algorithmic_bytes(w, prob.n, prob.E, prob.n_loc, w.nrhs, w.prec)),
                           "source_digest": source_digest()}), flush=True)
+        return
+    if a.mode == "solve":
+        for _ in range(a.warmup):
+            prob.solve(b, "bras", rtol=w.tol)
+        ms, st, its, rel, _ = time_solves(prob, b, "bras", w.tol, a.steps)
+        prob.close()
+        print(json.dumps({"mode": "solve", "workload": w.name, "steps": a.steps, "ms_per_solve": round(ms, 4),
+                          "iterations": [int(v) for v in its], "source_digest": source_digest()}), flush=True)
         return
     for _ in range(a.warmup):
         prob.solve(b, "bras", rtol=w.tol)

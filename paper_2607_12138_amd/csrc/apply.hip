@@ -722,7 +722,8 @@ int launch_bras(Ctx* c, const double* x, double* y, int R, hipStream_t s, const 
 
 int launch_jacobi(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
                   const int* active) {
-  k_diag_scale<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, c->invdiag, x, y, dotv, dotpart, active);
+  k_diag_scale<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, c->ip_mode ? c->pt.invdiag_ip : c->invdiag, x, y, dotv,
+                                                   dotpart, active);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
@@ -783,7 +784,8 @@ int cg_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
     return reduce_launch<double, OUT_BRAS_CG>(c, (const double*)c->zb, scale, nullptr, R, s, nullptr, nullptr, cg);
   }
   if (pc == BRAS_PC_BRAS) return cg_bras_bf16_step(c, cg, R, s);
-  k_diag_cg<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, pc == BRAS_PC_JACOBI ? c->invdiag : nullptr, cg);
+  const double* invdiag = c->ip_mode ? c->pt.invdiag_ip : c->invdiag;
+  k_diag_cg<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, pc == BRAS_PC_JACOBI ? invdiag : nullptr, cg);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
@@ -802,7 +804,7 @@ int st_mass_step(Ctx* c, const CgArgs& cg, int R, hipStream_t s) {
 // Stationary iterations: d = a d + c C r, x += d (pc: BRAS_PC_BRAS or BRAS_PC_JACOBI)
 int st_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
   if (pc == BRAS_PC_JACOBI) {
-    k_diag_st<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, c->invdiag, cg);
+    k_diag_st<<<vector_blocks(c, R), kBS, 0, s>>>(c->n, R, c->ip_mode ? c->pt.invdiag_ip : c->invdiag, cg);
     BRAS_HIP(hipGetLastError());
     return BRAS_OK;
   }

@@ -51,6 +51,9 @@ struct Ctx {
   int max_restart = 8;
   int small_cg = 1;          // solve eligible small problems in one work-group (pcg_small.hip)
   int use_patch = 1;         // one-column operator passes in patch form when the handle has a plan (patch.hip)
+  int patch_xcd = 1;         // patch passes: each XCD takes a contiguous run of patches (BRAS_PATCH_XCD=0: round robin)
+  int ip_mode = 0;           // 1 while a patch-form solve runs: operator passes address vectors in the
+                             // internal DOF numbering of the patch plan (PatchDev::ip2g)
   int last_path = 0;         // path of the last pcg_solve: 0 multi-pass, 1 one work-group
   int64_t last_restarts = 0;
 

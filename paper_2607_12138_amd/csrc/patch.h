@@ -17,10 +17,15 @@ struct PatchPlan {
   std::vector<int32_t> pnl;     // [npatch] DOFs of the patch whose copies all lie in it (listed first)
   std::vector<int32_t> pdof;    // patch DOF lists (conforming DOF numbers)
   std::vector<uint16_t> code;   // [E*nl] copy (e, l) of patch p at pe[p]*nl + l*ne_p + e: j | rank << lbits
-  std::vector<int32_t> sbase;   // [npatch+1] first partial of each patch's shared DOFs
-  std::vector<int32_t> srp;     // [ns+1] partials of shared DOF s: spos[srp[s] .. srp[s+1])
-  std::vector<int32_t> spos;    // partial indices, in patch order
+  std::vector<int32_t> sbase;   // [npatch+1] first partial of each patch's shared DOFs (patch-major)
+  std::vector<int32_t> srp;     // [ns+1] partials of shared DOF s: spos[srp[s] .. srp[s+1]), in patch order
+  std::vector<int32_t> spos;    // partial indices
   std::vector<int32_t> sdof;    // [ns] the shared DOFs, increasing
+  // internal DOF numbering of the solvers' vectors: the local DOFs of patch 0,
+  // of patch 1, ..., then the shared DOFs in sdof order
+  std::vector<int32_t> ip2g;    // [n] internal -> conforming DOF
+  std::vector<int32_t> pidx;    // like pdof, internal numbers
+  int64_t nloc_total = 0;       // DOFs local to some patch (the first internal numbers)
   int lbits = 0, rbits = 0, maxrank = 0, maxdofs = 0;
 };
 
@@ -50,6 +55,12 @@ struct PatchDev {
   int32_t* spos = nullptr;
   int32_t* sdof = nullptr;
   double* part = nullptr;  // [nspart] partial sums (the handle's workspace)
+  // internal DOF numbering (the solvers' vectors while a patch-form solve runs)
+  int64_t nloc_total = 0;
+  int32_t* ip2g = nullptr;
+  int32_t* pidx = nullptr;
+  double* invd_ip = nullptr;      // D^-1 in internal numbering
+  double* invdiag_ip = nullptr;   // diag(M)^-1 in internal numbering
 };
 
 // Work-group size of the patch pass: at most this many elements per patch.
@@ -57,7 +68,10 @@ constexpr int kPatchBlock = 256;
 // Default patch size and DOF cap (LDS holds one float64 per patch DOF).
 constexpr int kPatchElems = 256;
 constexpr int kPatchMaxDofs = 3072;
-// Work-groups of the shared-DOF pass (at most).
-constexpr int kPatchSharedBlocks = 1024;
+// Shared-DOF pass: each thread sums kPatchSharedPerThread shared DOFs
+// (independent loads in flight), so a work-group covers kPatchSharedPerBlock.
+constexpr int kPatchSharedPerThread = 4;
+constexpr int kPatchSharedPerBlock = kPatchBlock * kPatchSharedPerThread;
+constexpr int kPatchSharedBlocks = 1 << 20;
 
 }  // namespace bras

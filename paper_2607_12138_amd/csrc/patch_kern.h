@@ -39,6 +39,8 @@ struct PatchArgs {
   const int32_t* sbase;
   int64_t E;
   int lbits, maxrank;
+  int64_t npatch;
+  int xcd_per;   // > 0: work-group b takes patch (b % 8) * xcd_per + b / 8 (each XCD a contiguous run)
 };
 
 // One call of the patch form of an operator (op 0 mass, 1 BRAS).
@@ -119,13 +121,21 @@ __device__ __forceinline__ void patch_dots(double d0, double d1, double d2, int6
   }
 }
 
+// Waves per SIMD the register allocator is asked for: 4 (at most 128 VGPRs)
+// where a lane's element fits without spilling, else its natural count.
+template <int NL, typename T>
+constexpr int kPatchWaves() {
+  return sizeof(T) == 4 ? (NL <= 20 ? 4 : 1) : (NL <= 12 ? 4 : 1);
+}
+
 // FORM_PACKED: M_K (or the folded inverse) from ap; FORM_METRIC with NSYM > 1:
 // pair tables symtab [q][NSYM] and coefficients coefK [nsym][E]; FORM_METRIC
 // with NSYM = 1: the scaled H1 form, symtab = the shared reference matrix as
 // a packed lower triangle, coefK [E] the element's factor.  Dynamic LDS:
 // max(maxdofs, 3 * kPatchBlock) doubles.
 template <int NL, int FORM, int NSYM, typename T, int OUT, bool DS, int VAR>
-__global__ void __launch_bounds__(kPatchBlock) k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
+__global__ void __launch_bounds__(kPatchBlock) __attribute__((amdgpu_waves_per_eu(kPatchWaves<NL, T>())))
+k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
                                                        const double* __restrict__ symtab,
                                                        const double* __restrict__ coefK, int nsym,
                                                        const double* __restrict__ dscale, double* __restrict__ y,
@@ -147,7 +157,8 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch(PatchArgs pa, InArgs in, 
   if (!act_s[0]) return;   // uniform across the grid
   const double cf = coef_s[0];                    // alpha (BRAS_CG) or beta (MASS_CG)
   const double c2 = in.x2 ? in.sign * cf : 0.0;   // weight of the second input vector
-  const int64_t p = blockIdx.x;
+  const int64_t p = pa.xcd_per > 0 ? (int64_t)(blockIdx.x % 8) * pa.xcd_per + blockIdx.x / 8 : (int64_t)blockIdx.x;
+  if (p >= pa.npatch) return;   // uniform across the work-group
   const int32_t e0 = pa.pe[p], ne = pa.pe[p + 1] - e0;
   const int32_t d0 = pa.pd[p], nd = pa.pd[p + 1] - d0, nloc = pa.pnl[p];
   __syncthreads();   // the prologue's use of wsh is over
@@ -165,13 +176,20 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch(PatchArgs pa, InArgs in, 
   const int e = on ? tid : 0;
   const uint32_t lmask = (1u << pa.lbits) - 1u;
   const uint16_t* cdp = pa.code + (int64_t)e0 * NL + e;
-  uint32_t cd[NL];
+  // codes two to a register (they stay live through the product)
+  constexpr int NC2 = (NL + 1) / 2;
+  uint32_t cd2[NC2];
+#pragma unroll
+  for (int h = 0; h < NC2; ++h) {
+    const uint32_t lo = cdp[(int64_t)(2 * h) * ne];
+    const uint32_t hi = 2 * h + 1 < NL ? (uint32_t)cdp[(int64_t)(2 * h + 1) * ne] : 0u;
+    cd2[h] = lo | (hi << 16);
+  }
+  auto code = [&](int l) -> uint32_t { return (cd2[l >> 1] >> (16 * (l & 1))) & 0xFFFFu; };
   T wr[NL], z[NL];
 #pragma unroll
-  for (int l = 0; l < NL; ++l) cd[l] = cdp[(int64_t)l * ne];
-#pragma unroll
   for (int l = 0; l < NL; ++l) {
-    wr[l] = (T)wsh[cd[l] & lmask];
+    wr[l] = (T)wsh[code(l) & lmask];
     z[l] = (T)0;
   }
   __syncthreads();   // every input read: the array now collects the sums
@@ -188,8 +206,10 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch(PatchArgs pa, InArgs in, 
   for (int r = 0; r <= pa.maxrank; ++r) {
     if (on) {
 #pragma unroll
-      for (int l = 0; l < NL; ++l)
-        if ((int)(cd[l] >> lb) == r) wsh[cd[l] & lmask] += (double)z[l];
+      for (int l = 0; l < NL; ++l) {
+        const uint32_t cl = code(l);
+        if ((int)(cl >> lb) == r) wsh[cl & lmask] += (double)z[l];
+      }
     }
     __syncthreads();
   }
@@ -213,10 +233,12 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch(PatchArgs pa, InArgs in, 
 }
 
 // Shared DOFs: the patch partials summed in patch order, then the epilogue.
+// DOF of shared DOF s: sdof[s], or (internal numbering, sdof null) sbase + s.
+// The partials of shared DOF s are spart[spos[k]], k = srp[s] .. srp[s+1]-1.
 template <int OUT, bool DS>
 __global__ void __launch_bounds__(kPatchBlock) k_patch_shared(int64_t ns, const int32_t* __restrict__ srp,
                                                               const int32_t* __restrict__ spos,
-                                                              const int32_t* __restrict__ sdof,
+                                                              const int32_t* __restrict__ sdof, int64_t sbase,
                                                               const double* __restrict__ spart,
                                                               const double* __restrict__ dscale,
                                                               double* __restrict__ y, const double* __restrict__ dotv,
@@ -229,13 +251,49 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_shared(int64_t ns, const 
                     : ((OUT == OUT_BRAS_CG || OUT == OUT_STAT) ? cg.sc[S_ALPHA] : 0.0);
   const double c2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int64_t s = (int64_t)blockIdx.x * kPatchBlock + threadIdx.x; s < ns; s += (int64_t)gridDim.x * kPatchBlock) {
-    const int32_t k0 = srp[s], k1 = srp[s + 1];
-    double acc = 0.0;
-    for (int32_t k = k0; k < k1; ++k) acc += spart[spos[k]];
-    const int32_t g = sdof[s];
-    if (DS) acc *= dscale[g];
-    patch_epilogue<OUT>(g, acc, c1, c2, cg, y, dotv, a0, a1, a2);
+  constexpr int U = kPatchSharedPerThread;
+  for (int64_t s0 = (int64_t)blockIdx.x * kPatchSharedPerBlock + threadIdx.x; s0 < ns;
+       s0 += (int64_t)gridDim.x * kPatchSharedPerBlock) {
+    // U shared DOFs per thread, their loads issued together
+    int32_t k0[U], k1[U];
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t s = s0 + (int64_t)u * kPatchBlock;
+      const bool ok = s < ns;
+      k0[u] = ok ? srp[s] : 0;
+      k1[u] = ok ? srp[s + 1] : 0;
+    }
+    // runs are short (the patches of one DOF): the first two partials of
+    // every DOF are loaded together
+    int32_t i0[U], i1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      i0[u] = k0[u] < k1[u] ? spos[k0[u]] : 0;
+      i1[u] = k0[u] + 1 < k1[u] ? spos[k0[u] + 1] : 0;
+    }
+    double v0[U], v1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v0[u] = k0[u] < k1[u] ? spart[i0[u]] : 0.0;
+      v1[u] = k0[u] + 1 < k1[u] ? spart[i1[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double t = v0[u];
+      if (k0[u] + 1 < k1[u]) t += v1[u];
+      for (int32_t k = k0[u] + 2; k < k1[u]; ++k) t += spart[spos[k]];
+      acc[u] = t;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t s = s0 + (int64_t)u * kPatchBlock;
+      if (s >= ns) continue;
+      const int32_t g = sdof ? sdof[s] : (int32_t)(sbase + s);
+      double v = acc[u];
+      if (DS) v *= dscale[g];
+      patch_epilogue<OUT>(g, v, c1, c2, cg, y, dotv, a0, a1, a2);
+    }
   }
   patch_dots<OUT>(a0, a1, a2, pbase + blockIdx.x, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, sh);
 }
@@ -244,16 +302,22 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_shared(int64_t ns, const 
 template <int NL, int FORM, int NSYM, typename T, int OUT, bool DS, int VAR>
 int patch_launch(Ctx* c, const PatchCall& pc, const T* ap, const double* symtab, const double* coefK, int nsym,
                  const double* dscale, hipStream_t s) {
+  // dscale: D^-1 (scaled H1 BRAS) in the caller's numbering; replaced below in internal mode
   const PatchDev& pt = c->pt;
-  PatchArgs pa{pt.pe, pt.pd, pt.pnl, pt.pdof, pt.code, pt.sbase, c->E, pt.lbits, pt.maxrank};
+  const bool ip = c->ip_mode != 0;   // vectors in the internal DOF numbering
+  const int xcd_per = c->patch_xcd ? (int)((pt.npatch + 7) / 8) : 0;
+  PatchArgs pa{pt.pe, pt.pd, pt.pnl, ip ? pt.pidx : pt.pdof, pt.code, pt.sbase, c->E, pt.lbits, pt.maxrank,
+               pt.npatch, xcd_per};
+  if (ip && dscale) dscale = pt.invd_ip;
   const int words = pt.maxdofs > 3 * kPatchBlock ? pt.maxdofs : 3 * kPatchBlock;
-  k_patch<NL, FORM, NSYM, T, OUT, DS, VAR><<<(unsigned)pt.npatch, kPatchBlock, sizeof(double) * words, s>>>(
+  const unsigned grid = xcd_per > 0 ? (unsigned)(8 * xcd_per) : (unsigned)pt.npatch;
+  k_patch<NL, FORM, NSYM, T, OUT, DS, VAR><<<grid, kPatchBlock, sizeof(double) * words, s>>>(
       pa, pc.in, ap, symtab, coefK, nsym, dscale, pc.y, pc.dotv, pc.dotpart, pc.cg, pc.spart);
   BRAS_HIP(hipGetLastError());
   if (pt.ns > 0) {
-    k_patch_shared<OUT, DS><<<(unsigned)pt.nb2, kPatchBlock, 0, s>>>(pt.ns, pt.srp, pt.spos, pt.sdof, pc.spart,
-                                                                       dscale, pc.y, pc.dotv, pc.dotpart,
-                                                                       pt.npatch, pc.in.active, pc.cg);
+    k_patch_shared<OUT, DS><<<(unsigned)pt.nb2, kPatchBlock, 0, s>>>(
+        pt.ns, pt.srp, pt.spos, ip ? nullptr : pt.sdof, pt.nloc_total, pc.spart, dscale, pc.y, pc.dotv, pc.dotpart,
+        pt.npatch, pc.in.active, pc.cg);
     BRAS_HIP(hipGetLastError());
   }
   return BRAS_OK;

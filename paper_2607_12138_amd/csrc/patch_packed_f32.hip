@@ -5,7 +5,7 @@ namespace bras {
 
 template <int NL, int OUT>
 static int bras_k(Ctx* c, const PatchCall& pc, hipStream_t s) {
-  return patch_launch<NL, FORM_PACKED, 0, float, OUT, false, 256>(c, pc, (const float*)c->ainv, nullptr, nullptr, 0, nullptr, s);
+  return patch_launch<NL, FORM_PACKED, 0, float, OUT, false, 272>(c, pc, (const float*)c->ainv, nullptr, nullptr, 0, nullptr, s);
 }
 
 template <int NL>

@@ -217,19 +217,15 @@ int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int
   }
   const int64_t npatch = (int64_t)plan->pe.size() - 1;
   plan->npatch = npatch;
-  // per-patch DOF lists and copy codes
-  plan->pd.assign(1, 0);
-  plan->pnl.assign(npatch, 0);
-  plan->pdof.clear();
-  std::vector<uint32_t> jr(E * nl, 0);   // (j, rank) per copy, packed below
-  plan->sbase.assign(npatch + 1, 0);
+  // per-patch DOF lists: local DOFs (every copy in the patch) first, by DOF;
+  // then the shared ones, in the order of the shared-DOF numbering below
   std::vector<int32_t> lj(n, -1);       // DOF -> index in the current patch's first-seen list
   std::vector<int32_t> seen, cnt_in;    // first-seen DOF list and copy counts
-  std::vector<int32_t> order, jof;
-  int maxd = 0, maxr = 0;
-  std::vector<int64_t> shared_cnt(n, 0);
+  std::vector<int64_t> lloc_off(npatch + 1, 0), lsh_off(npatch + 1, 0);
+  std::vector<int32_t> lloc, lsh;       // per patch: local DOFs (sorted), shared DOFs (unsorted)
+  std::vector<int32_t> shared_cnt(n, 0);
   for (int64_t p = 0; p < npatch; ++p) {
-    const int32_t e0 = plan->pe[p], e1 = plan->pe[p + 1], ne = e1 - e0;
+    const int32_t e0 = plan->pe[p], e1 = plan->pe[p + 1];
     seen.clear();
     cnt_in.clear();
     for (int32_t e = e0; e < e1; ++e) {
@@ -244,42 +240,80 @@ int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int
         ++cnt_in[lj[g]];
       }
     }
-    const int nd = (int)seen.size();
-    // order: local DOFs (every copy in the patch) by DOF, then shared by DOF
-    order.resize(nd);
-    for (int k = 0; k < nd; ++k) order[k] = k;
-    std::sort(order.begin(), order.end(), [&](int a, int b) {
-      const bool la = cnt_in[a] == mult[seen[a]], lb = cnt_in[b] == mult[seen[b]];
-      if (la != lb) return la;
-      return seen[a] < seen[b];
-    });
-    jof.assign(nd, 0);
-    int nloc = 0;
-    for (int k = 0; k < nd; ++k) {
-      jof[order[k]] = k;
-      const int32_t g = seen[order[k]];
-      plan->pdof.push_back(g);
-      if (cnt_in[order[k]] == mult[g]) ++nloc;
-      else ++shared_cnt[g];
+    const size_t l0 = lloc.size();
+    for (size_t k = 0; k < seen.size(); ++k) {
+      const int32_t g = seen[k];
+      if (cnt_in[k] == mult[g]) {
+        lloc.push_back(g);
+      } else {
+        lsh.push_back(g);
+        ++shared_cnt[g];
+      }
+      lj[g] = -1;
     }
+    std::sort(lloc.begin() + l0, lloc.end());
+    lloc_off[p + 1] = (int64_t)lloc.size();
+    lsh_off[p + 1] = (int64_t)lsh.size();
+  }
+  // Shared DOFs ordered by the list of patches that hold them, then by DOF:
+  // the DOFs of one interface between patches are then consecutive, both in
+  // this numbering and in each of those patches' lists, so the second pass
+  // reads their partial sums in runs.
+  std::vector<int64_t> sp_off(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) sp_off[i + 1] = sp_off[i] + shared_cnt[i];
+  std::vector<int32_t> sp_list(sp_off[n]);   // patches of each shared DOF, increasing
+  {
+    std::vector<int64_t> fill(sp_off.begin(), sp_off.end() - 1);
+    for (int64_t p = 0; p < npatch; ++p)
+      for (int64_t k = lsh_off[p]; k < lsh_off[p + 1]; ++k) sp_list[fill[lsh[k]]++] = (int32_t)p;
+  }
+  plan->sdof.clear();
+  for (int64_t i = 0; i < n; ++i)
+    if (shared_cnt[i] > 0) plan->sdof.push_back((int32_t)i);
+  std::sort(plan->sdof.begin(), plan->sdof.end(), [&](int32_t a, int32_t b) {
+    const int64_t na = sp_off[a + 1] - sp_off[a], nb = sp_off[b + 1] - sp_off[b];
+    for (int64_t k = 0; k < na && k < nb; ++k)
+      if (sp_list[sp_off[a] + k] != sp_list[sp_off[b] + k]) return sp_list[sp_off[a] + k] < sp_list[sp_off[b] + k];
+    if (na != nb) return na < nb;
+    return a < b;
+  });
+  std::vector<int32_t> sidx(n, -1);
+  for (size_t k = 0; k < plan->sdof.size(); ++k) sidx[plan->sdof[k]] = (int32_t)k;
+  // final patch lists, copy codes and ranks
+  plan->pd.assign(1, 0);
+  plan->pnl.assign(npatch, 0);
+  plan->pdof.clear();
+  plan->sbase.assign(npatch + 1, 0);
+  std::vector<uint32_t> jr(E * nl, 0);   // (j, rank) per copy, packed below
+  std::vector<int32_t> jof(n, -1), rk;
+  int maxd = 0, maxr = 0;
+  for (int64_t p = 0; p < npatch; ++p) {
+    const int32_t e0 = plan->pe[p], e1 = plan->pe[p + 1], ne = e1 - e0;
+    const int64_t d0 = (int64_t)plan->pdof.size();
+    for (int64_t k = lloc_off[p]; k < lloc_off[p + 1]; ++k) plan->pdof.push_back(lloc[k]);
+    std::sort(lsh.begin() + lsh_off[p], lsh.begin() + lsh_off[p + 1],
+              [&](int32_t a, int32_t b) { return sidx[a] < sidx[b]; });
+    for (int64_t k = lsh_off[p]; k < lsh_off[p + 1]; ++k) plan->pdof.push_back(lsh[k]);
+    const int nd = (int)((int64_t)plan->pdof.size() - d0);
+    const int nloc = (int)(lloc_off[p + 1] - lloc_off[p]);
+    for (int k = 0; k < nd; ++k) jof[plan->pdof[d0 + k]] = k;
     plan->pnl[p] = nloc;
     plan->pd.push_back((int32_t)plan->pdof.size());
     plan->sbase[p + 1] = plan->sbase[p] + (nd - nloc);
     maxd = std::max(maxd, nd);
     // ranks in element order
-    std::vector<int32_t> rk(nd, 0);
+    rk.assign(nd, 0);
     for (int32_t e = e0; e < e1; ++e) {
       const int64_t K = plan->perm[e];
       for (int l = 0; l < nl; ++l) {
-        const int32_t g = l2g[K * nl + l];
-        const int32_t j = jof[lj[g]];
+        const int32_t j = jof[l2g[K * nl + l]];
         const int32_t r = rk[j]++;
         maxr = std::max(maxr, r);
         // j and r packed once lbits is known: keep (j, r) for now
         jr[(int64_t)e0 * nl + (int64_t)l * ne + (e - e0)] = (uint32_t)j | ((uint32_t)r << 16);
       }
     }
-    for (int k = 0; k < nd; ++k) lj[seen[k]] = -1;
+    for (int k = 0; k < nd; ++k) jof[plan->pdof[d0 + k]] = -1;
   }
   // code packing: lbits for j, the rank above (maxd <= Dmax <= 2^(16 - rbits), maxr < maxmult <= 2^rbits)
   int lbits = 1;
@@ -291,27 +325,48 @@ int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int
   plan->maxdofs = maxd;
   plan->code.resize(E * nl);
   for (int64_t q = 0; q < E * nl; ++q) plan->code[q] = (uint16_t)((jr[q] & 0xFFFFu) | ((jr[q] >> 16) << lbits));
-  // second pass: the shared DOFs in increasing order, each with its partials in patch order
-  plan->srp.assign(1, 0);
-  plan->sdof.clear();
-  std::vector<int64_t> sfirst(n + 1, 0);
-  for (int64_t i = 0; i < n; ++i) sfirst[i + 1] = sfirst[i] + shared_cnt[i];
-  plan->spos.assign(sfirst[n], 0);
+  // second pass: shared DOF s has partials spos[srp[s] .. srp[s+1]), one per
+  // patch that holds it, in patch order (patches write theirs patch-major)
+  const int64_t ns = (int64_t)plan->sdof.size();
+  plan->srp.assign(ns + 1, 0);
+  for (int64_t k = 0; k < ns; ++k) plan->srp[k + 1] = plan->srp[k] + shared_cnt[plan->sdof[k]];
+  plan->spos.assign(plan->srp[ns], 0);
   {
-    std::vector<int64_t> fill(sfirst.begin(), sfirst.end() - 1);
+    std::vector<int32_t> fill(plan->srp.begin(), plan->srp.end() - 1);
     for (int64_t p = 0; p < npatch; ++p) {
       const int32_t d0 = plan->pd[p], d1 = plan->pd[p + 1], nloc = plan->pnl[p];
       for (int32_t j = d0 + nloc; j < d1; ++j) {
-        const int32_t g = plan->pdof[j];
-        plan->spos[fill[g]++] = plan->sbase[p] + (j - d0 - nloc);
+        const int32_t s = sidx[plan->pdof[j]];
+        plan->spos[fill[s]++] = plan->sbase[p] + (j - d0 - nloc);
+      }
+    }
+  }
+  // internal numbering: local DOFs patch by patch, then the shared DOFs
+  int64_t nloc_total = 0;
+  for (int64_t p = 0; p < npatch; ++p) nloc_total += plan->pnl[p];
+  plan->nloc_total = nloc_total;
+  plan->ip2g.assign(n, -1);
+  plan->pidx.assign(plan->pdof.size(), 0);
+  std::vector<int32_t> g2ip(n, -1);
+  for (size_t k = 0; k < plan->sdof.size(); ++k) {
+    plan->ip2g[nloc_total + (int64_t)k] = plan->sdof[k];
+    g2ip[plan->sdof[k]] = (int32_t)(nloc_total + (int64_t)k);
+  }
+  int64_t lb = 0;
+  for (int64_t p = 0; p < npatch; ++p) {
+    const int32_t d0 = plan->pd[p], d1 = plan->pd[p + 1], nloc = plan->pnl[p];
+    for (int32_t j = d0; j < d1; ++j) {
+      const int32_t g = plan->pdof[j];
+      if (j - d0 < nloc) {
+        plan->ip2g[lb] = g;
+        plan->pidx[j] = (int32_t)lb++;
+      } else {
+        plan->pidx[j] = g2ip[g];
       }
     }
   }
   for (int64_t i = 0; i < n; ++i)
-    if (shared_cnt[i] > 0) {
-      plan->sdof.push_back((int32_t)i);
-      plan->srp.push_back((int32_t)sfirst[i + 1]);
-    }
+    if (plan->ip2g[i] < 0) return 1;   // every DOF has a copy, so this cannot happen
   return 0;
 }
 

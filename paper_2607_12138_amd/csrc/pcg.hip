@@ -198,6 +198,48 @@ void cg_free(Ctx* c) {
   c->cg = nullptr;
 }
 
+// Vectors into / out of the internal DOF numbering of a patch plan:
+// in: dst[i] = src[ip2g[i]]; out: dst[ip2g[i]] = src[i].
+__global__ void __launch_bounds__(kBS) k_perm_in(int64_t n, const int32_t* __restrict__ ip2g,
+                                                 const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[ip2g[i]];
+}
+__global__ void __launch_bounds__(kBS) k_perm_out(int64_t n, const int32_t* __restrict__ ip2g,
+                                                  const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[ip2g[i]] = src[i];
+}
+
+// A solve's vectors (b, x) enter the CG state, and x leaves it, in the
+// caller's numbering or, when the one-column passes run in patch form, in the
+// plan's internal numbering (c->ip_mode is set for the duration of the solve,
+// including graph capture).
+struct SolveNumbering {
+  Ctx* c;
+  bool ip;
+  SolveNumbering(Ctx* c_, int R) : c(c_), ip(patch_active(c_, R)) { c->ip_mode = ip ? 1 : 0; }
+  ~SolveNumbering() { c->ip_mode = 0; }
+  int in(const double* src, double* dst, size_t bytes, hipStream_t s) const {
+    if (!ip) {
+      BRAS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+      return BRAS_OK;
+    }
+    k_perm_in<<<(unsigned)((c->n + kBS - 1) / kBS), kBS, 0, s>>>(c->n, c->pt.ip2g, src, dst);
+    BRAS_HIP(hipGetLastError());
+    return BRAS_OK;
+  }
+  int out(const double* src, double* dst, size_t bytes, hipStream_t s) const {
+    if (!ip) {
+      BRAS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+      return BRAS_OK;
+    }
+    k_perm_out<<<(unsigned)((c->n + kBS - 1) / kBS), kBS, 0, s>>>(c->n, c->pt.ip2g, src, dst);
+    BRAS_HIP(hipGetLastError());
+    return BRAS_OK;
+  }
+};
+
 static size_t state_bytes(int R) { return sizeof(double) * S_NSC * R + sizeof(int) * I_NIC * R; }
 
 static int cg_alloc(Ctx* c, int R) {
@@ -427,6 +469,7 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
     return report(c, nrhs, rtol, maxit, iters_h, relres_h);
   }
   c->last_path = 0;
+  const SolveNumbering num(c, nrhs);
   std::vector<hipGraphExec_t>* graphs = nullptr;
   if ((st = get_graphs(c, pc, flexible, maxit, &graphs))) return st;
   // order the internal stream after the caller's prior work
@@ -434,8 +477,10 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   BRAS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   BRAS_HIP(hipEventRecord(ev, us));
   BRAS_HIP(hipStreamWaitEvent(s, ev, 0));
-  BRAS_HIP(hipMemcpyAsync(g->b, b_d, vec, hipMemcpyDeviceToDevice, s));
-  BRAS_HIP(hipMemcpyAsync(g->x, x_d, vec, hipMemcpyDeviceToDevice, s));
+  if ((st = num.in(b_d, g->b, vec, s)) || (st = num.in(x_d, g->x, vec, s))) {
+    (void)hipEventDestroy(ev);
+    return st;
+  }
   const int R = nrhs;
   const int nb = vector_blocks(c, R);
   int restarts = 0;
@@ -467,8 +512,7 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   }
   c->last_restarts = restarts;
   if (st == BRAS_OK) {
-    hipError_t e = hipMemcpyAsync(x_d, g->x, vec, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) st = fail(BRAS_EHIP, "copy of the solution failed");
+    st = num.out(g->x, x_d, vec, s);
     BRAS_HIP(hipEventRecord(ev, s));
     BRAS_HIP(hipStreamWaitEvent(us, ev, 0));
     BRAS_HIP(hipStreamSynchronize(s));
@@ -639,6 +683,7 @@ static int stationary(Ctx* c, int pc, const std::vector<double>& ca, const std::
     return report(c, R, rtol, maxit, iters_h, relres_h, false);
   }
   c->last_path = 0;
+  const SolveNumbering num(c, nrhs);
   std::vector<hipGraphExec_t>* graphs = nullptr;
   if ((st = capture_graphs(c, CgState::Key{1, pc, 0, maxit}, [&](hipStream_t ss) { return st_iteration(c, pc, maxit, ss); },
                            &graphs)))
@@ -648,8 +693,10 @@ static int stationary(Ctx* c, int pc, const std::vector<double>& ca, const std::
   BRAS_HIP(hipEventRecord(ev, us));
   BRAS_HIP(hipStreamWaitEvent(s, ev, 0));
   BRAS_HIP(hipMemcpyAsync(g->stcoef, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
-  BRAS_HIP(hipMemcpyAsync(g->b, b_d, vec, hipMemcpyDeviceToDevice, s));
-  BRAS_HIP(hipMemcpyAsync(g->x, x_d, vec, hipMemcpyDeviceToDevice, s));
+  if ((st = num.in(b_d, g->b, vec, s)) || (st = num.in(x_d, g->x, vec, s))) {
+    (void)hipEventDestroy(ev);
+    return st;
+  }
   const int nbv = vector_blocks(c, R);
   k_zero<<<nbv, kBS, 0, s>>>(c->n * R, g->p);
   k_set_int<<<1, kBS, 0, s>>>(g->ic + I_ACTIVE * R, R, 1);   // every column takes part in the first residual
@@ -666,8 +713,7 @@ static int stationary(Ctx* c, int pc, const std::vector<double>& ca, const std::
     st = read_state(c, s);
   }
   if (st == BRAS_OK) {
-    hipError_t e = hipMemcpyAsync(x_d, g->x, vec, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) st = fail(BRAS_EHIP, "copy of the solution failed");
+    st = num.out(g->x, x_d, vec, s);
     (void)hipEventRecord(ev, s);
     (void)hipStreamWaitEvent(us, ev, 0);
     (void)hipStreamSynchronize(s);

@@ -233,6 +233,13 @@ __global__ void k_permute_rows(const double* __restrict__ in, const int32_t* __r
   out[t] = in[(int64_t)perm[K] * w + i];
 }
 
+// dst[i] = src[map[i]] (a vector in the internal DOF numbering of a patch plan)
+__global__ void k_gather_vec(const double* __restrict__ src, const int32_t* __restrict__ map, int64_t n,
+                             double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[map[i]];
+}
+
 // AoS [E][nsym] -> SoA [nsym][E]
 __global__ void k_transpose_coef(const double* __restrict__ in, int64_t E, int nsym, double* __restrict__ out) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -465,6 +472,18 @@ static int reset_flag(Ctx* c, hipStream_t s) {
 }
 
 static int element_setup_ordered(Ctx* c, const double* elem_d, hipStream_t s);
+static int element_setup_permuted(Ctx* c, const double* elem_d, hipStream_t s);
+
+// Element data (caller's order) -> element inverses and diag(M), and the
+// internal-numbering copy of diag(M)^-1 when the handle has a patch plan.
+int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
+  const int st = element_setup_permuted(c, elem_d, s);
+  if (st || !c->pt.invdiag_ip) return st;
+  k_gather_vec<<<blocks_for(c->n, 256), 256, 0, s>>>(c->invdiag, c->pt.ip2g, c->n, c->pt.invdiag_ip);
+  BRAS_HIP(hipGetLastError());
+  BRAS_HIP(hipStreamSynchronize(s));
+  return BRAS_OK;
+}
 
 // The caller's number of internal element K (errors name the caller's element).
 static int caller_element(const Ctx* c, int K) {
@@ -476,7 +495,7 @@ static int caller_element(const Ctx* c, int K) {
 
 // Element data arrive in the caller's element order; with a patch plan the
 // handle's order is patch-major, so they are permuted first.
-int element_setup(Ctx* c, const double* elem_d, hipStream_t s) {
+static int element_setup_permuted(Ctx* c, const double* elem_d, hipStream_t s) {
   if (!c->pt.perm) return element_setup_ordered(c, elem_d, s);
   const int w = c->form == BRAS_ELEM_SCALED_REF ? 1 : (c->form == BRAS_ELEM_METRIC_REF ? c->nsym : c->nl * c->nl);
   struct Tmp {
@@ -563,7 +582,7 @@ static void free_ctx(Ctx* c) {
   void* ptrs[] = {c->l2g, c->mult, c->invd, c->rowptr, c->chunk, c->slot, c->ref, c->refinv, c->coef, c->icoef, c->ainv,
                   c->symtab, c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag, c->ref_pk, c->refinv_pk,
                   c->pt.perm, c->pt.pe, c->pt.pd, c->pt.pnl, c->pt.pdof, c->pt.code, c->pt.sbase, c->pt.srp,
-                  c->pt.spos, c->pt.sdof, c->pt.part};
+                  c->pt.spos, c->pt.sdof, c->pt.part, c->pt.ip2g, c->pt.pidx, c->pt.invd_ip, c->pt.invdiag_ip};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   cg_free(c);
@@ -595,6 +614,7 @@ static int patch_setup(Ctx* c, hipStream_t s) {
   int P = kPatchElems, D = kPatchMaxDofs;
   if (const char* e = getenv("BRAS_PATCH_ELEMS")) P = atoi(e);
   if (const char* e = getenv("BRAS_PATCH_DOFS")) D = atoi(e);
+  if (const char* e = getenv("BRAS_PATCH_XCD")) c->patch_xcd = atoi(e) != 0;
   if (P < 1 || P > kPatchBlock) return fail(BRAS_EINVAL, "BRAS_PATCH_ELEMS must be in 1..%d", kPatchBlock);
   if (D < 1 || D > 65536) return fail(BRAS_EINVAL, "BRAS_PATCH_DOFS must be in 1..65536");
   const int64_t n = c->n, E = c->E, nl = c->nl, nbr = c->nbr;
@@ -621,14 +641,20 @@ static int patch_setup(Ctx* c, hipStream_t s) {
   if ((st = up(&pt.perm, plan.perm)) || (st = up(&pt.pe, plan.pe)) || (st = up(&pt.pd, plan.pd)) ||
       (st = up(&pt.pnl, plan.pnl)) || (st = up(&pt.pdof, plan.pdof)) || (st = up(&pt.code, plan.code)) ||
       (st = up(&pt.sbase, plan.sbase)) || (st = up(&pt.srp, plan.srp)) || (st = up(&pt.spos, plan.spos)) ||
-      (st = up(&pt.sdof, plan.sdof)))
+      (st = up(&pt.sdof, plan.sdof)) || (st = up(&pt.ip2g, plan.ip2g)) || (st = up(&pt.pidx, plan.pidx)))
     return st;
+  pt.nloc_total = plan.nloc_total;
+  if (hipMalloc((void**)&pt.invd_ip, sizeof(double) * n) != hipSuccess ||
+      hipMalloc((void**)&pt.invdiag_ip, sizeof(double) * n) != hipSuccess)
+    return fail(BRAS_ENOMEM, "patch plan allocation failed");
+  k_gather_vec<<<blocks_for(n, 256), 256, 0, s>>>(c->invd, pt.ip2g, n, pt.invd_ip);
+  BRAS_HIP(hipGetLastError());
   BRAS_HIP(hipMemcpy(c->l2g, il2g.data(), sizeof(int32_t) * nbr, hipMemcpyHostToDevice));
   pt.ns = (int64_t)plan.sdof.size();
   pt.nspart = (int64_t)plan.spos.size();
   if (hipMalloc((void**)&pt.part, sizeof(double) * (size_t)(pt.nspart > 0 ? pt.nspart : 1)) != hipSuccess)
     return fail(BRAS_ENOMEM, "patch partial-sum buffer allocation failed");
-  const int64_t nb2 = (pt.ns + kPatchBlock - 1) / kPatchBlock;
+  const int64_t nb2 = (pt.ns + kPatchSharedPerBlock - 1) / kPatchSharedPerBlock;
   pt.nb2 = (int)(nb2 < kPatchSharedBlocks ? (nb2 > 0 ? nb2 : 1) : kPatchSharedBlocks);
   pt.lbits = plan.lbits;
   pt.maxrank = plan.maxrank;
