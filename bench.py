@@ -30,6 +30,7 @@ import workloads  # noqa: E402
 
 METRIC = "BRAS-PCG time to 1e-8 rel. residual vs Jacobi-PCG; BRAS apply HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 DEFAULT = "n1curl2_3d_48_jit"
 
 
@@ -235,14 +236,17 @@ def schur_section(prob, w, reps=3):
     return out
 
 
-def cpu_baseline(w, its_gpu, budget_s=20.0):
+def cpu_baseline(w, its_gpu, budget_s=20.0, y_gpu=None):
     """The oracle's BRAS-PCG on the same workload, matrix-free (its element
     route), one thread.  Setup (mesh, numbering, element matrices and
     inverses) is excluded, as the paper excludes preconditioner
     construction.  A bounded sample: at most budget_s of iterations; the
-    time per iteration is scaled to the GPU's iteration count."""
+    time per iteration is scaled to the GPU's iteration count.
+    With y_gpu (the device BRAS apply of the right-hand side, column 0) it also
+    returns that apply's error against the oracle's float64 one."""
     from threadpoolctl import threadpool_limits
     from oracle import fe, mesh, dofmap, assembly, pcg
+    extra = {}
     with threadpool_limits(1):
         ref = fe.reference_element(w.family, w.dim, w.degree)
         coords, cells = mesh.structured_mesh(w.dim, w.N, jitter=w.jitter, seed=w.mesh_seed)
@@ -251,10 +255,15 @@ def cpu_baseline(w, its_gpu, budget_s=20.0):
         mats = assembly.element_matrices(ref, coords, cells, rho)
         inv = assembly.element_inverses(mats)
         d = np.bincount(pi.ravel(), minlength=n).astype(float)
-        b = workloads.rhs(n, 1, w.seed(1))
-        b = b if b.ndim == 1 else b[:, 0]
+        b = workloads.rhs(n, w.nrhs, w.seed(1))
+        b = b if b.ndim == 1 else np.ascontiguousarray(b[:, 0])   # column 0 of the device workload
         M = lambda v: assembly.mass_apply_matrix_free(pi, mats, v)        # noqa: E731
         C = lambda v: assembly.bras_apply_matrix_free(pi, inv, d, v)     # noqa: E731
+        if y_gpu is not None:
+            y64 = C(b)
+            dy = y_gpu - y64
+            extra = {"bras_apply_rel_err_2": float(np.linalg.norm(dy) / np.linalg.norm(y64)),
+                     "bras_apply_rel_err_inf": float(np.max(np.abs(dy)) / np.max(np.abs(y64)))}
         t0 = time.perf_counter()
         M(b)
         C(b)
@@ -265,7 +274,9 @@ def cpu_baseline(w, its_gpu, budget_s=20.0):
         dt = time.perf_counter() - t0
     per_it = dt / max(done, 1)
     full = bool(ok)
-    return {
+    if full:
+        extra["oracle_iterations"] = int(done)
+    return extra, {
         "value": round(per_it * (done if full else its_gpu) * 1e3, 3),
         "unit": "ms per solve (BRAS-PCG, one right-hand side)",
         "cores": 1,
@@ -275,6 +286,59 @@ def cpu_baseline(w, its_gpu, budget_s=20.0):
                    "workload (numpy, 1 thread; setup excluded), %.1f s, scaled to %d iterations"
                    % (done, its_gpu, dt, its_gpu)),
     }
+
+
+def gradient_section(prob, w, b, steps=2):
+    """x = M(rho)^-1 b and its gradient (autograd: BRAS-PCG forward, adjoint
+    BRAS-PCG and the per-element contraction backward) for the density
+    workload, loss 0.5 ||x - x*||^2, at the workload's tolerance."""
+    import torch
+    from paper_2607_12138_amd.autograd import mass_solve
+    rho = torch.from_numpy(workloads.density(prob.E, w.seed(2))).cuda()
+    xs = torch.from_numpy(workloads.target(prob.n, w.seed(3))).cuda()
+    fw = bw = None
+    for k in range(steps + 1):
+        bt = b.clone().requires_grad_(True)
+        rt = rho.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = mass_solve(bt, rt, prob, w.tol)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * torch.sum((x - xs) ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if k > 0:   # the first pass captures the graphs
+            fw = (t1 - t0) if fw is None else min(fw, t1 - t0)
+            bw = (t2 - t1) if bw is None else min(bw, t2 - t1)
+    return {"forward_ms": round(fw * 1e3, 3), "backward_ms": round(bw * 1e3, 3), "rtol": w.tol,
+            "note": "best of %d; backward = adjoint BRAS-PCG + per-element contraction" % steps}
+
+
+def setup_section(prob):
+    """Time of bras_update (element coefficients -> per-element FP64
+    Cholesky, triangular inverse and folded inverse or Gram factor, and
+    diag(M)), against the FP64 peak: about n_loc^3 flops per element (n^3/3
+    each for the factorisation, the triangular inverse and the product of the
+    inverse factors)."""
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    reps = 3
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.bras_update(prob.h, prob.elem_d)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    flop = float(prob.E) * prob.n_loc ** 3
+    if prob.form == L.ELEM_SCALED_REF:
+        flop = float(prob.n_loc) ** 3   # one shared reference inverse (the rest is per-element scaling)
+    tf = flop / best / 1e12
+    return {"update_ms": round(best * 1e3, 3), "gflop": round(flop / 1e9, 3), "tflops": round(tf, 4),
+            "frac_fp64_peak": round(tf / FP64_PEAK_TFLOPS, 5)}
 
 
 def main():
@@ -374,6 +438,15 @@ def main():
         print("assembled done: %s" % json.dumps(assembled), file=sys.stderr, flush=True)
         schur = schur_section(prob, w)
         print("schur done: %s" % json.dumps(schur), file=sys.stderr, flush=True)
+    y_b0 = None
+    if not a.no_cpu_baseline:
+        yb = prob.vec(w.nrhs)
+        L.bras_apply(prob.h, b, yb)
+        y_b0 = (yb if w.nrhs == 1 else yb[:, 0]).cpu().numpy()
+    grad = gradient_section(prob, w, b) if w.density else None
+    if grad:
+        print("gradient done: %s" % json.dumps(grad), file=sys.stderr, flush=True)
+    setup_upd = setup_section(prob)
     traffic = stored_traffic(w.name)
     out = {
         "metric": METRIC,
@@ -405,7 +478,8 @@ def main():
         "bras_apply_cold_gbs": round(nbytes / (cold_us * 1e-6) / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "bras_apply (element pass + transpose-map reduce)",
+                     "kernel": ("bras_apply (patch pass k_patch + shared-DOF pass k_patch_shared)"
+                                if prob.info("patches") > 0 else "bras_apply (element pass + transpose-map reduce)"),
                      "bytes_per_launch": int(nbytes), "us_per_launch": round(bras_us, 3),
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "source_digest": source_digest(),
@@ -414,10 +488,18 @@ def main():
         "stationary": stat,
         "assembled_bras": assembled,
         "schur_bras": schur,
+        "element_setup": setup_upd,
+        "gradient": grad,
+        "patches": int(prob.info("patches")),
     }
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, int(max(its_b)))
+        extra, out["cpu_baseline"] = cpu_baseline(w, int(max(its_b)), y_gpu=y_b0)
+        prec = {"apply_precision": w.prec}
+        prec.update(extra)
+        if "oracle_iterations" in extra:
+            prec["iterations_gpu_minus_oracle"] = int(its_b[0]) - extra["oracle_iterations"]
+        out["precision_vs_fp64_oracle"] = prec
     prob.close()
     print(json.dumps(out), flush=True)
 

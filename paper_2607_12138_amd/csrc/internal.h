@@ -79,8 +79,6 @@ struct Ctx {
   double* symtab = nullptr;  // METRIC_REF, n_loc <= kLaneMaxNL: pair tables packed [npack][sym_stride(nsym)]
   double* mpack = nullptr;   // packed float64 M_K [npack][E] for the mass pass (EXPLICIT, or METRIC with
                              // n_loc > kLaneMaxNL)
-  double* ref_pk = nullptr;    // SCALED_REF with a patch plan: Mhat, packed lower [npack]
-  double* refinv_pk = nullptr; // SCALED_REF with a patch plan: Mhat^-1, packed lower [npack]
   PatchDev pt;               // patch plan (npatch == 0: none); element order is then patch-major
   double* diag = nullptr;    // diag(M) [n]
   double* invdiag = nullptr; // [n]

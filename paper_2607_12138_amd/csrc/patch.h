@@ -43,6 +43,7 @@ struct PatchDev {
   int64_t ns = 0;          // shared DOFs
   int64_t nspart = 0;      // partial sums of shared DOFs
   int lbits = 0, maxrank = 0, maxdofs = 0;
+  int maxelems = 0;        // elements of the largest patch
   int nb2 = 0;             // work-groups of the shared-DOF pass
   int32_t* perm = nullptr;
   int32_t* pe = nullptr;

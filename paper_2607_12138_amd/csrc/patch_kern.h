@@ -121,6 +121,121 @@ __device__ __forceinline__ void patch_dots(double d0, double d1, double d2, int6
   }
 }
 
+// Phase 1 of a patch pass: wsh[j] = input value of patch DOF j, the loads of
+// U DOFs per thread issued together (out-of-range slots read DOF 0 of the
+// patch and store nothing).
+template <bool DS>
+__device__ __forceinline__ void patch_gather(const int32_t* __restrict__ pdof, int32_t d0, int nd, const InArgs& in,
+                                             double c2, const double* __restrict__ dscale, double* wsh) {
+  constexpr int U = 4;
+  for (int j0 = threadIdx.x; j0 < nd; j0 += U * kPatchBlock) {
+    int32_t g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * kPatchBlock;
+      g[u] = pdof[d0 + (j < nd ? j : 0)];
+    }
+    double v[U], v2[U], ds[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = in.x[g[u]];
+      v2[u] = in.x2 ? in.x2[g[u]] : 0.0;
+      ds[u] = DS ? dscale[g[u]] : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * kPatchBlock;
+      double t = in.x2 ? fma(c2, v2[u], v[u]) : v[u];
+      if (DS) t *= ds[u];
+      if (j < nd) wsh[j] = t;
+    }
+  }
+}
+
+// Phase 3 of a patch pass: the final values of the patch's local DOFs with
+// the epilogue, and the partial sums of its shared DOFs; the loads of U DOFs
+// per thread are issued before any of their stores.
+template <int OUT, bool DS>
+__device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
+                                             const double* wsh, const double* __restrict__ dscale, double ep1,
+                                             double ep2, const CgArgs& cg, double* __restrict__ y,
+                                             const double* __restrict__ dotv, double* __restrict__ spart,
+                                             int32_t sb, double& a0, double& a1, double& a2) {
+  constexpr int U = 4;
+  for (int j0 = threadIdx.x; j0 < nd; j0 += U * kPatchBlock) {
+    int32_t g[U];
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * kPatchBlock;
+      const bool in_range = j < nd;
+      g[u] = pdof[d0 + (in_range ? j : 0)];
+      acc[u] = in_range ? wsh[j] : 0.0;
+    }
+    // vectors the epilogue reads, for the U DOFs at once
+    double v0[U], v1[U], v2[U], v3[U], v4[U], ds[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t gg = g[u];
+      ds[u] = DS ? dscale[gg] : 1.0;
+      if (OUT == OUT_PLAIN) {
+        v0[u] = dotv ? dotv[gg] : 0.0;
+      } else if (OUT == OUT_MASS_CG) {
+        v0[u] = cg.p[gg];
+        v1[u] = cg.z[gg];
+      } else if (OUT == OUT_BRAS_CG) {
+        v0[u] = cg.q[gg];
+        v1[u] = cg.r[gg];
+        v2[u] = cg.x[gg];
+        v3[u] = cg.p[gg];
+        v4[u] = cg.flexible ? cg.z[gg] : 0.0;
+      } else if (OUT == OUT_RES) {
+        v0[u] = cg.b[gg];
+      } else {
+        v0[u] = cg.p[gg];
+        v1[u] = cg.x[gg];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * kPatchBlock;
+      if (j >= nd) continue;
+      if (j >= nloc) {
+        spart[sb + (j - nloc)] = acc[u];
+        continue;
+      }
+      const int32_t gg = g[u];
+      double t = acc[u];
+      if (DS) t *= ds[u];
+      if (OUT == OUT_PLAIN) {
+        y[gg] = t;
+        if (dotv) a0 = fma(t, v0[u], a0);
+      } else if (OUT == OUT_MASS_CG) {
+        const double pn = fma(ep1, v0[u], v1[u]);
+        cg.p[gg] = pn;
+        cg.q[gg] = t;
+        a0 = fma(pn, t, a0);
+      } else if (OUT == OUT_BRAS_CG) {
+        const double rn = fma(-ep1, v0[u], v1[u]);
+        cg.x[gg] = fma(ep1, v3[u], v2[u]);
+        if (cg.flexible) a2 = fma(rn, v4[u], a2);
+        cg.z[gg] = t;
+        cg.r[gg] = rn;
+        a0 = fma(rn, rn, a0);
+        a1 = fma(rn, t, a1);
+      } else if (OUT == OUT_RES) {
+        const double rv = v0[u] - t;
+        cg.r[gg] = rv;
+        a0 = fma(rv, rv, a0);
+      } else {
+        const double dn = fma(ep1, v0[u], ep2 * t);
+        cg.p[gg] = dn;
+        cg.x[gg] = v1[u] + dn;
+      }
+    }
+  }
+}
+
 // Waves per SIMD the register allocator is asked for: 4 (at most 128 VGPRs)
 // where a lane's element fits without spilling, else its natural count.
 template <int NL, typename T>
@@ -163,13 +278,7 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const int32_t d0 = pa.pd[p], nd = pa.pd[p + 1] - d0, nloc = pa.pnl[p];
   __syncthreads();   // the prologue's use of wsh is over
   // 1. patch DOF values
-  for (int j = tid; j < nd; j += kPatchBlock) {
-    const int32_t g = pa.pdof[d0 + j];
-    double v = in.x[g];
-    if (in.x2) v = fma(c2, in.x2[g], v);
-    if (DS) v *= dscale[g];
-    wsh[j] = v;
-  }
+  patch_gather<DS>(pa.pdof, d0, nd, in, c2, dscale, wsh);
   __syncthreads();
   // 2. one element per lane (idle lanes repeat element 0 and add nothing)
   const bool on = tid < ne;
@@ -217,17 +326,7 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  const int32_t sb = pa.sbase[p];
-  for (int j = tid; j < nd; j += kPatchBlock) {
-    double acc = wsh[j];
-    if (j < nloc) {
-      const int32_t g2 = pa.pdof[d0 + j];
-      if (DS) acc *= dscale[g2];
-      patch_epilogue<OUT>(g2, acc, ep1, ep2, cg, y, dotv, a0, a1, a2);
-    } else {
-      spart[sb + (j - nloc)] = acc;
-    }
-  }
+  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, wsh, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0, a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
 }

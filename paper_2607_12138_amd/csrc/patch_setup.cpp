@@ -324,7 +324,11 @@ int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int
   plan->maxrank = maxr;
   plan->maxdofs = maxd;
   plan->code.resize(E * nl);
-  for (int64_t q = 0; q < E * nl; ++q) plan->code[q] = (uint16_t)((jr[q] & 0xFFFFu) | ((jr[q] >> 16) << lbits));
+  for (int64_t q = 0; q < E * nl; ++q) {
+    const uint32_t cd = (jr[q] & 0xFFFFu) | ((jr[q] >> 16) << lbits);
+    if (cd == 0xFFFFu) return 1;   // reserved by the matrix-core pass for "no output"
+    plan->code[q] = (uint16_t)cd;
+  }
   // second pass: shared DOF s has partials spos[srp[s] .. srp[s+1]), one per
   // patch that holds it, in patch order (patches write theirs patch-major)
   const int64_t ns = (int64_t)plan->sdof.size();

@@ -580,7 +580,7 @@ static int element_setup_ordered(Ctx* c, const double* elem_d, hipStream_t s) {
 static void free_ctx(Ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->l2g, c->mult, c->invd, c->rowptr, c->chunk, c->slot, c->ref, c->refinv, c->coef, c->icoef, c->ainv,
-                  c->symtab, c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag, c->ref_pk, c->refinv_pk,
+                  c->symtab, c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag,
                   c->pt.perm, c->pt.pe, c->pt.pd, c->pt.pnl, c->pt.pdof, c->pt.code, c->pt.sbase, c->pt.srp,
                   c->pt.spos, c->pt.sdof, c->pt.part, c->pt.ip2g, c->pt.pidx, c->pt.invd_ip, c->pt.invdiag_ip};
   for (void* p : ptrs)
@@ -604,14 +604,22 @@ using namespace bras;
 
 // Patch plan of the handle (host partition of the validated map), the map in
 // patch-major element order, and the device copy of the plan.  Skipped for
-// element forms without a patch kernel, and when BRAS_PATCH=0 is set in the
-// environment; BRAS_PATCH_ELEMS / BRAS_PATCH_DOFS change the patch size and
-// DOF cap.
+// element forms without a patch kernel, for the scaled H1 form unless
+// BRAS_PATCH_SCALED=1, and when BRAS_PATCH=0 is set in the environment;
+// BRAS_PATCH_ELEMS / BRAS_PATCH_DOFS change the patch size and DOF cap.
 static int patch_setup(Ctx* c, hipStream_t s) {
   const char* env = getenv("BRAS_PATCH");
   if (env && atoi(env) == 0) return BRAS_OK;
   if (!patch_supported(c->form, c->prec, c->nl)) return BRAS_OK;
-  int P = kPatchElems, D = kPatchMaxDofs;
+  // scaled H1: the element / reduce passes are faster on the meshes measured
+  // (the element-pass matrix-core product there); the patch form on request
+  if (c->form == BRAS_ELEM_SCALED_REF) {
+    const char* e = getenv("BRAS_PATCH_SCALED");
+    if (!e || atoi(e) == 0) return BRAS_OK;
+  }
+  // the matrix-core pass of the scaled H1 form holds two 16-element column
+  // tiles per wavefront above n_loc 20 (patches of at most 128 elements)
+  int P = (c->form == BRAS_ELEM_SCALED_REF && c->nl > 20) ? 128 : kPatchElems, D = kPatchMaxDofs;
   if (const char* e = getenv("BRAS_PATCH_ELEMS")) P = atoi(e);
   if (const char* e = getenv("BRAS_PATCH_DOFS")) D = atoi(e);
   if (const char* e = getenv("BRAS_PATCH_XCD")) c->patch_xcd = atoi(e) != 0;
@@ -659,6 +667,7 @@ static int patch_setup(Ctx* c, hipStream_t s) {
   pt.lbits = plan.lbits;
   pt.maxrank = plan.maxrank;
   pt.maxdofs = plan.maxdofs;
+  for (int64_t q = 0; q < plan.npatch; ++q) pt.maxelems = std::max(pt.maxelems, plan.pe[q + 1] - plan.pe[q]);
   pt.npatch = plan.npatch;   // last: the plan is complete
   return BRAS_OK;
 }
@@ -824,15 +833,6 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     (void)hipFree(work);
     if (st) { free_ctx(c); return st; }
     if (f != 0x7fffffff) { free_ctx(c); return fail(BRAS_ENOTSPD, "reference mass matrix is not SPD"); }
-    if (c->pt.npatch > 0) {
-      // the patch passes read the shared matrices as packed lower triangles
-      const int npk = npack_of(n_loc);
-      TRY(dalloc(&c->ref_pk, npk));
-      TRY(dalloc(&c->refinv_pk, npk));
-      k_pack_sym<<<blocks_for(npk, 256), 256, 0, s>>>(c->ref, n_loc, 1, 1, c->ref_pk);
-      k_pack_sym<<<blocks_for(npk, 256), 256, 0, s>>>(c->refinv, n_loc, 1, 1, c->refinv_pk);
-      if (hipGetLastError() != hipSuccess) { free_ctx(c); return fail(BRAS_EHIP, "reference table packing failed"); }
-    }
   } else {
     if (form == BRAS_ELEM_METRIC_REF) {
       TRY(dalloc(&c->ref, (size_t)c->nsym * nn));
