@@ -31,6 +31,7 @@ import workloads  # noqa: E402
 METRIC = "BRAS-PCG time to 1e-8 rel. residual vs Jacobi-PCG; BRAS apply HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak (no sparsity)
 DEFAULT = "n1curl2_3d_48_jit"
 
 
@@ -54,7 +55,7 @@ def algorithmic_bytes(w, n, E, n_loc, R, prec):
 
 # sources of the operator passes and their data layout (the kernels the
 # stored counter measurements describe)
-APPLY_SOURCES = ("apply.hip", "elem_lane.h", "lane_*.hip", "elem_mfma.hip", "bf16.hip", "cg_common.h",
+APPLY_SOURCES = ("apply.hip", "elem_lane.h", "lane_*.hip", "elem_mfma.hip", "bf16.hip", "bf16_gram.h", "cg_common.h",
                  "block_reduce.h", "internal.h", "setup.hip", "patch*.hip", "patch*.h", "patch_setup.cpp")
 
 
@@ -316,6 +317,35 @@ def gradient_section(prob, w, b, steps=2):
             "note": "best of %d; backward = adjoint BRAS-PCG + per-element contraction" % steps}
 
 
+def mfma_section(prob, w, bras_us, iters=400, blocks=2048):
+    """BF16 apply: matrix-core FLOPs of the full apply against the BF16 peak,
+    and the LDS-resident microbenchmark of its element-local Gram products."""
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    nl, R = prob.n_loc, w.nrhs
+    per_round = L.bras_bench_bf16_local_gemm(nl, 1, 0)          # one element, 32 columns, zero padding included
+    issued = per_round * prob.E * ((R + 31) // 32)
+    useful = 2.0 * nl * (nl + 1) * R * prob.E                   # the two triangular products
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    L.bras_bench_bf16_local_gemm(nl, 10, blocks, out)            # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    flops = L.bras_bench_bf16_local_gemm(nl, iters, blocks, out)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    mb = flops / (ms * 1e-3) / 1e12
+    return {"full_apply": {"issued_tflops": round(issued / (bras_us * 1e-6) / 1e12, 2),
+                           "useful_tflops": round(useful / (bras_us * 1e-6) / 1e12, 2),
+                           "peak_tflops": BF16_PEAK_TFLOPS,
+                           "frac_issued": round(issued / (bras_us * 1e-6) / 1e12 / BF16_PEAK_TFLOPS, 4)},
+            "local_gemm_microbenchmark": {
+                "label": "microbenchmark: element-local Gram products on LDS-resident tiles, no HBM traffic",
+                "blocks": blocks, "rounds_per_block": iters, "ms": round(ms, 3), "issued_tflops": round(mb, 1),
+                "frac_of_bf16_peak": round(mb / BF16_PEAK_TFLOPS, 4),
+                "useful_fraction_of_issued": round(useful / issued, 4)}}
+
+
 def setup_section(prob):
     """Time of bras_update (element coefficients -> per-element FP64
     Cholesky, triangular inverse and folded inverse or Gram factor, and
@@ -447,6 +477,7 @@ def main():
     if grad:
         print("gradient done: %s" % json.dumps(grad), file=sys.stderr, flush=True)
     setup_upd = setup_section(prob)
+    mfma = mfma_section(prob, w, bras_us) if w.prec == "bf16" else None
     traffic = stored_traffic(w.name)
     out = {
         "metric": METRIC,
@@ -490,7 +521,10 @@ def main():
         "schur_bras": schur,
         "element_setup": setup_upd,
         "gradient": grad,
+        "mfma": mfma,
         "patches": int(prob.info("patches")),
+        "autotune": {"variant": int(variant), "patch_form": int(prob.info("patch_on")),
+                     "note": "bras_autotune's pick among the element-pass variants and the patch form"},
     }
     if not a.no_cpu_baseline:
         print("cpu baseline ...", file=sys.stderr, flush=True)

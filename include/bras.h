@@ -249,6 +249,8 @@ int bras_rho_grad(bras_handle h, const double* x_d, const double* lam_d,
                                   chebyshev_solve: 0 multi-pass, 1 one work-group */
 #define BRAS_INFO_PATCHES  10  /* patches of the one-column operator passes
                                   (0: element / reduce form only)             */
+#define BRAS_INFO_PATCH_ON 11  /* 1 when one-column passes run in patch form
+                                  (a plan exists and BRAS_OPT_PATCH is 1)     */
 int bras_info(bras_handle h, int what, int64_t* value_h);
 
 /* Copy derived setup data to device buffers for inspection:
@@ -385,16 +387,30 @@ int fixed_point_solve(bras_handle h, int pc, double omega, const double* b_d, do
 int chebyshev_solve(bras_handle h, int pc, double lmin, double lmax, const double* b_d, double* x_d, int nrhs,
                     double rtol, int maxit, int* iters_h, double* relres_h, void* stream);
 
-/* Time the element-pass scheduling variants this handle offers (3D H(curl) /
- * H(div) metric-form mass passes with n_loc <= 36: row order in batches of 2
- * or 4 table entries, diagonal order in batches of 8; every other handle has
- * one) on one mass + one BRAS apply at nrhs columns on stream, and keep the
- * fastest.  All variants compute the same products (the summation order of
- * each M_K entry's pair terms is the same; the order in which entries are
- * accumulated differs).  Read the choice back with BRAS_INFO_VARIANT; setting
- * BRAS_OPT_VARIANT overrides it.  Allocates two [n][nrhs] scratch vectors
- * for the duration of the call.  Synchronous. */
+/* Time the candidate forms of this handle's operator passes on one mass +
+ * one BRAS apply at nrhs columns on stream, and keep the fastest.  Candidates:
+ * the element-pass scheduling variants (3D H(curl) / H(div) metric-form mass
+ * passes with n_loc <= 36: row order in batches of 2 or 4 table entries,
+ * diagonal order in batches of 8; scaled H1: the FP64 matrix-core product or
+ * the per-row FMA product; every other handle has one) and, for nrhs = 1 on a
+ * handle with patches, the patch form.  All candidates compute the same
+ * operator (summation orders differ).  Read the choice back with
+ * BRAS_INFO_VARIANT and BRAS_INFO_PATCH_ON; BRAS_OPT_VARIANT and
+ * BRAS_OPT_PATCH override it.  Allocates two [n][nrhs] scratch vectors for
+ * the duration of the call.  Synchronous. */
 int bras_autotune(bras_handle h, int nrhs, void* stream);
+
+/* Microbenchmark, not an operator pass: the two element-local Gram products
+ * of the BF16 BRAS apply (U = Gtil W, Z = Gtil^T bf16(U) for 32 columns, the
+ * multi-right-hand-side form of eq. mhatinvbras_def) on tiles that stay in
+ * LDS, so that no HBM traffic limits them.  Launches `blocks` work-groups of
+ * `iters` rounds each on stream (asynchronous); each thread writes a checksum
+ * to out_d[blocks * 256] (float32, device, caller-owned).  *flops_h receives
+ * the issued matrix-core FLOPs of the launch (zero-padded tiles included).
+ * n_loc: 20, 36, 70 or 84 (BRAS_EINVAL otherwise).  blocks = 0 launches
+ * nothing and reports the FLOPs of one round of one work-group (one element,
+ * 32 columns). */
+int bras_bench_bf16_local_gemm(int n_loc, int iters, int blocks, float* out_d, long long* flops_h, void* stream);
 
 const char* bras_last_error(void);
 

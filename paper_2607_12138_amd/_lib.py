@@ -23,7 +23,7 @@ FP64, FP32, BF16 = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_BRAS = 0, 1, 2
 PC = {"none": PC_NONE, "jacobi": PC_JACOBI, "bras": PC_BRAS}
 INFO = {"n": 0, "E": 1, "nloc": 2, "nbr": 3, "prec": 4, "form": 5, "maxrhs": 6, "restarts": 7, "variant": 8,
-        "solve_path": 9, "patches": 10}
+        "solve_path": 9, "patches": 10, "patch_on": 11}
 EXPORT_MULT, EXPORT_ROWPTR, EXPORT_SLOT, EXPORT_DIAG = 0, 1, 2, 3
 OPT_GRAPH_ITERS, OPT_MAX_RESTART, OPT_VARIANT, OPT_SMALL_CG, OPT_PATCH = 0, 1, 2, 3, 4
 NOALLOC_SCRATCH_BYTES = 32 << 20   # BRAS_NOALLOC_SCRATCH_BYTES
@@ -74,6 +74,7 @@ _SIGS = {
     "bras_export": [vp, i32, vp, vp],
     "bras_set_option": [vp, i32, dbl],
     "bras_autotune": [vp, i32, vp],
+    "bras_bench_bf16_local_gemm": [i32, i32, i32, vp, C.POINTER(C.c_longlong), vp],
     "bras_csr_rowptr": [vp, vp, P_i64, vp],
     "bras_csr_assemble": [vp, i32, vp, vp, vp, vp],
     "bras_csr_apply": [i64, vp, vp, vp, vp, vp, vp],
@@ -219,6 +220,15 @@ def bras_apply(h, x_d, y_d, stream=None):
 
 def bras_apply_noalloc(h, x_d, y_d, stream=None):
     check(lib().bras_apply_noalloc(h, _dev(x_d), _dev(y_d), _nrhs(x_d), _stream(stream)))
+
+
+def bras_bench_bf16_local_gemm(n_loc, iters, blocks, out_d=None, stream=None):
+    """Microbenchmark launch (asynchronous); returns the issued matrix-core FLOPs."""
+    fl = C.c_longlong(0)
+    launch = int(blocks) > 0
+    check(lib().bras_bench_bf16_local_gemm(int(n_loc), int(iters), int(blocks), _dev(out_d) if launch else None,
+                                           C.byref(fl), _stream(stream) if launch else None))
+    return int(fl.value)
 
 
 def mass_apply(h, x_d, y_d, stream=None):

@@ -33,6 +33,7 @@ SOURCES = [
     ("pcg_small.hip", []),
     ("bf16.hip", []),
     ("noalloc.hip", []),
+    ("microbench.hip", []),
     ("patch_setup.cpp", []),
     ("patch.hip", []),
     ("patch_scaled.hip", []),

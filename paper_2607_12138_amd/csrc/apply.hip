@@ -152,6 +152,117 @@ __global__ void __launch_bounds__(kEB) __attribute__((amdgpu_waves_per_eu(NL <= 
   }
 }
 
+// The same element pass on the FP64 matrix cores: per group of 64 elements
+// Z = A W (W [n_loc][64] the gathered inputs in LDS, A the shared matrix,
+// zero padded in LDS to 16-row tiles and 4-deep k steps), one 16-element
+// column tile per wavefront on v_mfma_f64_16x16x4_f64, each column scaled by
+// its element's coefficient on the way out.  Persistent: a work-group loads
+// A once and strides over the element groups.
+//   A[i][k]: lane l holds i = l%16, k = l/16;  B[k][j]: lane l holds j = l%16,
+//   k = l/16;  D[i][j]: lane l, reg r holds j = l%16, i = l/16 + 4 r.
+typedef double h1f64x4 __attribute__((ext_vector_type(4)));
+template <int NL, bool DS>
+__global__ void __launch_bounds__(kEB) k_elem_h1_mfma(int64_t E, int R, const int32_t* __restrict__ l2g, InArgs in,
+                                                     const double* __restrict__ dscale,
+                                                     const double* __restrict__ A,
+                                                     const double* __restrict__ coefK, double* __restrict__ zb) {
+  constexpr int MT = (NL + 15) / 16;
+  constexpr int KS = (NL + 3) / 4;
+  constexpr int LDA = 4 * KS + 1;
+  __shared__ double sA[MT * 16 * LDA];
+  __shared__ double w[NL * kWS];
+  __shared__ double coef_s[256];
+  __shared__ int act_s[256];
+  __shared__ double red_s[kEB];
+  if (in.apart) {
+    alpha_prologue(in.apart, in.anb, R, in.sc, in.ic, coef_s, act_s, red_s);
+    for (int c = threadIdx.x; c < R; c += kEB) coef_s[c] *= in.sign;
+    __syncthreads();
+  } else {
+    for (int c = threadIdx.x; c < R; c += kEB) {
+      act_s[c] = in.active ? in.active[c] : 1;
+      coef_s[c] = in.cvec ? in.sign * in.cvec[c] : 0.0;
+    }
+    __syncthreads();
+  }
+  {
+    bool any = false;
+    for (int c = 0; c < R; ++c) any = any || act_s[c];
+    if (!any) return;   // uniform across the grid
+  }
+  const int tid = threadIdx.x;
+  for (int t = tid; t < MT * 16 * LDA; t += kEB) {
+    const int i = t / LDA, k = t - i * LDA;
+    sA[t] = (i < NL && k < NL) ? A[i * NL + k] : 0.0;
+  }
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int colq = lane & 15, kq = lane >> 4;
+  const int64_t ngroups = (E + kEPB - 1) / kEPB;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t K0 = grp * kEPB;
+    const int ne = (int)((E - K0) < kEPB ? (E - K0) : kEPB);
+    const int e = 16 * wv + colq;
+    const bool on = e < ne;
+    const double ck = on ? coefK[K0 + e] : 0.0;
+    for (int col = 0; col < R; ++col) {
+      if (!act_s[col]) continue;   // uniform
+      const double cf = coef_s[col];
+      {
+        // gather as in k_elem: map entries past the last element repeat its last entry
+        constexpr int GPT = (NL * kEPB + kEB - 1) / kEB;
+        const int qmax = ne * NL - 1;
+        int32_t gi[GPT];
+#pragma unroll
+        for (int u = 0; u < GPT; ++u) {
+          const int q = tid + u * kEB;
+          gi[u] = l2g[K0 * NL + (q < qmax ? q : qmax)];
+        }
+        const double* x2 = in.x2 ? in.x2 : in.x;
+        const double c2 = in.x2 ? cf : 0.0;
+        double v[GPT];
+#pragma unroll
+        for (int u = 0; u < GPT; ++u) {
+          const int64_t g = (int64_t)gi[u] * R + col;
+          double t = fma(c2, x2[g], in.x[g]);
+          if (DS) t *= dscale[gi[u]];
+          v[u] = t;
+        }
+#pragma unroll
+        for (int u = 0; u < GPT; ++u) {
+          const int q = tid + u * kEB;
+          if (q < NL * kEPB) {
+            const int ee = q / NL, j = q - ee * NL;
+            w[j * kWS + ee] = v[u];
+          }
+        }
+      }
+      __syncthreads();   // w (and, the first time, sA) complete
+      h1f64x4 acc[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = h1f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + kq;
+        const double b = k < NL ? w[k * kWS + e] : 0.0;   // columns past ne hold stale values, never stored
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(16 * mt + colq) * LDA + 4 * ks + kq], b, acc[mt], 0, 0, 0);
+      }
+      if (on) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * mt + kq + 4 * r;
+            if (i < NL) zb[((int64_t)i * E + K0 + e) * R + col] = acc[mt][r] * ck;
+          }
+      }
+      __syncthreads();   // before w is overwritten
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // reduce pass, optionally fused with a CG update
 // ---------------------------------------------------------------------------
@@ -208,13 +319,15 @@ __device__ __forceinline__ void reduce_epilogue(int64_t t, double acc, double co
 // loads, so long rows do not serialise), then each thread sums its rows.  The
 // row bounds and the vectors the epilogue reads are loaded together with the
 // chunk's slots, so a chunk costs two dependent memory round trips.
+// skip1: rows with a single broken copy are left to the element pass (which
+// then ran their epilogue itself).
 template <typename ZT, int OUT>
 __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __restrict__ chunk,
                                                 const int32_t* __restrict__ rowptr,
                                                 const int32_t* __restrict__ slot, const ZT* __restrict__ zb,
                                                 const double* __restrict__ scale, double* __restrict__ y,
                                                 const double* __restrict__ dotv, double* __restrict__ partial,
-                                                CgArgs cg) {
+                                                CgArgs cg, int skip1) {
   __shared__ double vals[kChunkCap];
   __shared__ double sh0[kBS], sh1[kBS], sh2[kBS];
   if (OUT != OUT_PLAIN && !cg.ic[I_ACTIVE]) return;   // uniform across the grid
@@ -288,6 +401,7 @@ __global__ void __launch_bounds__(kBS) k_reduce(int nchunk, const int32_t* __res
     for (int k = 0; k < kRowsPerThread; ++k) {
       const int32_t i = i0 + tid + k * kBS;
       if (i >= i1) continue;
+      if (skip1 && rb[k] - ra[k] == 1) continue;
       double acc = 0.0;
       if (!big)
         for (int32_t q = ra[k]; q < rb[k]; ++q) acc += vals[q];
@@ -363,7 +477,7 @@ __global__ void __launch_bounds__(kBS) k_reduce_mc(int R, int nchunk, const int3
                                                    const int32_t* __restrict__ slot, const ZT* __restrict__ zb,
                                                    const double* __restrict__ scale, double* __restrict__ y,
                                                    const double* __restrict__ dotv, double* __restrict__ partial,
-                                                   CgArgs cg) {
+                                                   CgArgs cg, int skip1) {
   __shared__ int32_t sl[kChunkCap];
   __shared__ int32_t rp[kChunkRows + 1];
   __shared__ double sh[kBS];
@@ -401,6 +515,7 @@ __global__ void __launch_bounds__(kBS) k_reduce_mc(int R, int nchunk, const int3
     if (act) {
       for (int r = g; r < nr; r += G) {
         const int a = rp[r], b = rp[r + 1];
+        if (skip1 && b - a == 1) continue;
         double acc = 0.0;
         int q = a;
         for (; q + 4 <= b; q += 4) {
@@ -590,10 +705,30 @@ int vector_blocks(Ctx* c, int R) {
 
 #define NL_CASES(X) X(3) X(4) X(6) X(8) X(10) X(15) X(20) X(21) X(24) X(28) X(35) X(36) X(45) X(56) X(70) X(84)
 
+// Scaled H1 element pass: variant 0 on the FP64 matrix cores (persistent,
+// a few work-groups per compute unit), variant 1 the per-row FMA pass.
+int scaled_variant(const Ctx* c) { return (c->variant == 0 || c->variant == 1) ? c->variant : 0; }
+
 template <int NL>
 static int elem_launch(Ctx* c, int R, const InArgs& in, const double* dscale, const double* A, const double* coefK,
                        double* zb, hipStream_t s) {
   const unsigned nb = (unsigned)((c->E + kEPB - 1) / kEPB);
+  if (scaled_variant(c) == 0) {
+    static int per_cu = 0;   // resident work-groups per compute unit (one grid of them strides over the groups)
+    if (per_cu == 0) {
+      int v = 0;
+      BRAS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_elem_h1_mfma<NL, true>, kEB, 0));
+      per_cu = v > 0 ? v : 1;
+    }
+    const unsigned cap = (unsigned)(c->ncu * per_cu);
+    const unsigned g = nb < cap ? nb : cap;
+    if (dscale)
+      k_elem_h1_mfma<NL, true><<<g, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, zb);
+    else
+      k_elem_h1_mfma<NL, false><<<g, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, zb);
+    BRAS_HIP(hipGetLastError());
+    return BRAS_OK;
+  }
   if (dscale)
     k_elem<NL, true><<<nb, kEB, 0, s>>>(c->E, R, c->l2g, in, dscale, A, coefK, zb);
   else
@@ -658,33 +793,42 @@ static int bras_elem(Ctx* c, const InArgs& in, int R, hipStream_t s, bool* zb_fl
 
 template <typename ZT, int OUT>
 static int reduce_launch(Ctx* c, const ZT* zb, const double* scale, double* y, int R, hipStream_t s,
-                         const double* dotv, double* partial, const CgArgs& cg) {
-  const unsigned nb = (unsigned)reduce_blocks(c, R);
+                         const double* dotv, double* partial, const CgArgs& cg, int skip1 = 0) {
+  const unsigned nb = (unsigned)reduce_chunk_blocks(c, R);
   if (R == 1)
     k_reduce<ZT, OUT><<<nb, kBS, 0, s>>>((int)c->nchunk, c->chunk, c->rowptr, c->slot, zb, scale, y, dotv, partial,
-                                         cg);
+                                         cg, skip1);
   else
     k_reduce_mc<ZT, OUT><<<nb, kBS, 0, s>>>(R, (int)c->nchunk, c->chunk, c->rowptr, c->slot, zb, scale, y, dotv,
-                                            partial, cg);
+                                            partial, cg, skip1);
   BRAS_HIP(hipGetLastError());
   return BRAS_OK;
 }
 
-int reduce_blocks(Ctx* c, int R) {
-  if (patch_active(c, R)) return patch_blocks(c);   // patch pass: one partial per work-group of its two kernels
-  // one column: one work-group per chunk up to a large cap (latency hiding);
-  // several columns: fewer, longer-lived work-groups and fewer partials
+// Work-groups of the transpose-map reduce: one column: one per chunk up to a
+// large cap (latency hiding); several columns: fewer, longer-lived work-groups
+// and fewer partials.
+int reduce_chunk_blocks(const Ctx* c, int R) {
   const int64_t cap = R == 1 ? kMaxReduceBlocks1 : kMaxReduceBlocks;
   return (int)(c->nchunk < cap ? c->nchunk : cap);
 }
 
+int reduce_blocks(Ctx* c, int R) {
+  if (patch_active(c, R)) return patch_blocks(c);   // patch pass: one partial per work-group of its two kernels
+  return reduce_chunk_blocks(c, R);
+}
+
 int reduce_float_plain(Ctx* c, const float* zb, double* y, int R, hipStream_t s, const double* dotv,
-                       double* dotpart) {
-  return reduce_launch<float, OUT_PLAIN>(c, zb, nullptr, y, R, s, dotv, dotpart, CgArgs());
+                       double* dotpart, int skip1) {
+  return reduce_launch<float, OUT_PLAIN>(c, zb, nullptr, y, R, s, dotv, dotpart, CgArgs(), skip1);
 }
 
 int reduce_float_cg(Ctx* c, const float* zb, int R, hipStream_t s, const CgArgs& cg) {
   return reduce_launch<float, OUT_BRAS_CG>(c, zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
+}
+
+int reduce_float_stat(Ctx* c, const float* zb, int R, hipStream_t s, const CgArgs& cg) {
+  return reduce_launch<float, OUT_STAT>(c, zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
 }
 
 int launch_mass(Ctx* c, const double* x, double* y, int R, hipStream_t s, const double* dotv, double* dotpart,
@@ -752,7 +896,7 @@ InArgs precond_input(const CgArgs& cg, int R) {
 // partials in its prologue).
 int precond_consumer_blocks(Ctx* c, int pc, int R) {
   if (pc == BRAS_PC_BRAS && patch_active(c, R)) return (int)c->pt.npatch;
-  if (pc == BRAS_PC_BRAS) return c->prec == BRAS_BF16 ? (int)c->E : (int)((c->E + kEPB - 1) / kEPB);
+  if (pc == BRAS_PC_BRAS) return c->prec == BRAS_BF16 ? c->bf16_grid_x2 : (int)((c->E + kEPB - 1) / kEPB);
   return vector_blocks(c, R);
 }
 
@@ -811,11 +955,7 @@ int st_precond_step(Ctx* c, int pc, const CgArgs& cg, int R, hipStream_t s) {
   InArgs in;
   in.x = cg.r;
   in.active = cg.ic + I_ACTIVE * R;
-  if (c->prec == BRAS_BF16) {
-    int st = bf16_elem_pass(c, in, R, s);
-    if (st) return st;
-    return reduce_launch<float, OUT_STAT>(c, (const float*)c->zb, nullptr, nullptr, R, s, nullptr, nullptr, cg);
-  }
+  if (c->prec == BRAS_BF16) return bf16_stat_step(c, cg, in, R, s);
   if (patch_active(c, R)) return patch_pass(c, 1, OUT_STAT, in, nullptr, nullptr, nullptr, cg, s);
   bool zf;
   int st = bras_elem(c, in, R, s, &zf, c->zb);

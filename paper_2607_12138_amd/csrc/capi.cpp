@@ -43,6 +43,7 @@ extern "C" int bras_info(bras_handle h, int what, int64_t* value_h) {
     case BRAS_INFO_VARIANT: *value_h = c->variant; break;
     case BRAS_INFO_SOLVE_PATH: *value_h = c->last_path; break;
     case BRAS_INFO_PATCHES: *value_h = c->pt.npatch; break;
+    case BRAS_INFO_PATCH_ON: *value_h = (c->pt.npatch > 0 && c->use_patch) ? 1 : 0; break;
     default: return fail(BRAS_EINVAL, "unknown info key %d", what);
   }
   return BRAS_OK;
@@ -124,18 +125,28 @@ extern "C" int bras_export(bras_handle h, int what, void* dst_d, void* stream) {
 
 int bras::variant_count(const Ctx* c) {
   const bool metric6 = c->form == BRAS_ELEM_METRIC_REF && c->nsym > 3 && c->nl <= kLaneMaxNL;
+  if (c->form == BRAS_ELEM_SCALED_REF) return 2;   // matrix-core / per-row FMA element pass
   return metric6 ? kMetricVariants : 1;
 }
 
 // Times mass apply + BRAS apply (one CG iteration's operator passes) for every
-// scheduling variant of this handle and keeps the fastest.
+// candidate of this handle and keeps the fastest: the element-pass
+// scheduling variants, and, when the handle has a patch plan and nrhs = 1,
+// the patch form of the passes (whose kernels do not depend on the variant).
 extern "C" int bras_autotune(bras_handle h, int nrhs, void* stream) {
   clear_error();
   BRAS_CHECK(h, "null handle");
   Ctx* c = (Ctx*)h;
   BRAS_CHECK(nrhs >= 1 && nrhs <= c->max_rhs, "nrhs outside 1..max_rhs");
   const int nv = variant_count(c);
-  if (nv == 1) {
+  const bool plan = c->pt.npatch > 0 && nrhs == 1;
+  struct Cand {
+    int patch, variant;
+  };
+  std::vector<Cand> cands;
+  if (plan) cands.push_back({1, c->variant >= 0 ? c->variant : 0});
+  for (int v = 0; v < nv; ++v) cands.push_back({0, v});
+  if (cands.size() == 1) {
     c->variant = 0;
     return BRAS_OK;
   }
@@ -153,9 +164,10 @@ extern "C" int bras_autotune(bras_handle h, int nrhs, void* stream) {
       hipEventCreate(&e1) != hipSuccess)
     st = fail(BRAS_EHIP, "autotune set-up failed");
   float best = 1e30f;
-  int best_v = 0;
-  for (int v = 0; v < nv && st == BRAS_OK; ++v) {
-    c->variant = v;
+  Cand pick = cands[0];
+  for (size_t k = 0; k < cands.size() && st == BRAS_OK; ++k) {
+    c->use_patch = cands[k].patch;
+    c->variant = cands[k].variant;
     auto pass = [&]() {
       int r = launch_mass(c, x, y, nrhs, s, nullptr, nullptr, nullptr);
       return r ? r : launch_bras(c, x, y, nrhs, s, nullptr, nullptr, nullptr);
@@ -170,10 +182,11 @@ extern "C" int bras_autotune(bras_handle h, int nrhs, void* stream) {
     (void)hipEventElapsedTime(&ms, e0, e1);
     if (ms < best) {
       best = ms;
-      best_v = v;
+      pick = cands[k];
     }
   }
-  c->variant = best_v;
+  c->use_patch = plan ? pick.patch : 1;
+  c->variant = pick.variant;
   cg_free(c);   // captured CG graphs hold the previous kernels
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);

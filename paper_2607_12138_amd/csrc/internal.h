@@ -52,6 +52,11 @@ struct Ctx {
   int small_cg = 1;          // solve eligible small problems in one work-group (pcg_small.hip)
   int use_patch = 1;         // one-column operator passes in patch form when the handle has a plan (patch.hip)
   int patch_xcd = 1;         // patch passes: each XCD takes a contiguous run of patches (BRAS_PATCH_XCD=0: round robin)
+  int bf16_direct = 1;       // BF16 plain applies write single-copy DOFs from the element pass (BRAS_BF16_DIRECT=0: off)
+  int bf16_grid = 0;         // BF16 element pass with that epilogue: persistent work-groups (0: other precisions)
+  int bf16_grid_plain = 0;   // BF16 element pass without it (one input vector)
+  int bf16_grid_x2 = 0;      // BF16 element pass with input r - alpha q (CG)
+  int32_t* l2g_dir = nullptr;   // [E][n_loc] l2g with bit 31 set on single-copy DOFs (BF16 with the epilogue)
   int ip_mode = 0;           // 1 while a patch-form solve runs: operator passes address vectors in the
                              // internal DOF numbering of the patch plan (PatchDev::ip2g)
   int last_path = 0;         // path of the last pcg_solve: 0 multi-pass, 1 one work-group
@@ -128,6 +133,10 @@ int launch_bras_bf16(Ctx* c, const double* x, double* y, int nrhs, hipStream_t s
 // bytes of broken-vector workspace one BRAS apply of nrhs columns uses
 size_t broken_bytes(const Ctx* c, int nrhs);
 int reduce_blocks(Ctx* c, int nrhs);   // blocks (= partials per column) of a reduce pass
+int reduce_chunk_blocks(const Ctx* c, int nrhs);   // work-groups of the transpose-map reduce
+// plain BF16 applies of nrhs columns write single-copy DOFs from the element pass (bf16.hip)
+inline bool bf16_bypass(const Ctx* c, int nrhs) { return c->l2g_dir && nrhs <= 32; }
+int bf16_setup(Ctx* c, hipStream_t s);   // persistent grids and flagged map of the BF16 element pass
 int vector_blocks(Ctx* c, int nrhs);   // blocks of a grid-stride vector pass (grid * 256 % nrhs == 0)
 void cg_free(Ctx* c);
 
@@ -141,14 +150,15 @@ int st_mass_step(Ctx* c, const CgArgs& cg, int nrhs, hipStream_t s);
 int st_precond_step(Ctx* c, int pc, const CgArgs& cg, int nrhs, hipStream_t s);
 struct InArgs;
 InArgs precond_input(const CgArgs& cg, int nrhs);
-int bf16_elem_pass(Ctx* c, const InArgs& in, int nrhs, hipStream_t s);   // bf16.hip
+int bf16_stat_step(Ctx* c, const CgArgs& cg, const InArgs& in, int nrhs, hipStream_t s);   // bf16.hip
 int precond_consumer_blocks(Ctx* c, int pc, int nrhs);
 int metric_variant(const Ctx* c);   // apply.hip
 int variant_count(const Ctx* c);    // scheduling variants of this handle's element passes
 // reduce passes over a float32 broken vector (apply.hip)
 int reduce_float_plain(Ctx* c, const float* zb, double* y, int nrhs, hipStream_t s, const double* dotv,
-                       double* dotpart);
+                       double* dotpart, int skip1);
 int reduce_float_cg(Ctx* c, const float* zb, int nrhs, hipStream_t s, const CgArgs& cg);
+int reduce_float_stat(Ctx* c, const float* zb, int nrhs, hipStream_t s, const CgArgs& cg);
 
 // Single work-group PCG (pcg_small.hip): scaled H1 form, float64, one
 // column, n <= kSmallMaxN, 16 n + 10 n_br <= kSmallLdsBytes (its LDS: two

@@ -580,7 +580,7 @@ static int element_setup_ordered(Ctx* c, const double* elem_d, hipStream_t s) {
 static void free_ctx(Ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->l2g, c->mult, c->invd, c->rowptr, c->chunk, c->slot, c->ref, c->refinv, c->coef, c->icoef, c->ainv,
-                  c->symtab, c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag,
+                  c->symtab, c->mpack, c->diag, c->invdiag, c->zb, c->partial, c->flag, c->l2g_dir,
                   c->pt.perm, c->pt.pe, c->pt.pd, c->pt.pnl, c->pt.pdof, c->pt.code, c->pt.sbase, c->pt.srp,
                   c->pt.spos, c->pt.sdof, c->pt.part, c->pt.ip2g, c->pt.pidx, c->pt.invd_ip, c->pt.invdiag_ip};
   for (void* p : ptrs)
@@ -872,6 +872,7 @@ extern "C" int bras_setup(bras_handle* h, int64_t n, int64_t E, int n_loc, const
     }
   }
   TRY(element_setup(c, elem_d, s));
+  if (apply_prec == BRAS_BF16) TRY(bf16_setup(c, s));
   // workspace
   size_t zbytes = sizeof(double) * (size_t)c->nbr * max_rhs;
   TRY(dalloc((char**)&c->zb, zbytes));

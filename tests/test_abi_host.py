@@ -135,3 +135,19 @@ def test_setup_and_geometry_reject_bad_arguments():
     for fn in ("bras_apply", "mass_apply", "jacobi_apply"):
         assert getattr(lib, fn)(None, P, P, 1, None) == L.BRAS_EINVAL, fn
     assert lib.pcg_solve(None, L.PC_BRAS, P, P, 1, 1e-8, 10, None, None, None) == L.BRAS_EINVAL
+
+
+def test_local_gemm_microbenchmark_counts():
+    """The BF16 local-GEMM microbenchmark's FLOP count (blocks = 0 launches
+    nothing): issued 32x32x16 MFMAs of one element and 32 columns, counted by
+    hand from the tile shapes (rows in 32-row tiles, k in 16-deep steps; the
+    first product stops at the tile's last row, the second starts at k-step 2t)."""
+    from paper_2607_12138_amd import _lib as L
+    per_mfma = 2 * 32 * 32 * 16
+    for nl, count in ((20, 2 + 2), (36, (2 + 3) + (3 + 1)), (70, (2 + 5) + (4 + 3) + (5 + 1)),
+                      (84, (2 + 6) + (4 + 4) + (6 + 2))):
+        assert L.bras_bench_bf16_local_gemm(nl, 1, 0) == count * per_mfma, nl
+    with pytest.raises(L.BrasError):
+        L.bras_bench_bf16_local_gemm(15, 1, 0)
+    with pytest.raises(L.BrasError):
+        L.bras_bench_bf16_local_gemm(70, -1, 0)

@@ -329,23 +329,38 @@ def test_bf16_flexible_pcg(case):
         assert int(its[r]) <= ito + 3                   # BF16 preconditioner costs at most a few iterations
 
 
-def test_autotune_variants():
-    """Every scheduling variant of the metric-form mass pass gives the
-    oracle's products; the autotuner keeps one of them; invalid variants are
-    rejected."""
+@pytest.mark.parametrize("case,nv", [(CASES[5], 3), (CASES[2], 2), (CASES[12], 2), (CASES[6], 3)],
+                         ids=lambda v: ids(v) if isinstance(v, tuple) else "nv%d" % v)
+def test_autotune_variants(case, nv):
+    """Every candidate the autotuner times gives the oracle's operators and
+    solves: the element-pass variants (metric-form mass pass orders; scaled H1
+    on the matrix cores or per-row FMA) with the patch form off, and the patch
+    form where the handle has one; the autotuner keeps one of them; invalid
+    variants are rejected."""
     from paper_2607_12138_amd import _lib as L
-    orc, gpu = build(CASES[5])
+    orc, gpu = build(case)
     x = workloads.vector(orc.n, 9)
-    say("autotune variants %s" % (CASES[5],))
-    for v in range(3):
-        L.bras_set_option(gpu.h, L.OPT_VARIANT, v)
-        assert rel_inf(gpu.mass(to_t(x)).cpu().numpy(), orc.M @ x) <= 1e-13
-        b = workloads.rhs(orc.n, 1, 41)
-        xs, st, its, rel = gpu.solve(to_t(b), "bras", rtol=1e-10)
-        assert st == L.BRAS_OK
+    b = workloads.rhs(orc.n, 1, 41)
+    tb = 1e-13 if case[6] == "f64" else 2e-4
+    rtol = 1e-10 if case[6] == "f64" else 1e-8
+    say("autotune variants %s" % (case,))
+    patch_forms = [1, 0] if gpu.info("patches") > 0 else [0]
+    for pf in patch_forms:
+        L.bras_set_option(gpu.h, L.OPT_PATCH, pf)
+        for v in range(nv):
+            L.bras_set_option(gpu.h, L.OPT_VARIANT, v)
+            assert rel_inf(gpu.mass(to_t(x)).cpu().numpy(), orc.M @ x) <= 1e-13
+            assert rel_inf(gpu.bras(to_t(x)).cpu().numpy(), orc.B @ x) <= tb
+            xs, st, its, rel = gpu.solve(to_t(b), "bras", rtol=rtol)
+            assert st == L.BRAS_OK
+            assert np.linalg.norm(b - orc.M @ xs.cpu().numpy()) <= rtol * np.linalg.norm(b)
+    L.bras_set_option(gpu.h, L.OPT_PATCH, 1)
     L.bras_autotune(gpu.h, 1)
-    assert 0 <= gpu.info("variant") < 3
+    assert 0 <= gpu.info("variant") < nv
+    assert gpu.info("patch_on") in ((0, 1) if len(patch_forms) == 2 else (0,))
+    say("  autotuner: variant %d, patch form %d" % (gpu.info("variant"), gpu.info("patch_on")))
     with pytest.raises(L.BrasError):
-        L.bras_set_option(gpu.h, L.OPT_VARIANT, 3)
+        L.bras_set_option(gpu.h, L.OPT_VARIANT, nv)
     L.bras_set_option(gpu.h, L.OPT_VARIANT, -1)
+    L.bras_set_option(gpu.h, L.OPT_PATCH, 1)
     assert gpu.info("variant") == -1
