@@ -155,9 +155,57 @@ __device__ __forceinline__ void patch_gather(const int32_t* __restrict__ pdof, i
 // Phase 3 of a patch pass: the final values of the patch's local DOFs with
 // the epilogue, and the partial sums of its shared DOFs; the loads of U DOFs
 // per thread are issued before any of their stores.
-template <int OUT, bool DS>
+// Sum of patch DOF j's copies as collected in LDS by the rank-ordered adds.
+struct LdsSums {
+  const double* w;
+  __device__ double operator()(int j) const { return w[j]; }
+};
+
+// Sum of patch DOF j's copies from their values stored in rank order at
+// zs[start[j] .. start[j+1]) (the same additions, in the same order, as the
+// rank-ordered adds).
+struct SegmentSums {
+  const int* start;
+  const double* zs;
+  __device__ double operator()(int j) const {
+    double a = 0.0;
+    for (int q = start[j]; q < start[j + 1]; ++q) a += zs[q];
+    return a;
+  }
+};
+
+// Exclusive scan, in place, of the copy counts I[0..nd) of a patch's DOFs
+// into segment starts, with I[nd] = the total (work-group wide; ps: 4 ints of
+// LDS).  Ends with a barrier.
+__device__ __forceinline__ void patch_count_scan(int* I, int nd, int* ps) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int per = (nd + kPatchBlock - 1) / kPatchBlock;
+  const int b0 = tid * per < nd ? tid * per : nd;
+  const int b1 = b0 + per < nd ? b0 + per : nd;
+  int s = 0;
+  for (int j = b0; j < b1; ++j) s += I[j];
+  int incl = s;   // inclusive prefix within the wavefront
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) ps[wv] = incl;
+  __syncthreads();
+  int off = incl - s;
+  for (int w = 0; w < wv; ++w) off += ps[w];
+  for (int j = b0; j < b1; ++j) {
+    const int c = I[j];
+    I[j] = off;
+    off += c;
+  }
+  if (tid == kPatchBlock - 1) I[nd] = off;   // b1 = nd for the last thread
+  __syncthreads();
+}
+
+template <int OUT, bool DS, typename VAL>
 __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
-                                             const double* wsh, const double* __restrict__ dscale, double ep1,
+                                             VAL val, const double* __restrict__ dscale, double ep1,
                                              double ep2, const CgArgs& cg, double* __restrict__ y,
                                              const double* __restrict__ dotv, double* __restrict__ spart,
                                              int32_t sb, double& a0, double& a1, double& a2) {
@@ -170,7 +218,7 @@ __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, i
       const int j = j0 + u * kPatchBlock;
       const bool in_range = j < nd;
       g[u] = pdof[d0 + (in_range ? j : 0)];
-      acc[u] = in_range ? wsh[j] : 0.0;
+      acc[u] = in_range ? val(j) : 0.0;
     }
     // vectors the epilogue reads, for the U DOFs at once
     double v0[U], v1[U], v2[U], v3[U], v4[U], ds[U];
@@ -326,7 +374,8 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, wsh, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0, a1, a2);
+  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, LdsSums{wsh}, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
+                        a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
 }

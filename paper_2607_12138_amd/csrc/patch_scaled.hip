@@ -9,8 +9,12 @@
 // outputs times D^-1).  A sits in LDS, zero padded to 16-row tiles and
 // 4-deep k steps; each wavefront takes 16-element column tiles and runs
 // v_mfma_f64_16x16x4_f64 with B read straight from the patch DOF values
-// through the copy codes, then scales its columns and adds the results into
-// the LDS sums rank by rank, as the per-lane passes do.
+// through the copy codes, then scales its columns.  The sums: DOF j's copies
+// are counted (LDS integer adds), the counts scanned into segment starts, and
+// the copy of rank r stored at start[j] + r; each DOF then adds its segment
+// in order, the same additions as the rank-by-rank adds of the per-lane
+// passes, with three barriers instead of one per rank (vertex DOFs of P4
+// patches have up to 24 copies).
 //
 // MFMA operand layout (16x16x4, one double per lane):
 //   A[i][k]: lane l holds i = l%16, k = l/16
@@ -35,6 +39,8 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_mfma(PatchArgs pa, InArgs
   constexpr int LDA = 4 * KS + 1;      // LDS row stride of A (odd: spreads banks)
   extern __shared__ double wsh[];      // inputs, then sums, then dot partials
   __shared__ double sA[MT * 16 * LDA];
+  __shared__ double zs[64 * TPW * NL];   // the patch's element outputs, segment by segment
+  __shared__ int scan_s[kPatchBlock / 64];
   __shared__ double coef_s[1];
   __shared__ int act_s[1];
   const int tid = threadIdx.x;
@@ -102,27 +108,39 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_mfma(PatchArgs pa, InArgs
       oc[t][mt][1] = c4[2] | (c4[3] << 16);
     }
   }
-  __syncthreads();   // every input read: the array now collects the sums
-  for (int j = tid; j < nd; j += kPatchBlock) wsh[j] = 0.0;
+  __syncthreads();   // every input read: wsh now holds the copy counts, then the segment starts
+  int* I = reinterpret_cast<int*>(wsh);   // nd + 1 ints fit in the nd >= 1 doubles of wsh
+  for (int j = tid; j <= nd; j += kPatchBlock) I[j] = 0;
   __syncthreads();
   const int lb = pa.lbits;
-  for (int r = 0; r <= pa.maxrank; ++r) {
 #pragma unroll
-    for (int t = 0; t < TPW; ++t)
+  for (int t = 0; t < TPW; ++t)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t cl = (oc[t][mt][q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
-          if (cl != 0xFFFFu && (int)(cl >> lb) == r) wsh[cl & lmask] += acc[t][mt][q];
-        }
-    __syncthreads();
-  }
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t cl = (oc[t][mt][q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+        if (cl != 0xFFFFu) atomicAdd(&I[cl & lmask], 1);
+      }
+  __syncthreads();
+  patch_count_scan(I, nd, scan_s);
+  // each copy's value at start[j] + rank: every DOF's copies in rank (= element) order
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t cl = (oc[t][mt][q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+        if (cl != 0xFFFFu) zs[I[cl & lmask] + (int)(cl >> lb)] = acc[t][mt][q];
+      }
+  __syncthreads();
   // 3. DOFs of the patch
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, wsh, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0, a1, a2);
+  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, SegmentSums{I, zs}, dscale, ep1, ep2, cg, y, dotv, spart,
+                        pa.sbase[p], a0, a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
 }
