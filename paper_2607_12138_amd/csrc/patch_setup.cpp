@@ -3,11 +3,15 @@
 // Elements are grouped into patches of at most P elements (one work-group
 // each) by greedy graph growing over the element graph of the local-to-global
 // map (two elements are neighbours when they share a DOF): a patch starts at
-// the lowest-numbered unassigned element and repeatedly takes the unassigned
-// neighbour with the most DOF copies already in the patch, which keeps
-// patches compact, so that most of their DOFs have every broken copy inside.
-// The library then numbers elements patch by patch (all element-indexed data
-// follow that internal order).
+// the most enclosed unassigned element (the most DOF incidences shared with
+// elements already assigned; the lowest-numbered unassigned one when none is
+// enclosed) and repeatedly takes the unassigned neighbour with the most DOF
+// copies already in the patch, which keeps patches compact, so that most of
+// their DOFs have every broken copy inside.  Growth stops at P - P/8
+// elements; afterwards a patch of fewer than a quarter of that joins the
+// neighbouring patch it shares the most copies with, where elements and DOFs
+// fit.  The library then numbers elements patch by patch (all element-indexed
+// data follow that internal order).
 //
 // For each patch the plan lists its DOFs (those whose copies all lie in the
 // patch first, then the shared ones, each group in increasing DOF order) and,
