@@ -41,6 +41,7 @@ struct PatchArgs {
   int lbits, maxrank;
   int64_t npatch;
   int xcd_per;   // > 0: work-group b takes patch (b % 8) * xcd_per + b / 8 (each XCD a contiguous run)
+  int ip;        // vectors in the internal numbering: patch p's local DOFs are pd[p] - sbase[p] + j, j < pnl[p]
 };
 
 // One call of the patch form of an operator (op 0 mass, 1 BRAS).
@@ -121,19 +122,27 @@ __device__ __forceinline__ void patch_dots(double d0, double d1, double d2, int6
   }
 }
 
+// DOF number of patch DOF j: from the list, or (lbase >= 0: internal
+// numbering) lbase + j for the patch's local DOFs, j < nloc.
+__device__ __forceinline__ int32_t patch_dof(const int32_t* __restrict__ pdof, int32_t d0, int j, int nloc,
+                                             int32_t lbase) {
+  return (lbase >= 0 && j < nloc) ? lbase + j : pdof[d0 + j];
+}
+
 // Phase 1 of a patch pass: wsh[j] = input value of patch DOF j, the loads of
 // U DOFs per thread issued together (out-of-range slots read DOF 0 of the
 // patch and store nothing).
 template <bool DS>
-__device__ __forceinline__ void patch_gather(const int32_t* __restrict__ pdof, int32_t d0, int nd, const InArgs& in,
-                                             double c2, const double* __restrict__ dscale, double* wsh) {
+__device__ __forceinline__ void patch_gather(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
+                                             int32_t lbase, const InArgs& in, double c2,
+                                             const double* __restrict__ dscale, double* wsh) {
   constexpr int U = 4;
   for (int j0 = threadIdx.x; j0 < nd; j0 += U * kPatchBlock) {
     int32_t g[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = j0 + u * kPatchBlock;
-      g[u] = pdof[d0 + (j < nd ? j : 0)];
+      g[u] = patch_dof(pdof, d0, j < nd ? j : 0, nloc, lbase);
     }
     double v[U], v2[U], ds[U];
 #pragma unroll
@@ -205,7 +214,7 @@ __device__ __forceinline__ void patch_count_scan(int* I, int nd, int* ps) {
 
 template <int OUT, bool DS, typename VAL>
 __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
-                                             VAL val, const double* __restrict__ dscale, double ep1,
+                                             int32_t lbase, VAL val, const double* __restrict__ dscale, double ep1,
                                              double ep2, const CgArgs& cg, double* __restrict__ y,
                                              const double* __restrict__ dotv, double* __restrict__ spart,
                                              int32_t sb, double& a0, double& a1, double& a2) {
@@ -217,7 +226,7 @@ __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, i
     for (int u = 0; u < U; ++u) {
       const int j = j0 + u * kPatchBlock;
       const bool in_range = j < nd;
-      g[u] = pdof[d0 + (in_range ? j : 0)];
+      g[u] = patch_dof(pdof, d0, in_range ? j : 0, nloc, lbase);
       acc[u] = in_range ? val(j) : 0.0;
     }
     // vectors the epilogue reads, for the U DOFs at once
@@ -326,7 +335,8 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const int32_t d0 = pa.pd[p], nd = pa.pd[p + 1] - d0, nloc = pa.pnl[p];
   __syncthreads();   // the prologue's use of wsh is over
   // 1. patch DOF values
-  patch_gather<DS>(pa.pdof, d0, nd, in, c2, dscale, wsh);
+  const int32_t lbase = pa.ip ? d0 - pa.sbase[p] : -1;
+  patch_gather<DS>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh);
   __syncthreads();
   // 2. one element per lane (idle lanes repeat element 0 and add nothing)
   const bool on = tid < ne;
@@ -374,7 +384,7 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, LdsSums{wsh}, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
+  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, lbase, LdsSums{wsh}, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
                         a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
@@ -455,7 +465,7 @@ int patch_launch(Ctx* c, const PatchCall& pc, const T* ap, const double* symtab,
   const bool ip = c->ip_mode != 0;   // vectors in the internal DOF numbering
   const int xcd_per = c->patch_xcd ? (int)((pt.npatch + 7) / 8) : 0;
   PatchArgs pa{pt.pe, pt.pd, pt.pnl, ip ? pt.pidx : pt.pdof, pt.code, pt.sbase, c->E, pt.lbits, pt.maxrank,
-               pt.npatch, xcd_per};
+               pt.npatch, xcd_per, ip ? 1 : 0};
   if (ip && dscale) dscale = pt.invd_ip;
   const int words = pt.maxdofs > 3 * kPatchBlock ? pt.maxdofs : 3 * kPatchBlock;
   const unsigned grid = xcd_per > 0 ? (unsigned)(8 * xcd_per) : (unsigned)pt.npatch;

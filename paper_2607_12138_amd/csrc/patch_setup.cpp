@@ -366,6 +366,8 @@ int build_patch_plan(int64_t n, int64_t E, int nl, const int32_t* l2g, const int
     for (int32_t j = d0; j < d1; ++j) {
       const int32_t g = plan->pdof[j];
       if (j - d0 < nloc) {
+        // the patch passes rely on this: local DOF j of patch p is pd[p] - sbase[p] + j
+        if (lb != (int64_t)d0 - plan->sbase[p] + (j - d0)) return 1;
         plan->ip2g[lb] = g;
         plan->pidx[j] = (int32_t)lb++;
       } else {
