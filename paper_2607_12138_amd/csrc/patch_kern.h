@@ -42,6 +42,7 @@ struct PatchArgs {
   int64_t npatch;
   int xcd_per;   // > 0: work-group b takes patch (b % 8) * xcd_per + b / 8 (each XCD a contiguous run)
   int ip;        // vectors in the internal numbering: patch p's local DOFs are pd[p] - sbase[p] + j, j < pnl[p]
+  int wstride;   // doubles of the gathered inputs in dynamic LDS (the sums follow them where both are kept)
 };
 
 // One call of the patch form of an operator (op 0 mass, 1 BRAS).
@@ -212,9 +213,15 @@ __device__ __forceinline__ void patch_count_scan(int* I, int nd, int* ps) {
   __syncthreads();
 }
 
-template <int OUT, bool DS, typename VAL>
+// REUSE (CG epilogues without D^-1): win[j] holds the pass's gathered input
+// of patch DOF j, which is the epilogue's new p (mass: z + beta p) or new r
+// (BRAS: r - alpha q), computed in the same arithmetic; the epilogue takes it
+// instead of reading the two vectors again.  Only local DOFs read epilogue
+// vectors (boundary DOFs write their partial sums).
+template <int OUT, bool DS, bool REUSE, typename VAL>
 __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
-                                             int32_t lbase, VAL val, const double* __restrict__ dscale, double ep1,
+                                             int32_t lbase, VAL val, const double* win,
+                                             const double* __restrict__ dscale, double ep1,
                                              double ep2, const CgArgs& cg, double* __restrict__ y,
                                              const double* __restrict__ dotv, double* __restrict__ spart,
                                              int32_t sb, double& a0, double& a1, double& a2) {
@@ -229,20 +236,32 @@ __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, i
       g[u] = patch_dof(pdof, d0, in_range ? j : 0, nloc, lbase);
       acc[u] = in_range ? val(j) : 0.0;
     }
-    // vectors the epilogue reads, for the U DOFs at once
+    // vectors the epilogue reads, for the U DOFs at once (local DOFs only)
     double v0[U], v1[U], v2[U], v3[U], v4[U], ds[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * kPatchBlock;
+      const bool loc = j < nd && j < nloc;
       const int32_t gg = g[u];
-      ds[u] = DS ? dscale[gg] : 1.0;
+      ds[u] = (DS && loc) ? dscale[gg] : 1.0;
+      v0[u] = v1[u] = v2[u] = v3[u] = v4[u] = 0.0;
+      if (!loc) continue;
       if (OUT == OUT_PLAIN) {
         v0[u] = dotv ? dotv[gg] : 0.0;
       } else if (OUT == OUT_MASS_CG) {
-        v0[u] = cg.p[gg];
-        v1[u] = cg.z[gg];
+        if (REUSE) {
+          v0[u] = win[j];
+        } else {
+          v0[u] = cg.p[gg];
+          v1[u] = cg.z[gg];
+        }
       } else if (OUT == OUT_BRAS_CG) {
-        v0[u] = cg.q[gg];
-        v1[u] = cg.r[gg];
+        if (REUSE) {
+          v0[u] = win[j];
+        } else {
+          v0[u] = cg.q[gg];
+          v1[u] = cg.r[gg];
+        }
         v2[u] = cg.x[gg];
         v3[u] = cg.p[gg];
         v4[u] = cg.flexible ? cg.z[gg] : 0.0;
@@ -268,12 +287,12 @@ __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, i
         y[gg] = t;
         if (dotv) a0 = fma(t, v0[u], a0);
       } else if (OUT == OUT_MASS_CG) {
-        const double pn = fma(ep1, v0[u], v1[u]);
+        const double pn = REUSE ? v0[u] : fma(ep1, v0[u], v1[u]);
         cg.p[gg] = pn;
         cg.q[gg] = t;
         a0 = fma(pn, t, a0);
       } else if (OUT == OUT_BRAS_CG) {
-        const double rn = fma(-ep1, v0[u], v1[u]);
+        const double rn = REUSE ? v0[u] : fma(-ep1, v0[u], v1[u]);
         cg.x[gg] = fma(ep1, v3[u], v2[u]);
         if (cg.flexible) a2 = fma(rn, v4[u], a2);
         cg.z[gg] = t;
@@ -360,7 +379,10 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
     z[l] = (T)0;
   }
   __syncthreads();   // every input read: the array now collects the sums
-  for (int j = tid; j < nd; j += kPatchBlock) wsh[j] = 0.0;
+  // the sums: after the inputs where the epilogue reuses them, else in their place
+  constexpr bool REUSE = !DS && (OUT == OUT_MASS_CG || OUT == OUT_BRAS_CG);
+  double* wsum = REUSE ? wsh + pa.wstride : wsh;
+  for (int j = tid; j < nd; j += kPatchBlock) wsum[j] = 0.0;
   double g[NSYM > 0 ? NSYM : 1];
   if (FORM == FORM_METRIC) {
 #pragma unroll
@@ -375,7 +397,7 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
 #pragma unroll
       for (int l = 0; l < NL; ++l) {
         const uint32_t cl = code(l);
-        if ((int)(cl >> lb) == r) wsh[cl & lmask] += (double)z[l];
+        if ((int)(cl >> lb) == r) wsum[cl & lmask] += (double)z[l];
       }
     }
     __syncthreads();
@@ -384,7 +406,7 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, lbase, LdsSums{wsh}, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
+  patch_finish<OUT, DS, REUSE>(pa.pdof, d0, nd, nloc, lbase, LdsSums{wsum}, wsh, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
                         a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
@@ -464,10 +486,12 @@ int patch_launch(Ctx* c, const PatchCall& pc, const T* ap, const double* symtab,
   const PatchDev& pt = c->pt;
   const bool ip = c->ip_mode != 0;   // vectors in the internal DOF numbering
   const int xcd_per = c->patch_xcd ? (int)((pt.npatch + 7) / 8) : 0;
+  constexpr bool REUSE = !DS && (OUT == OUT_MASS_CG || OUT == OUT_BRAS_CG);
   PatchArgs pa{pt.pe, pt.pd, pt.pnl, ip ? pt.pidx : pt.pdof, pt.code, pt.sbase, c->E, pt.lbits, pt.maxrank,
-               pt.npatch, xcd_per, ip ? 1 : 0};
+               pt.npatch, xcd_per, ip ? 1 : 0, pt.maxdofs};
   if (ip && dscale) dscale = pt.invd_ip;
-  const int words = pt.maxdofs > 3 * kPatchBlock ? pt.maxdofs : 3 * kPatchBlock;
+  const int need = (REUSE ? 2 : 1) * pt.maxdofs;
+  const int words = need > 3 * kPatchBlock ? need : 3 * kPatchBlock;
   const unsigned grid = xcd_per > 0 ? (unsigned)(8 * xcd_per) : (unsigned)pt.npatch;
   k_patch<NL, FORM, NSYM, T, OUT, DS, VAR><<<grid, kPatchBlock, sizeof(double) * words, s>>>(
       pa, pc.in, ap, symtab, coefK, nsym, dscale, pc.y, pc.dotv, pc.dotpart, pc.cg, pc.spart);

@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_mfma(PatchArgs pa, InArgs
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  patch_finish<OUT, DS>(pa.pdof, d0, nd, nloc, lbase, SegmentSums{I, zs}, dscale, ep1, ep2, cg, y, dotv, spart,
+  patch_finish<OUT, DS, false>(pa.pdof, d0, nd, nloc, lbase, SegmentSums{I, zs}, nullptr, dscale, ep1, ep2, cg, y, dotv, spart,
                         pa.sbase[p], a0, a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
@@ -153,7 +153,7 @@ static int mfma_launch(Ctx* c, const PatchCall& pc, const double* A, const doubl
   const bool ip = c->ip_mode != 0;
   const int xcd_per = c->patch_xcd ? (int)((pt.npatch + 7) / 8) : 0;
   PatchArgs pa{pt.pe, pt.pd, pt.pnl, ip ? pt.pidx : pt.pdof, pt.code, pt.sbase, c->E, pt.lbits, pt.maxrank,
-               pt.npatch, xcd_per, ip ? 1 : 0};
+               pt.npatch, xcd_per, ip ? 1 : 0, pt.maxdofs};
   if (ip && dscale) dscale = pt.invd_ip;
   const int words = pt.maxdofs > 3 * kPatchBlock ? pt.maxdofs : 3 * kPatchBlock;
   const unsigned grid = xcd_per > 0 ? (unsigned)(8 * xcd_per) : (unsigned)pt.npatch;
