@@ -57,33 +57,60 @@ struct PatchCall {
   double* spart = nullptr;   // partial sums of shared DOFs
 };
 
+// The CG / stationary epilogue of entry g in two halves: the vectors it reads
+// (loaded early, beside other loads), then the update from them.
 template <int OUT>
-__device__ __forceinline__ void patch_epilogue(int32_t g, double acc, double coef, double coef2, const CgArgs& cg,
-                                               double* y, const double* dotv, double& d0, double& d1, double& d2) {
+__device__ __forceinline__ void patch_epilogue_load(bool ok, int32_t g, const CgArgs& cg, const double* dotv,
+                                                    double* v) {
+  v[0] = v[1] = v[2] = v[3] = v[4] = 0.0;
+  if (!ok) return;
+  if (OUT == OUT_PLAIN) {
+    v[0] = dotv ? dotv[g] : 0.0;
+  } else if (OUT == OUT_MASS_CG) {
+    v[0] = cg.p[g];
+    v[1] = cg.z[g];
+  } else if (OUT == OUT_BRAS_CG) {
+    v[0] = cg.q[g];
+    v[1] = cg.r[g];
+    v[2] = cg.x[g];
+    v[3] = cg.p[g];
+    v[4] = cg.flexible ? cg.z[g] : 0.0;
+  } else if (OUT == OUT_RES) {
+    v[0] = cg.b[g];
+  } else {
+    v[0] = cg.p[g];
+    v[1] = cg.x[g];
+  }
+}
+
+template <int OUT>
+__device__ __forceinline__ void patch_epilogue_pre(int32_t g, double acc, double coef, double coef2, const CgArgs& cg,
+                                                   double* y, bool has_dotv, const double* v, double& d0, double& d1,
+                                                   double& d2) {
   if (OUT == OUT_PLAIN) {
     y[g] = acc;
-    if (dotv) d0 = fma(acc, dotv[g], d0);
+    if (has_dotv) d0 = fma(acc, v[0], d0);
   } else if (OUT == OUT_MASS_CG) {
-    const double pn = fma(coef, cg.p[g], cg.z[g]);
+    const double pn = fma(coef, v[0], v[1]);
     cg.p[g] = pn;
     cg.q[g] = acc;
     d0 = fma(pn, acc, d0);
   } else if (OUT == OUT_BRAS_CG) {
-    const double rn = fma(-coef, cg.q[g], cg.r[g]);
-    cg.x[g] = fma(coef, cg.p[g], cg.x[g]);
-    if (cg.flexible) d2 = fma(rn, cg.z[g], d2);
+    const double rn = fma(-coef, v[0], v[1]);
+    cg.x[g] = fma(coef, v[3], v[2]);
+    if (cg.flexible) d2 = fma(rn, v[4], d2);
     cg.z[g] = acc;
     cg.r[g] = rn;
     d0 = fma(rn, rn, d0);
     d1 = fma(rn, acc, d1);
   } else if (OUT == OUT_RES) {
-    const double rv = cg.b[g] - acc;
+    const double rv = v[0] - acc;
     cg.r[g] = rv;
     d0 = fma(rv, rv, d0);
   } else {
-    const double dn = fma(coef, cg.p[g], coef2 * acc);
+    const double dn = fma(coef, v[0], coef2 * acc);
     cg.p[g] = dn;
-    cg.x[g] += dn;
+    cg.x[g] = v[1] + dn;
   }
 }
 
@@ -435,14 +462,22 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_shared(int64_t ns, const 
   for (int64_t s0 = (int64_t)blockIdx.x * kPatchSharedPerBlock + threadIdx.x; s0 < ns;
        s0 += (int64_t)gridDim.x * kPatchSharedPerBlock) {
     // U shared DOFs per thread, their loads issued together
-    int32_t k0[U], k1[U];
-    double acc[U];
+    int32_t k0[U], k1[U], gd[U];
+    double acc[U], ev[U][5], ds[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t s = s0 + (int64_t)u * kPatchBlock;
       const bool ok = s < ns;
       k0[u] = ok ? srp[s] : 0;
       k1[u] = ok ? srp[s + 1] : 0;
+      gd[u] = ok ? (sdof ? sdof[s] : (int32_t)(sbase + s)) : 0;
+    }
+    // the vectors the epilogue reads, loaded beside the partials
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = s0 + (int64_t)u * kPatchBlock < ns;
+      ds[u] = (DS && ok) ? dscale[gd[u]] : 1.0;
+      patch_epilogue_load<OUT>(ok, gd[u], cg, dotv, ev[u]);
     }
     // runs are short (the patches of one DOF): the first two partials of
     // every DOF are loaded together
@@ -469,10 +504,9 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_shared(int64_t ns, const 
     for (int u = 0; u < U; ++u) {
       const int64_t s = s0 + (int64_t)u * kPatchBlock;
       if (s >= ns) continue;
-      const int32_t g = sdof ? sdof[s] : (int32_t)(sbase + s);
       double v = acc[u];
-      if (DS) v *= dscale[g];
-      patch_epilogue<OUT>(g, v, c1, c2, cg, y, dotv, a0, a1, a2);
+      if (DS) v *= ds[u];
+      patch_epilogue_pre<OUT>(gd[u], v, c1, c2, cg, y, dotv != nullptr, ev[u], a0, a1, a2);
     }
   }
   patch_dots<OUT>(a0, a1, a2, pbase + blockIdx.x, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, sh);
