@@ -81,3 +81,19 @@ def test_bf16_single_copy_epilogue(case):
     assert np.array_equal(xs1.cpu().numpy().view(np.uint64), xs0.cpu().numpy().view(np.uint64))
     on.close()
     off.close()
+
+
+def test_local_gemm_microbenchmark_runs():
+    """The LDS-resident microbenchmark of the BF16 Gram products: runs for every
+    covered n_loc, reports the issued FLOPs of the launch, and its per-thread
+    checksums are finite and repeatable (the products are deterministic)."""
+    import torch
+    from paper_2607_12138_amd import _lib as L
+    for nl in (20, 36, 70, 84):
+        out = torch.empty(8 * 256, dtype=torch.float32, device="cuda")
+        fl = L.bras_bench_bf16_local_gemm(nl, 3, 8, out)
+        assert fl == 3 * 8 * L.bras_bench_bf16_local_gemm(nl, 1, 0)
+        a = out.cpu().numpy().copy()
+        L.bras_bench_bf16_local_gemm(nl, 3, 8, out)
+        b = out.cpu().numpy()
+        assert np.all(np.isfinite(a)) and np.array_equal(a, b)
