@@ -7,8 +7,10 @@
 //           (or after maxit products M p); z = C r; rho' = r.z;
 //           beta = rho'/rho; rho = rho'
 //
-// Each iteration is two fused operator passes (apply.hip) and one or two
-// one-block kernels:
+// Each iteration is two fused operator passes (apply.hip; for one column on
+// a handle with a patch plan, each pass is a patch pass and a boundary-DOF
+// pass, patch_kern.h, run on vectors permuted into the plan's internal DOF
+// numbering) and one or two one-block kernels:
 //   mass pass    element pass on z + beta p, reduce pass writes q and the new
 //                p and the p.q partials;
 //   alpha        alpha = rho / p.q, in a one-block kernel on large meshes or
