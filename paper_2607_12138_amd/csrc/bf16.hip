@@ -62,8 +62,7 @@ k_bras_bf16(int64_t E, int R, const int32_t* __restrict__ map, InArgs in, const 
   __shared__ double coef_s[256];
   __shared__ int act_s[256];
   __shared__ double red_s[kB16];
-  __shared__ int32_t gidx[KP];
-  __shared__ int dir_s[KP];   // row k of the current element has a single copy (DIRECT)
+  __shared__ int32_t gidx[KP];   // map of the current element (DIRECT: bit 31 = single copy)
 
   if (in.apart) {
     alpha_prologue(in.apart, in.anb, R, in.sc, in.ic, coef_s, act_s, red_s);
@@ -112,32 +111,43 @@ k_bras_bf16(int64_t E, int R, const int32_t* __restrict__ map, InArgs in, const 
   __bf16 greg[MPT];
   double xa[GPT], xb[X2 ? GPT : 1];
   int32_t gcur[GPT], gnxt[GPT];
+  // Loads below are issued unconditionally from clamped (valid) addresses and
+  // their values selected afterwards: without branches around them the
+  // compiler can count them, so waiting for one element's loads does not wait
+  // for the later map loads and stores.
   auto load_map = [&](int64_t Kx, int32_t* gm) {
+    const int64_t Kc = Kx < E ? Kx : E - 1;
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       const int k = (tid + u * kB16) >> 5;
-      gm[u] = (Kx < Kend && k < NL) ? map[Kx * NL + k] : 0;
+      const int32_t v = map[Kc * NL + (k < NL ? k : NL - 1)];
+      gm[u] = (Kx < Kend && k < NL) ? v : 0;
     }
   };
   auto load_elem = [&](int64_t Kx, const int32_t* gm) {
     const bool ok = Kx < Kend;
+    const int64_t Kc = Kx < E ? Kx : E - 1;
 #pragma unroll
     for (int u = 0; u < MPT; ++u) {
       const int q = tid + u * kB16;
       // non-temporal: the factors are read once per apply
-      greg[u] = (ok && q < NPK)
-                    ? __builtin_bit_cast(__bf16, __builtin_nontemporal_load(
-                                                     reinterpret_cast<const unsigned short*>(G) + Kx * NPK + q))
-                    : zero;
+      const unsigned short v = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(G) + Kc * NPK +
+                                                          (q < NPK ? q : NPK - 1));
+      greg[u] = (ok && q < NPK) ? __builtin_bit_cast(__bf16, v) : zero;
     }
     const bool cok = ok && r0 < rc0 && act_s[r0];
+    const int rcl = r0 < R ? r0 : R - 1;
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       const int k = (tid + u * kB16) >> 5;
       const bool v = cok && k < NL;
-      const int64_t gi = (int64_t)(gm[u] & 0x7fffffff) * R + r0;
-      xa[u] = v ? in.x[gi] : 0.0;
-      if (X2) xb[u] = v ? in.x2[gi] : 0.0;
+      const int64_t gi = (int64_t)(gm[u] & 0x7fffffff) * R + rcl;   // gm is 0 (a valid DOF) where unused
+      const double a = in.x[gi];
+      xa[u] = v ? a : 0.0;
+      if (X2) {
+        const double b = in.x2[gi];
+        xb[u] = v ? b : 0.0;
+      }
     }
   };
   // Z = Gtil^T bf16(Gtil W) for the 32 columns c0.. in sW
@@ -149,12 +159,19 @@ k_bras_bf16(int64_t E, int R, const int32_t* __restrict__ map, InArgs in, const 
       const f32x16 acc = gram_z<NL>(sG, sU, t, lane);
       const int col = lane & 31;
       if (col < rc && act_s[c0 + col]) {
+        // the 16 rows' map entries read together, then the stores
+        int32_t gr[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          gr[r] = (DIRECT && row < NL) ? gidx[row] : 0;
+        }
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int row = 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
           if (row >= NL) continue;
-          if (DIRECT && dir_s[row]) {
-            y[(int64_t)gidx[row] * R + c0 + col] = (double)acc[r];
+          if (DIRECT && gr[r] < 0) {
+            y[(int64_t)(gr[r] & 0x7fffffff) * R + c0 + col] = (double)acc[r];
           } else {
             zb[((int64_t)row * E + K) * R + c0 + col] = acc[r];
           }
@@ -178,8 +195,7 @@ k_bras_bf16(int64_t E, int R, const int32_t* __restrict__ map, InArgs in, const 
       if (k < NL) {
         sW[r0 * LD + k] = (__bf16)(float)(X2 ? fma(cf0, xb[u], xa[u]) : xa[u]);
         if (r0 == 0) {
-          gidx[k] = gcur[u] & 0x7fffffff;
-          if (DIRECT) dir_s[k] = (uint32_t)gcur[u] >> 31;
+          gidx[k] = gcur[u];
         }
       }
     }
@@ -196,7 +212,7 @@ k_bras_bf16(int64_t E, int R, const int32_t* __restrict__ map, InArgs in, const 
         const int k = q >> 5, r = q & 31;
         double v = 0.0;
         if (r < rc && act_s[c0 + r]) {
-          const int64_t gi = (int64_t)gidx[k] * R + c0 + r;
+          const int64_t gi = (int64_t)(gidx[k] & 0x7fffffff) * R + c0 + r;
           v = in.x[gi];
           if (X2) v = fma(coef_s[c0 + r], in.x2[gi], v);
         }
