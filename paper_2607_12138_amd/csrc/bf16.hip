@@ -112,42 +112,34 @@ k_bras_bf16(int64_t E, int R, const int32_t* __restrict__ map, InArgs in, const 
   double xa[GPT], xb[X2 ? GPT : 1];
   int32_t gcur[GPT], gnxt[GPT];
   // Loads below are issued unconditionally from clamped (valid) addresses and
-  // their values selected afterwards: without branches around them the
-  // compiler can count them, so waiting for one element's loads does not wait
-  // for the later map loads and stores.
+  // their raw values kept: entries past the element range, past n_loc or in
+  // columns that are inactive or past R are never staged, or only reach
+  // outputs that are not stored.  Without branches or selects after them the
+  // compiler can count the loads, so waiting for one element's loads does not
+  // wait for the later map loads and stores.
   auto load_map = [&](int64_t Kx, int32_t* gm) {
     const int64_t Kc = Kx < E ? Kx : E - 1;
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
       const int k = (tid + u * kB16) >> 5;
-      const int32_t v = map[Kc * NL + (k < NL ? k : NL - 1)];
-      gm[u] = (Kx < Kend && k < NL) ? v : 0;
+      gm[u] = map[Kc * NL + (k < NL ? k : NL - 1)];
     }
   };
   auto load_elem = [&](int64_t Kx, const int32_t* gm) {
-    const bool ok = Kx < Kend;
     const int64_t Kc = Kx < E ? Kx : E - 1;
 #pragma unroll
     for (int u = 0; u < MPT; ++u) {
       const int q = tid + u * kB16;
       // non-temporal: the factors are read once per apply
-      const unsigned short v = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(G) + Kc * NPK +
-                                                          (q < NPK ? q : NPK - 1));
-      greg[u] = (ok && q < NPK) ? __builtin_bit_cast(__bf16, v) : zero;
+      greg[u] = __builtin_bit_cast(__bf16, __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(G) +
+                                                                      Kc * NPK + (q < NPK ? q : NPK - 1)));
     }
-    const bool cok = ok && r0 < rc0 && act_s[r0];
     const int rcl = r0 < R ? r0 : R - 1;
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
-      const int k = (tid + u * kB16) >> 5;
-      const bool v = cok && k < NL;
-      const int64_t gi = (int64_t)(gm[u] & 0x7fffffff) * R + rcl;   // gm is 0 (a valid DOF) where unused
-      const double a = in.x[gi];
-      xa[u] = v ? a : 0.0;
-      if (X2) {
-        const double b = in.x2[gi];
-        xb[u] = v ? b : 0.0;
-      }
+      const int64_t gi = (int64_t)(gm[u] & 0x7fffffff) * R + rcl;
+      xa[u] = in.x[gi];
+      if (X2) xb[u] = in.x2[gi];
     }
   };
   // Z = Gtil^T bf16(Gtil W) for the 32 columns c0.. in sW
