@@ -54,17 +54,33 @@ def algorithmic_bytes(w, n, E, n_loc, R, prec):
 
 
 # sources of the operator passes and their data layout (the kernels the
-# stored counter measurements describe)
-APPLY_SOURCES = ("apply.hip", "elem_lane.h", "lane_*.hip", "elem_mfma.hip", "bf16.hip", "bf16_gram.h", "cg_common.h",
-                 "block_reduce.h", "internal.h", "setup.hip", "patch*.hip", "patch*.h", "patch_setup.cpp")
+# stored counter measurements describe): shared by every apply, then by form
+COMMON_SOURCES = ("apply.hip", "cg_common.h", "block_reduce.h", "internal.h", "setup.hip")
+FORM_SOURCES = {
+    "patch": ("patch*.hip", "patch*.h", "patch_setup.cpp", "elem_lane.h"),   # one column, vector families
+    "bf16": ("bf16.hip", "bf16_gram.h"),                                    # BF16 Gram-factor element pass
+    "element": ("elem_lane.h", "lane_*.hip", "elem_mfma.hip"),              # element pass + reduce
+}
 
 
-def source_digest():
-    """sha256 over the sources of the operator passes (to tell whether a
-    stored counter measurement still describes the kernels being run)."""
+def apply_form(w):
+    """Which kernels a workload's BRAS apply runs (see FORM_SOURCES)."""
+    if w.prec == "bf16":
+        return "bf16"
+    if w.nrhs == 1 and w.family not in ("P", "B"):
+        return "patch"
+    return "element"
+
+
+def source_digest(w=None):
+    """sha256 over the sources of the operator passes a workload's apply runs
+    (all of them without a workload), to tell whether a stored counter
+    measurement still describes the kernels being run."""
+    pats = COMMON_SOURCES + (FORM_SOURCES[apply_form(w)] if w is not None
+                             else tuple(p for v in FORM_SOURCES.values() for p in v))
     h = hashlib.sha256()
     files = set()
-    for pat in APPLY_SOURCES:
+    for pat in pats:
         files.update(glob.glob(os.path.join(ROOT, "paper_2607_12138_amd", "csrc", pat)))
     for f in sorted(files):
         with open(f, "rb") as fh:
@@ -81,7 +97,7 @@ def stored_traffic(workload):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_digest") != source_digest():
+    if rec.get("source_digest") != source_digest(workloads.BY_NAME[workload]):
         return None
     return rec.get("hbm_bytes_per_apply")
 
@@ -478,7 +494,7 @@ def main():
         us = time_apply(lambda u, v: L.mass_apply(prob.h, u, v), b, y, a.apply_reps)
         prob.close()
         print(json.dumps({"mode": "mass", "workload": w.name, "reps": a.apply_reps, "us_per_apply": round(us, 3),
-                          "source_digest": source_digest()}), flush=True)
+                          "source_digest": source_digest(w)}), flush=True)
         return
     if a.mode == "apply":
         y = prob.vec(w.nrhs)
@@ -486,7 +502,7 @@ def main():
         prob.close()
         print(json.dumps({"mode": "apply", "workload": w.name, "reps": a.apply_reps, "us_per_apply": round(us, 3),
                           "bytes_per_apply": int(algorithmic_bytes(w, prob.n, prob.E, prob.n_loc, w.nrhs, w.prec)),
-                          "source_digest": source_digest()}), flush=True)
+                          "source_digest": source_digest(w)}), flush=True)
         return
     if a.mode == "solve":
         for _ in range(a.warmup):
@@ -494,7 +510,7 @@ def main():
         ms, st, its, rel, _ = time_solves(prob, b, "bras", w.tol, a.steps)
         prob.close()
         print(json.dumps({"mode": "solve", "workload": w.name, "steps": a.steps, "ms_per_solve": round(ms, 4),
-                          "iterations": [int(v) for v in its], "source_digest": source_digest()}), flush=True)
+                          "iterations": [int(v) for v in its], "source_digest": source_digest(w)}), flush=True)
         return
     for _ in range(a.warmup):
         prob.solve(b, "bras", rtol=w.tol)
@@ -573,7 +589,7 @@ def main():
                                 if prob.info("patches") > 0 else "bras_apply (element pass + transpose-map reduce)"),
                      "bytes_per_launch": int(nbytes), "us_per_launch": round(bras_us, 3),
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
-        "source_digest": source_digest(),
+        "source_digest": source_digest(w),
         "setup_s": round(setup_s, 3),
         "element_pass_variant": int(variant),
         "stationary": stat,
