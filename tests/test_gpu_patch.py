@@ -6,7 +6,8 @@ bit-for-bit repeatable, and inside CG (where the vectors use the plan's
 internal DOF numbering) against the oracle's iteration counts.  Cases: every
 per-lane form (packed float32 / float64 inverses, 2D and 3D metric tables,
 explicit element matrices), the scaled H1 form on the matrix cores (patch form
-on request), and small patches (many shared DOFs, several ranks per patch)."""
+on request), small patches (many shared DOFs, several ranks per patch), one
+element per patch, and a single patch without shared DOFs (no boundary pass)."""
 import os
 import sys
 
@@ -30,6 +31,9 @@ CASES = [
     ("P", 3, 3, 4, 0.2, "f64", {"BRAS_PATCH_SCALED": "1"}),
     ("P", 3, 4, 3, 0.0, "f64", {"BRAS_PATCH_SCALED": "1", "BRAS_PATCH_ELEMS": "64"}),
     ("P", 2, 2, 9, 0.2, "f64", {"BRAS_PATCH_SCALED": "1", "BRAS_PATCH_ELEMS": "5"}),
+    ("N1curl", 3, 2, 2, 0.2, "f64", {}),                               # one patch, no shared DOFs
+    ("RT", 3, 2, 3, 0.2, "f32", {"BRAS_PATCH_ELEMS": "1"}),             # one element per patch
+    ("P", 3, 2, 2, 0.0, "f64", {"BRAS_PATCH_SCALED": "1"}),            # scaled form, one patch
 ]
 
 
@@ -77,6 +81,10 @@ def test_patch_operators(case):
     say("patch form %s" % (case,))
     orc, gpu = build(case)
     assert gpu.info("patches") > 0
+    if case[6].get("BRAS_PATCH_ELEMS") == "1":
+        assert gpu.info("patches") == gpu.E
+    if case[3] == 2:
+        assert gpu.info("patches") == 1
     tb = 1e-13 if case[5] == "f64" else 2e-4
     x = workloads.vector(orc.n, 41)
     xd = to_t(x)
