@@ -202,8 +202,9 @@ int jacobi_apply(bras_handle h, const double* x_d, double* y_d, int nrhs, void* 
  * pc: BRAS_PC_NONE / JACOBI / BRAS.  x_d holds the initial guess on entry and
  * the solution on exit.  Column c stops when ||r_k||_2 / ||r_0||_2 <= rtol
  * (r_k the recursive residual, r_0 = b - M x_0) or after maxit products M p.
- * When the stored inverses are FP32 / BF16, the iteration uses the flexible
- * beta.  At exit the true residual b - M x is recomputed; while it exceeds
+ * With BF16 inverses the iteration uses the flexible beta
+ * r_new.(z_new - z_old) / rho_old (FP32 inverses too when BRAS_OPT_FLEXIBLE
+ * is 1; the default for FP32 is the standard beta).  At exit the true residual b - M x is recomputed; while it exceeds
  * rtol ||r_0|| in a column, the iteration restarts from x (iterative
  * refinement, at most BRAS_OPT_MAX_RESTART times, default 8; the products
  * of every restart count in iters_h).
@@ -352,6 +353,10 @@ int bras_csr_add_fill(int64_t m, const int64_t* a_rowptr_d, const int32_t* a_col
                                    in patch form when the handle has patches
                                    (BRAS_INFO_PATCHES > 0); 0: element pass
                                    plus transpose-map reduce               */
+#define BRAS_OPT_FLEXIBLE    5  /* BRAS-PCG beta with reduced-precision
+                                   inverses: -1 (default) flexible for BF16,
+                                   standard for FP32; 0 standard; 1 flexible
+                                   for FP32 and BF16 (FP64: always standard) */
 int bras_set_option(bras_handle h, int opt, double value);
 
 /* ======================================================================== *

@@ -25,7 +25,7 @@ PC = {"none": PC_NONE, "jacobi": PC_JACOBI, "bras": PC_BRAS}
 INFO = {"n": 0, "E": 1, "nloc": 2, "nbr": 3, "prec": 4, "form": 5, "maxrhs": 6, "restarts": 7, "variant": 8,
         "solve_path": 9, "patches": 10, "patch_on": 11}
 EXPORT_MULT, EXPORT_ROWPTR, EXPORT_SLOT, EXPORT_DIAG = 0, 1, 2, 3
-OPT_GRAPH_ITERS, OPT_MAX_RESTART, OPT_VARIANT, OPT_SMALL_CG, OPT_PATCH = 0, 1, 2, 3, 4
+OPT_GRAPH_ITERS, OPT_MAX_RESTART, OPT_VARIANT, OPT_SMALL_CG, OPT_PATCH, OPT_FLEXIBLE = 0, 1, 2, 3, 4, 5
 NOALLOC_SCRATCH_BYTES = 32 << 20   # BRAS_NOALLOC_SCRATCH_BYTES
 FAMILY = {"P": H1, "N1curl": HCURL, "RT": HDIV, "B": H1_BERNSTEIN, "N2curl": HCURL2, "BDM": HDIV2}
 

@@ -76,6 +76,10 @@ extern "C" int bras_set_option(bras_handle h, int opt, double value) {
       c->use_patch = (int)value;
       cg_free(c);   // captured CG graphs and partial buffers follow the operator form
       break;
+    case BRAS_OPT_FLEXIBLE:
+      BRAS_CHECK(value == -1 || value == 0 || value == 1, "flexible-beta switch must be -1, 0 or 1");
+      c->flexible_opt = (int)value;
+      break;
     default: return fail(BRAS_EINVAL, "unknown option %d", opt);
   }
   return BRAS_OK;

@@ -52,6 +52,7 @@ struct Ctx {
   int small_cg = 1;          // solve eligible small problems in one work-group (pcg_small.hip)
   int use_patch = 1;         // one-column operator passes in patch form when the handle has a plan (patch.hip)
   int patch_xcd = 1;         // patch passes: each XCD takes a contiguous run of patches (BRAS_PATCH_XCD=0: round robin)
+  int flexible_opt = -1;     // BRAS-PCG beta: -1 flexible for BF16 inverses only, 0 never, 1 for FP32 / BF16
   int bf16_direct = 1;       // BF16 plain applies write single-copy DOFs from the element pass (BRAS_BF16_DIRECT=0: off)
   int bf16_grid = 0;         // BF16 element pass with that epilogue: persistent work-groups (0: other precisions)
   int bf16_grid_plain = 0;   // BF16 element pass without it (one input vector)

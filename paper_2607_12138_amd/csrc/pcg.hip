@@ -24,7 +24,7 @@
 // Iterations are captured into hipGraphs of 1, 2, 4, 8, 16 and 32
 // iterations; columns that have stopped are skipped by every kernel, and the
 // host reads the flags only between graph launches.  When the stored BRAS
-// inverses are FP32/BF16 the flexible beta = r_new.(z_new - z_old)/rho_old
+// inverses are BF16 (FP32 with BRAS_OPT_FLEXIBLE 1) the flexible beta = r_new.(z_new - z_old)/rho_old
 // is used and, at exit, CG restarts from x while the true residual is above
 // the tolerance.  The fixed-point and Chebyshev iterations at the end of this
 // file share the passes and the graph machinery.  Small single-column
@@ -460,7 +460,12 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   hipStream_t us = (hipStream_t)stream, s = c->s_int;
   const size_t vec = sizeof(double) * (size_t)c->n * nrhs;
   // graphs are captured on the idle internal stream before any work is queued
-  const int flexible = (pc == BRAS_PC_BRAS && c->prec != BRAS_FP64) ? 1 : 0;
+  // flexible beta: BF16 inverses (a perturbation at the 2^-9 level), or FP32
+  // on request; FP32 inverses are a fixed symmetric matrix applied with
+  // float32 rounding (2^-24), for which the standard beta keeps the counts
+  const int flexible = (pc != BRAS_PC_BRAS || c->prec == BRAS_FP64)
+                           ? 0
+                           : (c->flexible_opt >= 0 ? c->flexible_opt : (c->prec == BRAS_BF16 ? 1 : 0));
   // small single-column problems: the whole solve in one work-group, on the
   // caller's stream (no graphs, so no internal stream)
   if (small_cg_eligible(c, nrhs, maxit)) {

@@ -93,7 +93,7 @@ def test_binding_constants_match_header():
                                                "FP64", "FP32", "BF16", "PC_NONE", "PC_JACOBI", "PC_BRAS",
                                                "EXPORT_MULT", "EXPORT_ROWPTR", "EXPORT_SLOT", "EXPORT_DIAG",
                                                "OP_MASS", "OP_BRAS", "OP_JACOBI", "OPT_GRAPH_ITERS", "OPT_MAX_RESTART",
-                                               "OPT_VARIANT", "OPT_SMALL_CG", "OPT_PATCH")}
+                                               "OPT_VARIANT", "OPT_SMALL_CG", "OPT_PATCH", "OPT_FLEXIBLE")}
     py.update({k: getattr(L, k) for k in ("BRAS_OK", "BRAS_EINVAL", "BRAS_ENOTSPD", "BRAS_EHIP", "BRAS_ENOCONV",
                                           "BRAS_EBREAKDOWN", "BRAS_ENOMEM")})
     py.update({"BRAS_INFO_" + k.upper(): v for k, v in L.INFO.items()})

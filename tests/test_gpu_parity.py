@@ -364,3 +364,29 @@ def test_autotune_variants(case, nv):
     L.bras_set_option(gpu.h, L.OPT_VARIANT, -1)
     L.bras_set_option(gpu.h, L.OPT_PATCH, 1)
     assert gpu.info("variant") == -1
+
+
+@pytest.mark.parametrize("case", [CASES[6], CASES[10], CASES[11]], ids=ids)
+def test_fp32_standard_and_flexible_beta(case):
+    """FP32 inverses: BRAS-PCG with the standard beta (the default) and with
+    the flexible beta (BRAS_OPT_FLEXIBLE 1) both reach the tolerance on the
+    true residual, within a few iterations of each other and of the oracle's
+    float64 PCG."""
+    from paper_2607_12138_amd import _lib as L
+    orc, gpu = build(case)
+    tol = 1e-8
+    b = workloads.rhs(orc.n, 1, 45)
+    xo, ito, ok, _ = opcg.pcg(orc.M, b, orc.B.dot, tol=tol)
+    its_by = {}
+    for opt in (-1, 0, 1):
+        L.bras_set_option(gpu.h, L.OPT_FLEXIBLE, opt)
+        x, st, its, rel = gpu.solve(to_t(b), "bras", rtol=tol)
+        assert st == L.BRAS_OK, opt
+        x = x.cpu().numpy()
+        true_rel = np.linalg.norm(b - orc.M @ x) / np.linalg.norm(b)
+        assert true_rel <= 1.5 * tol, (opt, true_rel)
+        its_by[opt] = int(its[0])
+        assert abs(its_by[opt] - ito) <= 3, (opt, its_by[opt], ito)
+    L.bras_set_option(gpu.h, L.OPT_FLEXIBLE, -1)
+    assert its_by[-1] == its_by[0]                 # the default is the standard beta for FP32
+    say("fp32 pcg %s: standard %d, flexible %d, oracle %d" % (case, its_by[0], its_by[1], ito))
