@@ -411,6 +411,10 @@ static int launch_chunk(std::vector<hipGraphExec_t>& graphs, int chunk, hipStrea
   return BRAS_OK;
 }
 
+// Iterations launched after the start of a solve before the host first
+// looks at the flags (an iteration of a stopped column costs only launches).
+constexpr int kFirstChunk = 8;
+
 // Iterations to launch before the host looks at the flags again: enough to
 // reach the target at the slowest running column's observed rate (1..32).
 static int predict_chunk(CgState* g, int R, int maxit, int cap) {
@@ -494,8 +498,12 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   int restart_mode = 0;
   while (true) {
     if ((st = start(c, pc, rtol, restart_mode, s))) break;
+    // a first chunk without a host check (columns already within tolerance
+    // or at maxit skip its iterations), then the remaining iterations
+    // predicted from the observed rate
+    const int first = kFirstChunk < c->graph_iters ? kFirstChunk : c->graph_iters;
+    if ((st = launch_chunk(*graphs, first < maxit ? first : maxit, s))) break;
     if ((st = read_state(c, s))) break;
-    // iterate: predict the remaining iterations from the observed rate
     while (true) {
       const int chunk = predict_chunk(g, R, maxit, c->graph_iters);
       if (chunk == 0) break;
