@@ -719,7 +719,10 @@ static int stationary(Ctx* c, int pc, const std::vector<double>& ca, const std::
   CgArgs a = st_args(c);
   if ((st = st_mass_step(c, a, R, s)) == BRAS_OK) {
     k_st_init<<<1, kBS, 0, s>>>(reduce_blocks(c, R), R, g->part[0], g->sc, g->ic, rtol, g->stcoef, g->stcoef_cap);
-    st = read_state(c, s);
+    // as in pcg_solve: a first chunk before the first host check
+    const int first = kFirstChunk < c->graph_iters ? kFirstChunk : c->graph_iters;
+    st = launch_chunk(*graphs, first < maxit ? first : maxit, s);
+    if (st == BRAS_OK) st = read_state(c, s);
   }
   while (st == BRAS_OK) {
     const int chunk = predict_chunk(g, R, maxit, c->graph_iters);
