@@ -515,6 +515,8 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
     if ((st = launch_mass(c, g->x, g->q, R, s, nullptr, nullptr, nullptr))) break;
     k_residual<<<nb, kBS, 0, s>>>(c->n, R, g->b, g->q, g->z, g->part[1]);
     k_fin_true<<<1, kBS, 0, s>>>(nb, R, g->part[1], g->sc);
+    // x goes out with this check (one host wait); a restart writes it again
+    if ((st = num.out(g->x, x_d, vec, s))) break;
     if ((st = read_state(c, s))) break;
     bool again = false;
     for (int col = 0; col < R; ++col)
@@ -527,7 +529,6 @@ extern "C" int pcg_solve(bras_handle h, int pc, const double* b_d, double* x_d, 
   }
   c->last_restarts = restarts;
   if (st == BRAS_OK) {
-    st = num.out(g->x, x_d, vec, s);
     BRAS_HIP(hipEventRecord(ev, s));
     BRAS_HIP(hipStreamWaitEvent(us, ev, 0));
     BRAS_HIP(hipStreamSynchronize(s));
