@@ -159,11 +159,12 @@ __device__ __forceinline__ int32_t patch_dof(const int32_t* __restrict__ pdof, i
 
 // Phase 1 of a patch pass: wsh[j] = input value of patch DOF j, the loads of
 // U DOFs per thread issued together (out-of-range slots read DOF 0 of the
-// patch and store nothing).
+// patch and store nothing); gsh (if not null) keeps the DOF numbers for the
+// last phase.
 template <bool DS>
 __device__ __forceinline__ void patch_gather(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
                                              int32_t lbase, const InArgs& in, double c2,
-                                             const double* __restrict__ dscale, double* wsh) {
+                                             const double* __restrict__ dscale, double* wsh, int32_t* gsh) {
   constexpr int U = 4;
   for (int j0 = threadIdx.x; j0 < nd; j0 += U * kPatchBlock) {
     int32_t g[U];
@@ -184,7 +185,10 @@ __device__ __forceinline__ void patch_gather(const int32_t* __restrict__ pdof, i
       const int j = j0 + u * kPatchBlock;
       double t = in.x2 ? fma(c2, v2[u], v[u]) : v[u];
       if (DS) t *= ds[u];
-      if (j < nd) wsh[j] = t;
+      if (j < nd) {
+        wsh[j] = t;
+        if (gsh) gsh[j] = g[u];
+      }
     }
   }
 }
@@ -240,6 +244,7 @@ __device__ __forceinline__ void patch_count_scan(int* I, int nd, int* ps) {
   __syncthreads();
 }
 
+// gdof (if not null): the DOF numbers kept by the gather phase.
 // REUSE (CG epilogues without D^-1): win[j] holds the pass's gathered input
 // of patch DOF j, which is the epilogue's new p (mass: z + beta p) or new r
 // (BRAS: r - alpha q), computed in the same arithmetic; the epilogue takes it
@@ -247,7 +252,7 @@ __device__ __forceinline__ void patch_count_scan(int* I, int nd, int* ps) {
 // vectors (boundary DOFs write their partial sums).
 template <int OUT, bool DS, bool REUSE, typename VAL>
 __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
-                                             int32_t lbase, VAL val, const double* win,
+                                             int32_t lbase, const int32_t* gdof, VAL val, const double* win,
                                              const double* __restrict__ dscale, double ep1,
                                              double ep2, const CgArgs& cg, double* __restrict__ y,
                                              const double* __restrict__ dotv, double* __restrict__ spart,
@@ -260,7 +265,7 @@ __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, i
     for (int u = 0; u < U; ++u) {
       const int j = j0 + u * kPatchBlock;
       const bool in_range = j < nd;
-      g[u] = patch_dof(pdof, d0, in_range ? j : 0, nloc, lbase);
+      g[u] = gdof ? gdof[in_range ? j : 0] : patch_dof(pdof, d0, in_range ? j : 0, nloc, lbase);
       acc[u] = in_range ? val(j) : 0.0;
     }
     // vectors the epilogue reads, for the U DOFs at once (local DOFs only)
@@ -349,8 +354,10 @@ constexpr int kPatchWaves() {
 // FORM_PACKED: M_K (or the folded inverse) from ap; FORM_METRIC with NSYM > 1:
 // pair tables symtab [q][NSYM] and coefficients coefK [nsym][E]; FORM_METRIC
 // with NSYM = 1: the scaled H1 form, symtab = the shared reference matrix as
-// a packed lower triangle, coefK [E] the element's factor.  Dynamic LDS:
-// max(maxdofs, 3 * kPatchBlock) doubles.
+// a packed lower triangle, coefK [E] the element's factor.  Dynamic LDS (at
+// least 3 * kPatchBlock doubles): maxdofs doubles of inputs, then maxdofs
+// doubles of sums where the epilogue reuses the inputs, else maxdofs ints of
+// DOF numbers (the sums overwrite the inputs).
 template <int NL, int FORM, int NSYM, typename T, int OUT, bool DS, int VAR>
 __global__ void __launch_bounds__(kPatchBlock) __attribute__((amdgpu_waves_per_eu(kPatchWaves<NL, T>())))
 k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
@@ -382,7 +389,12 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   __syncthreads();   // the prologue's use of wsh is over
   // 1. patch DOF values
   const int32_t lbase = pa.ip ? d0 - pa.sbase[p] : -1;
-  patch_gather<DS>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh);
+  // the sums: after the inputs where the epilogue reuses them, else in their
+  // place; otherwise the DOF numbers follow them for the last phase
+  constexpr bool REUSE = !DS && (OUT == OUT_MASS_CG || OUT == OUT_BRAS_CG);
+  double* wsum = REUSE ? wsh + pa.wstride : wsh;
+  int32_t* gsh = REUSE ? nullptr : reinterpret_cast<int32_t*>(wsh + pa.wstride);
+  patch_gather<DS>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh, gsh);
   __syncthreads();
   // 2. one element per lane (idle lanes repeat element 0 and add nothing)
   const bool on = tid < ne;
@@ -406,9 +418,6 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
     z[l] = (T)0;
   }
   __syncthreads();   // every input read: the array now collects the sums
-  // the sums: after the inputs where the epilogue reuses them, else in their place
-  constexpr bool REUSE = !DS && (OUT == OUT_MASS_CG || OUT == OUT_BRAS_CG);
-  double* wsum = REUSE ? wsh + pa.wstride : wsh;
   for (int j = tid; j < nd; j += kPatchBlock) wsum[j] = 0.0;
   double g[NSYM > 0 ? NSYM : 1];
   if (FORM == FORM_METRIC) {
@@ -433,7 +442,7 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  patch_finish<OUT, DS, REUSE>(pa.pdof, d0, nd, nloc, lbase, LdsSums{wsum}, wsh, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
+  patch_finish<OUT, DS, REUSE>(pa.pdof, d0, nd, nloc, lbase, gsh, LdsSums{wsum}, wsh, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
                         a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
@@ -524,7 +533,8 @@ int patch_launch(Ctx* c, const PatchCall& pc, const T* ap, const double* symtab,
   PatchArgs pa{pt.pe, pt.pd, pt.pnl, ip ? pt.pidx : pt.pdof, pt.code, pt.sbase, c->E, pt.lbits, pt.maxrank,
                pt.npatch, xcd_per, ip ? 1 : 0, pt.maxdofs};
   if (ip && dscale) dscale = pt.invd_ip;
-  const int need = (REUSE ? 2 : 1) * pt.maxdofs;
+  // inputs and sums, or inputs (then sums) and the DOF numbers
+  const int need = REUSE ? 2 * pt.maxdofs : pt.maxdofs + (pt.maxdofs + 1) / 2;
   const int words = need > 3 * kPatchBlock ? need : 3 * kPatchBlock;
   const unsigned grid = xcd_per > 0 ? (unsigned)(8 * xcd_per) : (unsigned)pt.npatch;
   k_patch<NL, FORM, NSYM, T, OUT, DS, VAR><<<grid, kPatchBlock, sizeof(double) * words, s>>>(

@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_mfma(PatchArgs pa, InArgs
   __syncthreads();   // the prologue's use of wsh is over
   // 1. patch DOF values, and A (zero padded)
   const int32_t lbase = pa.ip ? d0 - pa.sbase[p] : -1;
-  patch_gather<DS>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh);
+  patch_gather<DS>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh, nullptr);
   for (int t = tid; t < MT * 16 * LDA; t += kPatchBlock) {
     const int i = t / LDA, k = t - i * LDA;
     sA[t] = (i < NL && k < NL) ? A[i * NL + k] : 0.0;
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(kPatchBlock) k_patch_mfma(PatchArgs pa, InArgs
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  patch_finish<OUT, DS, false>(pa.pdof, d0, nd, nloc, lbase, SegmentSums{I, zs}, nullptr, dscale, ep1, ep2, cg, y, dotv, spart,
+  patch_finish<OUT, DS, false>(pa.pdof, d0, nd, nloc, lbase, nullptr, SegmentSums{I, zs}, nullptr, dscale, ep1, ep2, cg, y, dotv, spart,
                         pa.sbase[p], a0, a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
