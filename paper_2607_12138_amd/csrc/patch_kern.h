@@ -418,7 +418,6 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
     z[l] = (T)0;
   }
   __syncthreads();   // every input read: the array now collects the sums
-  for (int j = tid; j < nd; j += kPatchBlock) wsum[j] = 0.0;
   double g[NSYM > 0 ? NSYM : 1];
   if (FORM == FORM_METRIC) {
 #pragma unroll
@@ -428,7 +427,16 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   lane_product<NL, FORM, NSYM, T, VAR>(wr, z, e0, e, pa.E, ap, symtab, g);
   __syncthreads();
   const int lb = pa.lbits;
-  for (int r = 0; r <= pa.maxrank; ++r) {
+  // every patch DOF has a copy of rank 0, which starts its sum (0 + z, as an add to a zeroed sum)
+  if (on) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const uint32_t cl = code(l);
+      if ((cl >> lb) == 0) wsum[cl & lmask] = 0.0 + (double)z[l];
+    }
+  }
+  __syncthreads();
+  for (int r = 1; r <= pa.maxrank; ++r) {
     if (on) {
 #pragma unroll
       for (int l = 0; l < NL; ++l) {
