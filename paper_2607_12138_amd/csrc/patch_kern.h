@@ -161,11 +161,10 @@ __device__ __forceinline__ int32_t patch_dof(const int32_t* __restrict__ pdof, i
 // U DOFs per thread issued together (out-of-range slots read DOF 0 of the
 // patch and store nothing); gsh (if not null) keeps the DOF numbers for the
 // last phase.
-template <bool DS>
+template <bool DS, int U = 4>
 __device__ __forceinline__ void patch_gather(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
                                              int32_t lbase, const InArgs& in, double c2,
                                              const double* __restrict__ dscale, double* wsh, int32_t* gsh) {
-  constexpr int U = 4;
   for (int j0 = threadIdx.x; j0 < nd; j0 += U * kPatchBlock) {
     int32_t g[U];
 #pragma unroll
@@ -250,14 +249,13 @@ __device__ __forceinline__ void patch_count_scan(int* I, int nd, int* ps) {
 // (BRAS: r - alpha q), computed in the same arithmetic; the epilogue takes it
 // instead of reading the two vectors again.  Only local DOFs read epilogue
 // vectors (boundary DOFs write their partial sums).
-template <int OUT, bool DS, bool REUSE, typename VAL>
+template <int OUT, bool DS, bool REUSE, typename VAL, int U = 4>
 __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, int32_t d0, int nd, int nloc,
                                              int32_t lbase, const int32_t* gdof, VAL val, const double* win,
                                              const double* __restrict__ dscale, double ep1,
                                              double ep2, const CgArgs& cg, double* __restrict__ y,
                                              const double* __restrict__ dotv, double* __restrict__ spart,
                                              int32_t sb, double& a0, double& a1, double& a2) {
-  constexpr int U = 4;
   for (int j0 = threadIdx.x; j0 < nd; j0 += U * kPatchBlock) {
     int32_t g[U];
     double acc[U];
@@ -394,7 +392,10 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   constexpr bool REUSE = !DS && (OUT == OUT_MASS_CG || OUT == OUT_BRAS_CG);
   double* wsum = REUSE ? wsh + pa.wstride : wsh;
   int32_t* gsh = REUSE ? nullptr : reinterpret_cast<int32_t*>(wsh + pa.wstride);
-  patch_gather<DS>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh, gsh);
+  // DOFs per thread whose loads go out together in the first and last phase
+  // (fewer where the CG epilogue's vectors take the registers)
+  constexpr int UD = REUSE ? 4 : 8;
+  patch_gather<DS, UD>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh, gsh);
   __syncthreads();
   // 2. one element per lane (idle lanes repeat element 0 and add nothing)
   const bool on = tid < ne;
@@ -450,7 +451,7 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const double ep1 = OUT == OUT_STAT ? cg.sc[S_ALPHA] : cf;
   const double ep2 = OUT == OUT_STAT ? cg.sc[S_BETA] : 0.0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  patch_finish<OUT, DS, REUSE>(pa.pdof, d0, nd, nloc, lbase, gsh, LdsSums{wsum}, wsh, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
+  patch_finish<OUT, DS, REUSE, LdsSums, UD>(pa.pdof, d0, nd, nloc, lbase, gsh, LdsSums{wsum}, wsh, dscale, ep1, ep2, cg, y, dotv, spart, pa.sbase[p], a0,
                         a1, a2);
   __syncthreads();   // wsh is free again
   patch_dots<OUT>(a0, a1, a2, p, OUT == OUT_PLAIN ? dotpart : cg.part0, cg, wsh);
