@@ -386,6 +386,11 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   const int32_t d0 = pa.pd[p], nd = pa.pd[p + 1] - d0, nloc = pa.pnl[p];
   __syncthreads();   // the prologue's use of wsh is over
   // 1. patch DOF values
+  // wavefront priority: raised in the latency-bound phases (gather, sums,
+  // last phase), normal while the element data stream in, so that a
+  // work-group between two barriers is not kept waiting for issue slots by the
+  // streaming wavefronts of the others on its SIMDs
+  __builtin_amdgcn_s_setprio(2);
   const int32_t lbase = pa.ip ? d0 - pa.sbase[p] : -1;
   // the sums: after the inputs where the epilogue reuses them, else in their
   // place; otherwise the DOF numbers follow them for the last phase
@@ -425,7 +430,9 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
     for (int q = 0; q < NSYM; ++q)
       g[q] = q < nsym ? __builtin_nontemporal_load(&coefK[(int64_t)q * pa.E + e0 + e]) : 0.0;
   }
+  __builtin_amdgcn_s_setprio(0);
   lane_product<NL, FORM, NSYM, T, VAR>(wr, z, e0, e, pa.E, ap, symtab, g);
+  __builtin_amdgcn_s_setprio(2);
   __syncthreads();
   const int lb = pa.lbits;
   // every patch DOF has a copy of rank 0, which starts its sum (0 + z, as an add to a zeroed sum)
