@@ -400,9 +400,9 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   // DOFs per thread whose loads go out together in the first and last phase
   // (fewer where the CG epilogue's vectors take the registers)
   constexpr int UD = REUSE ? 4 : 8;
-  patch_gather<DS, UD>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh, gsh);
-  __syncthreads();
-  // 2. one element per lane (idle lanes repeat element 0 and add nothing)
+  // the element data that do not depend on the gather (copy codes, metric
+  // coefficients) are requested before it, so that they arrive during it
+  // (idle lanes repeat element 0 and add nothing)
   const bool on = tid < ne;
   const int e = on ? tid : 0;
   const uint32_t lmask = (1u << pa.lbits) - 1u;
@@ -416,6 +416,15 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
     const uint32_t hi = 2 * h + 1 < NL ? (uint32_t)cdp[(int64_t)(2 * h + 1) * ne] : 0u;
     cd2[h] = lo | (hi << 16);
   }
+  double g[NSYM > 0 ? NSYM : 1];
+  if (FORM == FORM_METRIC) {
+#pragma unroll
+    for (int q = 0; q < NSYM; ++q)
+      g[q] = q < nsym ? __builtin_nontemporal_load(&coefK[(int64_t)q * pa.E + e0 + e]) : 0.0;
+  }
+  patch_gather<DS, UD>(pa.pdof, d0, nd, nloc, lbase, in, c2, dscale, wsh, gsh);
+  __syncthreads();
+  // 2. one element per lane
   auto code = [&](int l) -> uint32_t { return (cd2[l >> 1] >> (16 * (l & 1))) & 0xFFFFu; };
   T wr[NL], z[NL];
 #pragma unroll
@@ -424,12 +433,6 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
     z[l] = (T)0;
   }
   __syncthreads();   // every input read: the array now collects the sums
-  double g[NSYM > 0 ? NSYM : 1];
-  if (FORM == FORM_METRIC) {
-#pragma unroll
-    for (int q = 0; q < NSYM; ++q)
-      g[q] = q < nsym ? __builtin_nontemporal_load(&coefK[(int64_t)q * pa.E + e0 + e]) : 0.0;
-  }
   __builtin_amdgcn_s_setprio(0);
   lane_product<NL, FORM, NSYM, T, VAR>(wr, z, e0, e, pa.E, ap, symtab, g);
   __builtin_amdgcn_s_setprio(2);
