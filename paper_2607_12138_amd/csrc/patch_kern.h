@@ -343,10 +343,12 @@ __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, i
 }
 
 // Waves per SIMD the register allocator is asked for: 4 (at most 128 VGPRs)
-// where a lane's element fits without spilling, else its natural count.
+// where a lane's element fits without spilling (float64 data re-read their
+// copy codes after the product instead of keeping them through it), else its
+// natural count.
 template <int NL, typename T>
 constexpr int kPatchWaves() {
-  return sizeof(T) == 4 ? (NL <= 20 ? 4 : 1) : (NL <= 12 ? 4 : 1);
+  return sizeof(T) == 4 ? (NL <= 20 ? 4 : 1) : (NL <= 20 ? 4 : 1);
 }
 
 // FORM_PACKED: M_K (or the folded inverse) from ap; FORM_METRIC with NSYM > 1:
@@ -436,6 +438,17 @@ k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
   __builtin_amdgcn_s_setprio(0);
   lane_product<NL, FORM, NSYM, T, VAR>(wr, z, e0, e, pa.E, ap, symtab, g);
   __builtin_amdgcn_s_setprio(2);
+  // float64 element data: the codes again (an L2 or Infinity Cache read), so that they take no
+  // registers during the product
+  if (sizeof(T) == 8) {
+    const uint16_t* cdq = cdp + pin_v(0, z[0]);
+#pragma unroll
+    for (int h = 0; h < NC2; ++h) {
+      const uint32_t lo = cdq[(int64_t)(2 * h) * ne];
+      const uint32_t hi = 2 * h + 1 < NL ? (uint32_t)cdq[(int64_t)(2 * h + 1) * ne] : 0u;
+      cd2[h] = lo | (hi << 16);
+    }
+  }
   __syncthreads();
   const int lb = pa.lbits;
   // every patch DOF has a copy of rank 0, which starts its sum (0 + z, as an add to a zeroed sum)
