@@ -346,9 +346,9 @@ __device__ __forceinline__ void patch_finish(const int32_t* __restrict__ pdof, i
 // where a lane's element fits without spilling (float64 data re-read their
 // copy codes after the product instead of keeping them through it), else its
 // natural count.
-template <int NL, typename T>
+template <int NL, int FORM, typename T>
 constexpr int kPatchWaves() {
-  return sizeof(T) == 4 ? (NL <= 20 ? 4 : 1) : (NL <= 20 ? 4 : 1);
+  return sizeof(T) == 4 ? (NL <= 20 ? 4 : 1) : ((NL <= 12 || (FORM == FORM_METRIC && NL <= 20)) ? 4 : 1);
 }
 
 // FORM_PACKED: M_K (or the folded inverse) from ap; FORM_METRIC with NSYM > 1:
@@ -359,7 +359,7 @@ constexpr int kPatchWaves() {
 // doubles of sums where the epilogue reuses the inputs, else maxdofs ints of
 // DOF numbers (the sums overwrite the inputs).
 template <int NL, int FORM, int NSYM, typename T, int OUT, bool DS, int VAR>
-__global__ void __launch_bounds__(kPatchBlock) __attribute__((amdgpu_waves_per_eu(kPatchWaves<NL, T>())))
+__global__ void __launch_bounds__(kPatchBlock) __attribute__((amdgpu_waves_per_eu(kPatchWaves<NL, FORM, T>())))
 k_patch(PatchArgs pa, InArgs in, const T* __restrict__ ap,
                                                        const double* __restrict__ symtab,
                                                        const double* __restrict__ coefK, int nsym,
