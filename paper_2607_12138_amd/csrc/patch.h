@@ -71,7 +71,7 @@ constexpr int kPatchElems = 256;
 constexpr int kPatchMaxDofs = 3072;
 // Shared-DOF pass: each thread sums kPatchSharedPerThread shared DOFs
 // (independent loads in flight), so a work-group covers kPatchSharedPerBlock.
-constexpr int kPatchSharedPerThread = 4;
+constexpr int kPatchSharedPerThread = 2;
 constexpr int kPatchSharedPerBlock = kPatchBlock * kPatchSharedPerThread;
 constexpr int kPatchSharedBlocks = 1 << 20;
 
